@@ -1,0 +1,98 @@
+"""DialSort CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, the smoke check in ``__graft_entry__`` and the CPU-baseline leg
+of ``bench.py`` may import this package.  The product (the HIP library and its
+Python binding) never does, and shares no code with it.
+
+``dialsort_oracle.c`` states the method as the paper defines it: ingestion,
+Eq. (1) (Sec. 3.3), then the ordered projection, Eq. (2) (Sec. 3.3).  This
+module compiles that file with gcc (``build()``), loads it with ctypes and
+marshals numpy arrays.  ``crn.py`` holds the Conflict Resolution Network model of
+Sec. 6, used by tests only.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Tuple
+
+import numpy as np
+
+OK, EINVAL, ERANGE, EOVERFLOW = 0, 1, 2, 3
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "dialsort_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib: Optional[ctypes.CDLL] = None
+
+
+def build() -> str:
+    """Compile the C oracle into oracle/liboracle.so (plain gcc, -O2)."""
+    tmp = _LIB_PATH + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-fPIC", "-shared",
+                           _SRC, "-o", tmp])
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        u64, p = ctypes.c_uint64, ctypes.c_void_p
+        lib.oracle_histogram.argtypes = [p, u64, u64, p]
+        lib.oracle_histogram.restype = ctypes.c_int
+        lib.oracle_reconstruct.argtypes = [p, u64, p, u64, ctypes.POINTER(u64)]
+        lib.oracle_reconstruct.restype = ctypes.c_int
+        lib.oracle_sort.argtypes = [p, u64, u64, p, p]
+        lib.oracle_sort.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _as_u32(a) -> np.ndarray:
+    a = np.asarray(a)
+    if a.dtype == np.int32:
+        a = a.view(np.uint32)
+    if a.dtype != np.uint32:
+        a = a.astype(np.uint32)
+    return np.ascontiguousarray(a)
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p) if a.size else None
+
+
+def histogram(keys, U: int) -> Tuple[int, np.ndarray]:
+    """Eq. (1): returns (status, H) with H of length U (uint32)."""
+    k = _as_u32(keys)
+    H = np.zeros(U, dtype=np.uint32)
+    st = _load().oracle_histogram(_ptr(k), k.size, U, H.ctypes.data_as(ctypes.c_void_p))
+    return st, H
+
+
+def reconstruct(H, out_cap: Optional[int] = None) -> Tuple[int, np.ndarray]:
+    """Eq. (2): returns (status, out) where out holds min(sum H, out_cap) keys."""
+    h = _as_u32(H)
+    total = int(h.sum(dtype=np.uint64))
+    cap = total if out_cap is None else int(out_cap)
+    # the C routine never writes more than min(cap, total) elements
+    out = np.empty(min(cap, total), dtype=np.uint32)
+    written = ctypes.c_uint64(0)
+    st = _load().oracle_reconstruct(h.ctypes.data_as(ctypes.c_void_p), h.size,
+                                    _ptr(out), cap, ctypes.byref(written))
+    return st, out[: written.value]
+
+
+def sort(keys, U: int, in_place: bool = False) -> Tuple[int, np.ndarray, np.ndarray]:
+    """Eq. (1) then Eq. (2): returns (status, H, out).  With in_place=True the
+    projection is written over (a copy of) the key array, as in Sec. 9.2."""
+    k = _as_u32(keys).copy()
+    H = np.zeros(U, dtype=np.uint32)
+    out = k if in_place else np.empty_like(k)
+    st = _load().oracle_sort(_ptr(k), k.size, U, H.ctypes.data_as(ctypes.c_void_p), _ptr(out))
+    return st, H, out

@@ -1,0 +1,85 @@
+/*
+ * DialSort CPU ORACLE -- test infrastructure only.
+ *
+ * A plain, sequential, obviously-correct statement of what the DialSort hot
+ * path computes.  Only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark may load this library; the product path never does.  It shares
+ * no source, header or table with the HIP library.
+ *
+ * What it follows (DialSort, Sec. 3.3 "Mathematical Formulation, Correctness,
+ * and Ordered Projection"):
+ *   - H is initialised to zero, then every key x adds one to H[x]
+ *     (ingestion, Eq. (1) "eq:ingestion");
+ *   - the ordered projection sweeps k = 0, 1, ..., U-1 and emits k exactly H[k]
+ *     times (Eq. (2) "eq:projection");
+ *   - Theorem "thm:correct": the emitted sequence is nondecreasing, equals the
+ *     input as a multiset and has length n = sum_k H[k].
+ * The output is written in place when out == keys, as the paper's CPU
+ * implementation does (Sec. 9.2, Table "tab:struct_cost").
+ *
+ * Readings where the paper is silent (each one is listed in the design notes):
+ *   - a key x >= U is an error (Sec. 16: the method applies only to keys in
+ *     [0, U-1]); the return code is ERANGE and outputs are unspecified;
+ *   - counters are 32-bit unsigned (Sec. 7, Table "tab:wse3" gives 4 bytes per
+ *     histogram cell), so n must be <= 2^32 - 1 (EOVERFLOW otherwise);
+ *   - U must lie in [1, 2^32] (EINVAL otherwise);
+ *   - the stand-alone projection writes min(sum H, out_cap) elements and returns
+ *     EOVERFLOW when sum H > out_cap.
+ *
+ * Status numbers: 0 OK, 1 EINVAL, 2 ERANGE, 3 EOVERFLOW (the same numbering as
+ * the product's public header, restated here on purpose).
+ */
+#include <stdint.h>
+#include <stddef.h>
+
+#define ORACLE_OK 0
+#define ORACLE_EINVAL 1
+#define ORACLE_ERANGE 2
+#define ORACLE_EOVERFLOW 3
+
+/* Eq. (1): H := 0; for every key x: H[x] := H[x] + 1. */
+int oracle_histogram(const uint32_t *keys, uint64_t n, uint64_t U, uint32_t *H) {
+    uint64_t i, k;
+    if (U == 0 || U > ((uint64_t)1 << 32) || H == NULL) return ORACLE_EINVAL;
+    if (n > 0 && keys == NULL) return ORACLE_EINVAL;
+    if (n > (uint64_t)0xFFFFFFFFu) return ORACLE_EOVERFLOW;
+    for (k = 0; k < U; ++k) H[k] = 0;
+    for (i = 0; i < n; ++i) {
+        uint64_t x = keys[i];
+        if (x >= U) return ORACLE_ERANGE;
+        H[x] = H[x] + 1;
+    }
+    return ORACLE_OK;
+}
+
+/* Eq. (2): for k = 0 .. U-1, emit k exactly H[k] times.  Writes at most
+ * out_cap elements; *written receives the number written. */
+int oracle_reconstruct(const uint32_t *H, uint64_t U, uint32_t *out, uint64_t out_cap,
+                       uint64_t *written) {
+    uint64_t k, r, pos = 0, total = 0;
+    if (U == 0 || U > ((uint64_t)1 << 32) || H == NULL) return ORACLE_EINVAL;
+    if (out_cap > 0 && out == NULL) return ORACLE_EINVAL;
+    for (k = 0; k < U; ++k) {
+        total += H[k];
+        for (r = 0; r < H[k]; ++r) {
+            if (pos < out_cap) {
+                out[pos] = (uint32_t)k;
+                pos = pos + 1;
+            }
+        }
+    }
+    if (written) *written = pos;
+    return total > out_cap ? ORACLE_EOVERFLOW : ORACLE_OK;
+}
+
+/* Ingestion followed by the ordered projection into out (out may equal keys). */
+int oracle_sort(const uint32_t *keys, uint64_t n, uint64_t U, uint32_t *H, uint32_t *out) {
+    uint64_t written = 0;
+    int st = oracle_histogram(keys, n, U, H);
+    if (st != ORACLE_OK) return st;
+    if (n > 0 && out == NULL) return ORACLE_EINVAL;
+    st = oracle_reconstruct(H, U, out, n, &written);
+    if (st != ORACLE_OK) return st;
+    /* Theorem "thm:correct", item 3: the projection has exactly n elements. */
+    return written == n ? ORACLE_OK : ORACLE_EOVERFLOW;
+}

@@ -1,0 +1,225 @@
+"""Pins for the CPU oracle (no GPU).
+
+The oracle states Eq. (1) and Eq. (2) of DialSort Sec. 3.3.  These tests tie it
+to things other than itself:
+  * the paper's worked examples (tests/golden, each file cites its figure);
+  * brute force on every sequence over U <= 3 of length <= 7 (count by equality,
+    order by a comparison sort -- the textbook definition of a sorted multiset);
+  * numpy's bincount and sort on random inputs (library routines that reduce to
+    the same definition);
+  * Theorem "thm:correct": nondecreasing output, multiset equality, sum H = n;
+  * the error readings (key >= U, U out of range, out_cap below sum H).
+A last group plants plausible mistakes in copies of the oracle's two steps and
+checks that these pins reject every one of them.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def read_golden(name):
+    d = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            k, v = (s.strip() for s in line.split("=", 1))
+            d[k] = v
+    return d
+
+
+def ints(s):
+    return [int(x) for x in s.split()]
+
+
+# --- worked examples --------------------------------------------------------
+
+def test_fig_viz_ingestion_and_projection():
+    g = read_golden("fig_viz.txt")
+    st, H, out = oracle.sort(ints(g["keys"]), int(g["U"]))
+    assert st == oracle.OK
+    assert H.tolist() == ints(g["H"])
+    assert out.tolist() == ints(g["out"])
+
+
+def test_fig_viz_in_place():
+    g = read_golden("fig_viz.txt")
+    st, H, out = oracle.sort(ints(g["keys"]), int(g["U"]), in_place=True)
+    assert st == oracle.OK and out.tolist() == ints(g["out"])
+
+
+@pytest.mark.parametrize("name", ["fig_abacus.txt", "fig_physical.txt", "fig_viz.txt"])
+def test_projection_examples(name):
+    g = read_golden(name)
+    st, out = oracle.reconstruct(ints(g["H"]))
+    assert st == oracle.OK
+    assert out.tolist() == ints(g["out"])
+    # and ingestion of that output gives back H
+    st, H = oracle.histogram(out, int(g["U"]))
+    assert st == oracle.OK and H.tolist() == ints(g["H"])
+
+
+# --- exhaustive brute force -------------------------------------------------
+
+def brute_hist(seq, U):
+    return [sum(1 for x in seq if x == k) for k in range(U)]
+
+
+def test_exhaustive_small_universes():
+    cases = 0
+    for U in (1, 2, 3):
+        for length in range(0, 8):
+            for seq in itertools.product(range(U), repeat=length):
+                st, H, out = oracle.sort(list(seq), U)
+                assert st == oracle.OK
+                assert H.tolist() == brute_hist(seq, U)
+                assert out.tolist() == sorted(seq)
+                cases += 1
+    assert cases == sum(U ** L for U in (1, 2, 3) for L in range(8))
+
+
+# --- library routines and Theorem "thm:correct" ------------------------------
+
+@pytest.mark.parametrize("U", [1, 2, 6, 128, 255, 256, 366, 1000, 1024, 4097, 65536, 65537, 1 << 20])
+@pytest.mark.parametrize("n", [0, 1, 7, 1000, 100_003])
+def test_against_numpy(U, n):
+    rng = np.random.default_rng(U * 7919 + n)
+    keys = rng.integers(0, U, n, dtype=np.uint64).astype(np.uint32)
+    st, H, out = oracle.sort(keys, U)
+    assert st == oracle.OK
+    assert np.array_equal(H, np.bincount(keys, minlength=U).astype(np.uint32))
+    assert np.array_equal(out, np.sort(keys))
+    # Theorem "thm:correct": nondecreasing, multiset-equal, length n
+    assert int(H.sum(dtype=np.uint64)) == n and out.size == n
+    assert np.all(out[1:] >= out[:-1])
+    assert np.array_equal(np.bincount(out, minlength=U).astype(np.uint32), H)
+
+
+def test_paper_distributions():
+    import workloads
+
+    for name, gen in workloads.PAPER_DISTRIBUTIONS.items():
+        for U in (256, 1024, 65536):
+            keys = workloads.as_u32(gen(20_000, U, workloads.BASE_SEED))
+            st, H, out = oracle.sort(keys, U)
+            assert st == oracle.OK, name
+            assert np.array_equal(out, np.sort(keys)), name
+            assert np.array_equal(H, np.bincount(keys, minlength=U).astype(np.uint32)), name
+
+
+def test_keys_near_top_of_universe():
+    U = (1 << 31) + 5
+    # only the top of the universe is touched; H is allocated in full, so keep U modest
+    U = (1 << 26) + 3
+    keys = np.array([U - 1, 0, U - 1, U - 2, 5], dtype=np.uint32)
+    st, H, out = oracle.sort(keys, U)
+    assert st == oracle.OK
+    assert out.tolist() == sorted(keys.tolist())
+    assert H[U - 1] == 2 and H[U - 2] == 1 and H[0] == 1 and H[5] == 1
+
+
+# --- errors ---------------------------------------------------------------
+
+def test_key_out_of_range():
+    st, H = oracle.histogram([0, 1, 6], 6)
+    assert st == oracle.ERANGE
+    st, H, out = oracle.sort([7], 7)
+    assert st == oracle.ERANGE
+
+
+def test_bad_universe():
+    lib = oracle._load()
+    H = np.zeros(4, dtype=np.uint32)
+    assert lib.oracle_histogram(None, 0, 0, H.ctypes.data_as(ctypes.c_void_p)) == oracle.EINVAL
+    assert lib.oracle_histogram(None, 0, (1 << 32) + 1, H.ctypes.data_as(ctypes.c_void_p)) == oracle.EINVAL
+
+
+def test_count_overflow_guard():
+    lib = oracle._load()
+    H = np.zeros(4, dtype=np.uint32)
+    k = np.zeros(1, dtype=np.uint32)
+    # rejected before any key is read
+    assert lib.oracle_histogram(k.ctypes.data_as(ctypes.c_void_p), 1 << 32, 4,
+                                H.ctypes.data_as(ctypes.c_void_p)) == oracle.EOVERFLOW
+
+
+def test_reconstruct_capacity():
+    st, out = oracle.reconstruct([1, 2, 0, 3, 1, 2], 4)
+    assert st == oracle.EOVERFLOW and out.tolist() == [0, 1, 1, 3]
+    st, out = oracle.reconstruct([1, 2, 0, 3, 1, 2], 100)
+    assert st == oracle.OK and out.tolist() == [0, 1, 1, 3, 3, 3, 4, 5, 5]
+    st, out = oracle.reconstruct([0, 0, 0], 0)
+    assert st == oracle.OK and out.size == 0
+
+
+# --- planted mistakes: every one must be rejected by the pins above ----------
+
+def pins_accept(hist_fn, proj_fn) -> bool:
+    """True if a (histogram, projection) pair passes the worked examples, the
+    exhaustive check and a numpy comparison."""
+    for name in ("fig_viz.txt",):
+        g = read_golden(name)
+        H = hist_fn(ints(g["keys"]), int(g["U"]))
+        if list(H) != ints(g["H"]) or list(proj_fn(H)) != ints(g["out"]):
+            return False
+    for name in ("fig_abacus.txt", "fig_physical.txt"):
+        g = read_golden(name)
+        if list(proj_fn(ints(g["H"]))) != ints(g["out"]):
+            return False
+    for U in (1, 2, 3):
+        for length in range(0, 6):
+            for seq in itertools.product(range(U), repeat=length):
+                H = hist_fn(list(seq), U)
+                if list(H) != brute_hist(seq, U) or list(proj_fn(H)) != sorted(seq):
+                    return False
+    rng = np.random.default_rng(5)
+    keys = rng.integers(0, 300, 5000)
+    H = hist_fn(keys.tolist(), 300)
+    return list(H) == np.bincount(keys, minlength=300).tolist() and list(proj_fn(H)) == sorted(keys.tolist())
+
+
+def good_hist(keys, U):
+    H = [0] * U
+    for x in keys:
+        H[x] += 1
+    return H
+
+
+def good_proj(H):
+    out = []
+    for k, c in enumerate(H):
+        out.extend([k] * c)
+    return out
+
+
+def test_pins_accept_the_plain_definition():
+    assert pins_accept(good_hist, good_proj)
+
+
+MUTANTS = {
+    "drops the last key": (lambda keys, U: good_hist(keys[:-1], U), good_proj),
+    "counts key x into x-1": (lambda keys, U: good_hist([max(x - 1, 0) for x in keys], U), good_proj),
+    "descending projection": (good_hist, lambda H: good_proj(H)[::-1]),
+    "emits each present key once": (good_hist, lambda H: [k for k, c in enumerate(H) if c]),
+    "skips bin 0": (good_hist, lambda H: good_proj([0] + list(H[1:]))),
+    "off-by-one emission count": (good_hist, lambda H: good_proj([c + 1 if c else 0 for c in H])),
+    "stops one bin early": (good_hist, lambda H: good_proj(list(H[:-1]))),
+    "emits k+1": (good_hist, lambda H: [x + 1 for x in good_proj(H)]),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_reject_planted_mistakes(name):
+    h, p = MUTANTS[name]
+    assert not pins_accept(h, p), name
