@@ -80,8 +80,9 @@ def reconstruct(H, out_cap: Optional[int] = None) -> Tuple[int, np.ndarray]:
     h = _as_u32(H)
     total = int(h.sum(dtype=np.uint64))
     cap = total if out_cap is None else int(out_cap)
-    # the C routine never writes more than min(cap, total) elements
-    out = np.empty(min(cap, total), dtype=np.uint32)
+    # the C routine never writes more than min(cap, total) elements; keep the
+    # buffer non-empty so that a nonzero cap never comes with a null pointer
+    out = np.empty(max(min(cap, total), 1), dtype=np.uint32)
     written = ctypes.c_uint64(0)
     st = _load().oracle_reconstruct(h.ctypes.data_as(ctypes.c_void_p), h.size,
                                     _ptr(out), cap, ctypes.byref(written))

@@ -161,6 +161,8 @@ def test_reconstruct_capacity():
     assert st == oracle.OK and out.tolist() == [0, 1, 1, 3, 3, 3, 4, 5, 5]
     st, out = oracle.reconstruct([0, 0, 0], 0)
     assert st == oracle.OK and out.size == 0
+    st, out = oracle.reconstruct([0, 0, 0], 5)  # nothing to emit, room to spare
+    assert st == oracle.OK and out.size == 0
 
 
 # --- planted mistakes: every one must be rejected by the pins above ----------
