@@ -1,0 +1,150 @@
+"""Python binding of libdialsort.so, the MI355X (gfx950) DialSort hot path.
+
+The functions carry the names of the C ABI in include/dialsort.h and only
+marshal arguments: torch tensors provide device memory and
+``torch.cuda.current_stream()`` the stream; every step of the method runs in the
+HIP kernels of the library.  There is no fallback: if the library is missing
+the import of this binding fails.
+
+Keys, H and outputs are 1-D ``torch.int32`` (or ``torch.uint32``) CUDA tensors
+whose bits are uint32 values.  Each function returns the C status code
+(``DIALSORT_OK`` == 0); ``check()`` turns a nonzero code into an exception.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+import torch
+
+DIALSORT_OK, DIALSORT_EINVAL, DIALSORT_ERANGE, DIALSORT_EOVERFLOW, DIALSORT_EWORKSPACE, DIALSORT_EHIP = range(6)
+DIALSORT_MODE_HISTOGRAM, DIALSORT_MODE_SORT, DIALSORT_MODE_RECONSTRUCT = 0, 1, 2
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdialsort.so")
+
+
+class DialSortError(RuntimeError):
+    def __init__(self, status: int):
+        super().__init__(f"dialsort status {status}: {dialsort_strerror(status)}")
+        self.status = status
+
+
+class dialsort_desc(ctypes.Structure):
+    _fields_ = [("keys", ctypes.c_void_p), ("n", ctypes.c_uint64), ("U", ctypes.c_uint64),
+                ("H", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2605_16667_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    u64, p, sz, st = ctypes.c_uint64, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
+    sig = {
+        "dialsort_workspace_bytes": (sz, [u64, u64, ctypes.c_int]),
+        "dialsort_histogram": (st, [p, u64, u64, p, p, sz, p]),
+        "dialsort_reconstruct": (st, [p, u64, p, u64, p, sz, p]),
+        "dialsort_sort": (st, [p, u64, u64, p, p, p, sz, p]),
+        "dialsort_batched_workspace_bytes": (sz, [ctypes.POINTER(dialsort_desc), ctypes.c_uint32]),
+        "dialsort_sort_batched": (st, [ctypes.POINTER(dialsort_desc), ctypes.c_uint32, p, sz, p]),
+        "dialsort_status_sync": (st, [p, p]),
+        "dialsort_result_total": (st, [p, p, ctypes.POINTER(u64)]),
+        "dialsort_strerror": (ctypes.c_char_p, [st]),
+        "dialsort_last_hip_error": (ctypes.c_int, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype, f.argtypes = res, args
+    return lib
+
+
+_lib = _load()
+EXPORTED = ("dialsort_workspace_bytes", "dialsort_histogram", "dialsort_reconstruct", "dialsort_sort",
+            "dialsort_batched_workspace_bytes", "dialsort_sort_batched", "dialsort_status_sync",
+            "dialsort_result_total", "dialsort_strerror", "dialsort_last_hip_error")
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if t.numel() and not t.is_cuda:
+        raise ValueError("dialsort tensors must live on the GPU")
+    if t.numel() and not t.is_contiguous():
+        raise ValueError("dialsort tensors must be contiguous")
+    return t.data_ptr() if t.numel() else None
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream or None
+    return getattr(stream, "cuda_stream", stream) or None
+
+
+def check(status: int) -> None:
+    if status != DIALSORT_OK:
+        raise DialSortError(status)
+
+
+def dialsort_strerror(status: int) -> str:
+    return _lib.dialsort_strerror(status).decode()
+
+
+def dialsort_last_hip_error() -> int:
+    return _lib.dialsort_last_hip_error()
+
+
+def dialsort_workspace_bytes(n: int, U: int, mode: int) -> int:
+    return _lib.dialsort_workspace_bytes(n, U, mode)
+
+
+def workspace(nbytes: int, device="cuda") -> torch.Tensor:
+    """A device byte tensor usable as a workspace of at least nbytes."""
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def dialsort_histogram(keys: torch.Tensor, U: int, H: torch.Tensor, ws: torch.Tensor, stream=None) -> int:
+    return _lib.dialsort_histogram(_ptr(keys), keys.numel(), U, _ptr(H), _ptr(ws), ws.numel(), _stream(stream))
+
+
+def dialsort_sort(keys: torch.Tensor, U: int, H: torch.Tensor, out: torch.Tensor, ws: torch.Tensor,
+                  stream=None) -> int:
+    if out.numel() < keys.numel():
+        return DIALSORT_EINVAL
+    return _lib.dialsort_sort(_ptr(keys), keys.numel(), U, _ptr(H), _ptr(out), _ptr(ws), ws.numel(),
+                              _stream(stream))
+
+
+def dialsort_reconstruct(H: torch.Tensor, out: torch.Tensor, ws: torch.Tensor, out_cap: Optional[int] = None,
+                         stream=None) -> int:
+    cap = out.numel() if out_cap is None else int(out_cap)
+    if cap > out.numel():
+        return DIALSORT_EINVAL
+    return _lib.dialsort_reconstruct(_ptr(H), H.numel(), _ptr(out), cap, _ptr(ws), ws.numel(), _stream(stream))
+
+
+def make_descs(arrays: Sequence[Tuple[torch.Tensor, int, torch.Tensor, torch.Tensor]]):
+    """(keys, U, H, out) tuples -> a ctypes array of dialsort_desc."""
+    descs = (dialsort_desc * max(len(arrays), 1))()
+    for i, (k, U, H, o) in enumerate(arrays):
+        descs[i] = dialsort_desc(_ptr(k), k.numel(), U, _ptr(H), _ptr(o))
+    return descs
+
+
+def dialsort_batched_workspace_bytes(descs, count: int) -> int:
+    return _lib.dialsort_batched_workspace_bytes(descs, count)
+
+
+def dialsort_sort_batched(descs, count: int, ws: torch.Tensor, stream=None) -> int:
+    return _lib.dialsort_sort_batched(descs, count, _ptr(ws), ws.numel(), _stream(stream))
+
+
+def dialsort_status_sync(ws: torch.Tensor, stream=None) -> int:
+    return _lib.dialsort_status_sync(_ptr(ws), _stream(stream))
+
+
+def dialsort_result_total(ws: torch.Tensor, stream=None) -> Tuple[int, int]:
+    total = ctypes.c_uint64(0)
+    st = _lib.dialsort_result_total(_ptr(ws), _stream(stream), ctypes.byref(total))
+    return st, total.value

@@ -1,0 +1,410 @@
+// libdialsort: host side of the DialSort gfx950 hot path -- argument checks,
+// plan selection, workspace layout and kernel launches behind the C ABI of
+// include/dialsort.h.
+//
+// Launch sequences (every sequence starts with k_init, which clears the control
+// block and the look-back tile flags, and zeroes H only where H is accumulated
+// with atomics):
+//   LDS32 / LDS16 (U <= 65536):  k_hist_lds -> [k_scan: sum rows into H]
+//   PART (65536 < U <= 2^28):     k_partition -> k_bucket
+//   GLOBAL (tiny n, or U > 2^28): k_hist_global
+//   sort adds                      k_scan (look-back + chunk map) -> k_fill
+//   reconstruct                    k_init -> k_scan -> k_fill
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "../../include/dialsort.h"
+#include "common.hpp"
+#include "hist_lds.hpp"
+#include "partition.hpp"
+#include "scan_fill.hpp"
+
+using namespace ds;
+
+namespace {
+
+thread_local int g_last_hip_error = 0;
+
+constexpr int FILL_NT = 256;
+constexpr int FILL_CL2 = 13;  // chunk of 8192 positions
+constexpr int SCAN_NT = 256;
+constexpr uint64_t U_MAX = 1ull << 32;
+constexpr uint64_t N_MAX = 0xFFFFFFFFull;
+constexpr size_t ALIGN = 256;
+
+enum Kind { K_EMPTY, K_LDS32S, K_LDS32, K_LDS16, K_PART, K_GLOBAL, K_NONE };
+
+struct Layout {
+  Kind kind = K_NONE;
+  uint32_t G = 1;        // LDS paths: workgroups (= partial rows)
+  uint64_t per = 0;      // LDS paths: keys per workgroup (multiple of 4)
+  uint32_t B = 0, T = 0, bstride = 0;  // PART
+  bool rows_in_ws = false;
+  uint64_t row_stride = 0;
+  bool scan = false;     // full projection
+  int scan_vpt = 16;
+  uint64_t scan_tiles = 0;
+  uint64_t limit = 0;
+  uint64_t item_cap = 0;
+  size_t off_tile = 0, off_items = 0, off_rows = 0, off_stage = 0, off_seg = 0, bytes = 0;
+};
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+inline uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+// Choose the number of LDS workgroups: enough to stream the keys at full
+// bandwidth, few enough that the partial rows stay small next to the keys.
+uint32_t choose_G(uint64_t n, uint64_t U, uint32_t gmax, uint64_t max_per) {
+  const double BWR = 6.0e12, BWW = 5.0e12, RWG = 25.0e9;
+  uint32_t g_lo = (uint32_t)std::max<uint64_t>(1, cdiv(n, max_per));
+  uint32_t best = g_lo;
+  double best_t = 1e30;
+  for (uint32_t g = 1; g <= gmax; g *= 2) {
+    uint32_t gg = std::max(g, g_lo);
+    const double t = 4.0 * n / std::min(BWR, gg * RWG) + gg * U * 4.0 / BWW + gg * U * 4.0 / BWR +
+                     (gg > 1 ? (gg / 8.0) * 1.0e-6 * (U < 16384 ? 1.0 : 0.1) : 0.0);
+    if (t < best_t) { best_t = t; best = gg; }
+  }
+  return std::min(best, std::max(g_lo, gmax));
+}
+
+Layout plan(uint64_t n, uint64_t U, int mode) {
+  Layout L;
+  const bool recon = mode == DIALSORT_MODE_RECONSTRUCT;
+  L.scan = mode != DIALSORT_MODE_HISTOGRAM;
+  L.limit = n;  // sort: n positions; reconstruct: out_cap
+  size_t off = ALIGN;  // control block first
+  if (recon) {
+    L.kind = K_NONE;
+  } else if (n == 0) {
+    L.kind = K_EMPTY;
+  } else if (U > (uint64_t)PART_W * PART_BMAX || (U > 65536 && n < (uint64_t)PART_TK)) {
+    L.kind = K_GLOBAL;
+  } else if (U <= 4096) {
+    L.kind = K_LDS32S;
+    L.G = choose_G(n, U, 512, 1ull << 40);
+  } else if (U <= 32768) {
+    L.kind = K_LDS32;
+    L.G = choose_G(n, U, 256, 1ull << 40);
+  } else if (U <= 65536) {
+    L.kind = K_LDS16;
+    L.G = choose_G(n, U, 256, 1ull << 22);
+  } else {
+    L.kind = K_PART;
+    L.B = (uint32_t)cdiv(U, PART_W);
+    L.T = (uint32_t)cdiv(n, PART_TK);
+    L.bstride = (uint32_t)align_up(L.B + 1, 8);
+  }
+  if (L.kind == K_LDS32S || L.kind == K_LDS32 || L.kind == K_LDS16) {
+    L.per = align_up(cdiv(n, L.G), 4);
+    L.G = (uint32_t)cdiv(n, L.per);
+    L.rows_in_ws = L.G > 1;
+    L.row_stride = align_up(U + 1, 64);
+  }
+  // scan tiles (also used to sum partial rows in histogram mode)
+  L.scan_vpt = (L.rows_in_ws && L.G >= 8) ? 1 : 16;
+  L.scan_tiles = cdiv(U, (uint64_t)SCAN_NT * L.scan_vpt);
+  if (L.scan) {
+    L.off_tile = off; off = align_up(off + L.scan_tiles * 8, ALIGN);
+    // at most one item per tile plus one per chunk start
+    L.item_cap = L.scan_tiles + cdiv(L.limit, 1ull << FILL_CL2) + 2;
+    L.off_items = off; off = align_up(off + L.item_cap * sizeof(FillItem), ALIGN);
+  }
+  if (L.rows_in_ws) {
+    L.off_rows = off; off = align_up(off + (size_t)L.G * L.row_stride * 4, ALIGN);
+  }
+  if (L.kind == K_PART) {
+    L.off_stage = off; off = align_up(off + (align_up(n, 8) + 16) * 2, ALIGN);
+    L.off_seg = off; off = align_up(off + (size_t)L.T * L.bstride * 2, ALIGN);
+  }
+  L.bytes = off + ALIGN;  // slack for aligning the caller's pointer
+  return L;
+}
+
+inline bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+inline bool aligned4(const void* p) { return ((uintptr_t)p & 3) == 0; }
+
+inline bool overlap(const void* a, size_t abytes, const void* b, size_t bbytes) {
+  if (!abytes || !bbytes) return false;
+  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  return x < y + bbytes && y < x + abytes;
+}
+
+inline char* ws_base(void* ws) { return (char*)align_up((uintptr_t)ws, ALIGN); }
+
+#define DS_LAUNCH(...)                                  \
+  do {                                                  \
+    hipLaunchKernelGGL(__VA_ARGS__);                    \
+    hipError_t e_ = hipGetLastError();                  \
+    if (e_ != hipSuccess) {                             \
+      g_last_hip_error = (int)e_;                       \
+      return DIALSORT_EHIP;                             \
+    }                                                   \
+  } while (0)
+
+// k_init: clear the control block, the look-back flags, and optionally H.
+__global__ void k_init(Ctl* ctl, uint64_t* tiles, uint64_t ntiles, uint32_t* H, uint64_t nH) {
+  const uint64_t tid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  uint32_t* c = reinterpret_cast<uint32_t*>(ctl);
+  if (tid < sizeof(Ctl) / 4) c[tid] = 0;
+  for (uint64_t i = tid; i < ntiles; i += stride) tiles[i] = 0;
+  for (uint64_t i = tid; i < nH; i += stride) H[i] = 0;
+}
+
+dialsort_status launch_init(char* base, const Layout& L, uint32_t* H, uint64_t nH, hipStream_t s) {
+  const uint64_t work = std::max<uint64_t>(std::max<uint64_t>(64, L.scan ? L.scan_tiles : 0), nH);
+  const uint32_t grid = (uint32_t)std::min<uint64_t>(cdiv(work, 256), 2048);
+  DS_LAUNCH(k_init, dim3(grid), dim3(256), 0, s, (Ctl*)base, (uint64_t*)(base + L.off_tile),
+            L.scan ? L.scan_tiles : 0, H, nH);
+  return DIALSORT_OK;
+}
+
+// Ingestion: H (or partial rows) from keys.
+dialsort_status launch_ingest(const uint32_t* keys, uint64_t n, uint64_t U, uint32_t* H, char* base,
+                              const Layout& L, hipStream_t s) {
+  Ctl* ctl = (Ctl*)base;
+  const uint32_t umax = (uint32_t)(U - 1);
+  const bool ka = aligned16(keys);
+  uint32_t* rows = L.rows_in_ws ? (uint32_t*)(base + L.off_rows) : H;
+  switch (L.kind) {
+    case K_LDS32S:
+      if (ka) DS_LAUNCH((k_hist_lds<1024, 4096, false, 1, true, 2>), dim3(L.G), dim3(1024), 0, s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
+      else DS_LAUNCH((k_hist_lds<1024, 4096, false, 1, false, 2>), dim3(L.G), dim3(1024), 0, s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
+      break;
+    case K_LDS32:
+      if (ka) DS_LAUNCH((k_hist_lds<1024, 32768, false, 1, true, 2>), dim3(L.G), dim3(1024), 0, s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
+      else DS_LAUNCH((k_hist_lds<1024, 32768, false, 1, false, 2>), dim3(L.G), dim3(1024), 0, s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
+      break;
+    case K_LDS16:
+      if (ka) DS_LAUNCH((k_hist_lds<1024, 32768, true, 1, true, 2>), dim3(L.G), dim3(1024), 0, s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
+      else DS_LAUNCH((k_hist_lds<1024, 32768, true, 1, false, 2>), dim3(L.G), dim3(1024), 0, s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
+      break;
+    case K_PART: {
+      uint16_t* stg = (uint16_t*)(base + L.off_stage);
+      uint16_t* seg = (uint16_t*)(base + L.off_seg);
+      if (ka) DS_LAUNCH((k_partition<0, true>), dim3(L.T), dim3(PART_NT), 0, s, keys, n, umax, L.B, stg, seg, L.bstride, ctl);
+      else DS_LAUNCH((k_partition<0, false>), dim3(L.T), dim3(PART_NT), 0, s, keys, n, umax, L.B, stg, seg, L.bstride, ctl);
+      if (aligned16(H)) DS_LAUNCH((k_bucket<1, true>), dim3(L.B), dim3(PART_NT), 0, s, stg, seg, L.bstride, L.T, L.B, U, H);
+      else DS_LAUNCH((k_bucket<1, false>), dim3(L.B), dim3(PART_NT), 0, s, stg, seg, L.bstride, L.T, L.B, U, H);
+      break;
+    }
+    case K_GLOBAL: {
+      const uint32_t grid = (uint32_t)std::min<uint64_t>(cdiv(n, 256 * 4), 4096);
+      if (ka) DS_LAUNCH((k_hist_global<256, 1, true>), dim3(grid), dim3(256), 0, s, keys, n, umax, H, ctl);
+      else DS_LAUNCH((k_hist_global<256, 1, false>), dim3(grid), dim3(256), 0, s, keys, n, umax, H, ctl);
+      break;
+    }
+    default:
+      break;
+  }
+  return DIALSORT_OK;
+}
+
+// k_scan over `rows` (nrows rows), writing H when H_out is set.
+dialsort_status launch_scan(const uint32_t* rows, uint32_t nrows, uint64_t row_stride, uint32_t* H_out,
+                            uint64_t U, char* base, const Layout& L, bool full, int report_overflow,
+                            hipStream_t s) {
+  Ctl* ctl = (Ctl*)base;
+  uint64_t* tiles = (uint64_t*)(base + L.off_tile);
+  FillItem* items = (FillItem*)(base + L.off_items);
+  const uint32_t icap = (uint32_t)std::min<uint64_t>(L.item_cap, 0xFFFFFFF0ull);
+  const dim3 grid((uint32_t)L.scan_tiles);
+  if (full) {
+    if (L.scan_vpt == 1)
+      DS_LAUNCH((k_scan<SCAN_NT, 1, true>), grid, dim3(SCAN_NT), 0, s, rows, nrows, row_stride, H_out, U, ctl, tiles, items, icap, L.limit, FILL_CL2, report_overflow);
+    else
+      DS_LAUNCH((k_scan<SCAN_NT, 16, true>), grid, dim3(SCAN_NT), 0, s, rows, nrows, row_stride, H_out, U, ctl, tiles, items, icap, L.limit, FILL_CL2, report_overflow);
+  } else {
+    if (L.scan_vpt == 1)
+      DS_LAUNCH((k_scan<SCAN_NT, 1, false>), grid, dim3(SCAN_NT), 0, s, rows, nrows, row_stride, H_out, U, ctl, tiles, items, icap, L.limit, FILL_CL2, report_overflow);
+    else
+      DS_LAUNCH((k_scan<SCAN_NT, 16, false>), grid, dim3(SCAN_NT), 0, s, rows, nrows, row_stride, H_out, U, ctl, tiles, items, icap, L.limit, FILL_CL2, report_overflow);
+  }
+  return DIALSORT_OK;
+}
+
+dialsort_status launch_fill(const uint32_t* H, uint32_t* out, char* base, const Layout& L, hipStream_t s) {
+  Ctl* ctl = (Ctl*)base;
+  const FillItem* items = (const FillItem*)(base + L.off_items);
+  if (L.limit == 0) return DIALSORT_OK;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>(L.item_cap, 256 * 8);
+  const uint32_t icap = (uint32_t)std::min<uint64_t>(L.item_cap, 0xFFFFFFF0ull);
+  if (aligned16(out))
+    DS_LAUNCH((k_fill<FILL_NT, FILL_CL2, true>), dim3(grid), dim3(FILL_NT), 0, s, H, out, ctl, items, icap);
+  else
+    DS_LAUNCH((k_fill<FILL_NT, FILL_CL2, false>), dim3(grid), dim3(FILL_NT), 0, s, H, out, ctl, items, icap);
+  return DIALSORT_OK;
+}
+
+#define DS_TRY(x)                          \
+  do {                                     \
+    dialsort_status st_ = (x);             \
+    if (st_ != DIALSORT_OK) return st_;    \
+  } while (0)
+
+dialsort_status check_common(uint64_t U, const void* ws, size_t ws_bytes, size_t need) {
+  if (U == 0 || U > U_MAX) return DIALSORT_EINVAL;
+  if (!ws || ws_bytes < need) return DIALSORT_EWORKSPACE;
+  return DIALSORT_OK;
+}
+
+// histogram or sort, after argument checks
+dialsort_status run_sort(const uint32_t* keys, uint64_t n, uint64_t U, uint32_t* H, uint32_t* out, void* ws,
+                         int mode, hipStream_t s) {
+  const Layout L = plan(n, U, mode);
+  char* base = ws_base(ws);
+  const bool zeroH = L.kind == K_EMPTY || L.kind == K_GLOBAL;
+  DS_TRY(launch_init(base, L, H, zeroH ? U : 0, s));
+  DS_TRY(launch_ingest(keys, n, U, H, base, L, s));
+  const uint32_t* rows = L.rows_in_ws ? (const uint32_t*)(base + L.off_rows) : H;
+  const uint32_t nrows = L.rows_in_ws ? L.G : 1;
+  if (mode == DIALSORT_MODE_HISTOGRAM) {
+    if (L.rows_in_ws) DS_TRY(launch_scan(rows, nrows, L.row_stride, H, U, base, L, false, 0, s));
+    return DIALSORT_OK;
+  }
+  DS_TRY(launch_scan(rows, nrows, L.rows_in_ws ? L.row_stride : 0, L.rows_in_ws ? H : nullptr, U, base, L,
+                     true, 0, s));
+  DS_TRY(launch_fill(H, out, base, L, s));
+  return DIALSORT_OK;
+}
+
+__global__ void k_or_status(Ctl* dst, const Ctl* src) {
+  if (threadIdx.x == 0 && src->status) atomicOr(&dst->status, src->status);
+}
+
+dialsort_status check_desc(const dialsort_desc& d) {
+  if (d.U == 0 || d.U > U_MAX || !d.H || (d.n && (!d.keys || !d.out))) return DIALSORT_EINVAL;
+  if (!aligned4(d.keys) || !aligned4(d.H) || !aligned4(d.out)) return DIALSORT_EINVAL;
+  if (d.n > N_MAX) return DIALSORT_EOVERFLOW;
+  if (overlap(d.keys, d.n * 4, d.H, d.U * 4) || overlap(d.out, d.n * 4, d.H, d.U * 4)) return DIALSORT_EINVAL;
+  if (d.out != d.keys && overlap(d.keys, d.n * 4, d.out, d.n * 4)) return DIALSORT_EINVAL;
+  return DIALSORT_OK;
+}
+
+// Batched form, stream-ordered: every array runs its own launch sequence in a
+// shared sub-workspace, and its device status is folded into the batch status.
+size_t batch_workspace_bytes(const dialsort_desc* d, uint32_t count) {
+  size_t mx = 0;
+  for (uint32_t i = 0; i < count; ++i) {
+    if (d[i].U == 0 || d[i].U > U_MAX) return 0;
+    mx = std::max(mx, plan(d[i].n, d[i].U, DIALSORT_MODE_SORT).bytes);
+  }
+  return 2 * ALIGN + mx;
+}
+
+dialsort_status batch_run(const dialsort_desc* d, uint32_t count, void* ws, size_t ws_bytes, hipStream_t s) {
+  if (count && !d) return DIALSORT_EINVAL;
+  for (uint32_t i = 0; i < count; ++i) DS_TRY(check_desc(d[i]));
+  if (!ws || ws_bytes < batch_workspace_bytes(d, count)) return DIALSORT_EWORKSPACE;
+  char* base = ws_base(ws);
+  Layout L0;
+  L0.scan = false;
+  DS_TRY(launch_init(base, L0, nullptr, 0, s));
+  char* sub = base + ALIGN;
+  for (uint32_t i = 0; i < count; ++i) {
+    DS_TRY(run_sort(d[i].keys, d[i].n, d[i].U, d[i].H, d[i].out, sub, DIALSORT_MODE_SORT, s));
+    DS_LAUNCH(k_or_status, dim3(1), dim3(64), 0, s, (Ctl*)base, (const Ctl*)sub);
+  }
+  return DIALSORT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t dialsort_workspace_bytes(uint64_t n, uint64_t U, int mode) {
+  if (U == 0 || U > U_MAX) return 0;
+  return plan(n, U, mode).bytes;
+}
+
+dialsort_status dialsort_histogram(const uint32_t* keys, uint64_t n, uint64_t U, uint32_t* H, void* ws,
+                                   size_t ws_bytes, hipStream_t stream) {
+  if (U == 0 || U > U_MAX || !H || (n && !keys)) return DIALSORT_EINVAL;
+  if (!aligned4(keys) || !aligned4(H)) return DIALSORT_EINVAL;
+  if (n > N_MAX) return DIALSORT_EOVERFLOW;
+  if (overlap(keys, n * 4, H, U * 4)) return DIALSORT_EINVAL;
+  DS_TRY(check_common(U, ws, ws_bytes, dialsort_workspace_bytes(n, U, DIALSORT_MODE_HISTOGRAM)));
+  return run_sort(keys, n, U, H, nullptr, ws, DIALSORT_MODE_HISTOGRAM, stream);
+}
+
+dialsort_status dialsort_sort(const uint32_t* keys, uint64_t n, uint64_t U, uint32_t* H, uint32_t* out, void* ws,
+                              size_t ws_bytes, hipStream_t stream) {
+  if (U == 0 || U > U_MAX || !H || (n && (!keys || !out))) return DIALSORT_EINVAL;
+  if (!aligned4(keys) || !aligned4(H) || !aligned4(out)) return DIALSORT_EINVAL;
+  if (n > N_MAX) return DIALSORT_EOVERFLOW;
+  if (overlap(keys, n * 4, H, U * 4) || overlap(out, n * 4, H, U * 4)) return DIALSORT_EINVAL;
+  if (out != keys && overlap(keys, n * 4, out, n * 4)) return DIALSORT_EINVAL;
+  DS_TRY(check_common(U, ws, ws_bytes, dialsort_workspace_bytes(n, U, DIALSORT_MODE_SORT)));
+  return run_sort(keys, n, U, H, out, ws, DIALSORT_MODE_SORT, stream);
+}
+
+dialsort_status dialsort_reconstruct(const uint32_t* H, uint64_t U, uint32_t* out, uint64_t out_cap, void* ws,
+                                     size_t ws_bytes, hipStream_t stream) {
+  if (U == 0 || U > U_MAX || !H || (out_cap && !out)) return DIALSORT_EINVAL;
+  if (!aligned4(H) || !aligned4(out)) return DIALSORT_EINVAL;
+  if (out_cap > LB_VAL - 1) return DIALSORT_EINVAL;
+  if (out_cap && overlap(out, out_cap * 4, H, U * 4)) return DIALSORT_EINVAL;
+  DS_TRY(check_common(U, ws, ws_bytes, dialsort_workspace_bytes(out_cap, U, DIALSORT_MODE_RECONSTRUCT)));
+  const Layout L = plan(out_cap, U, DIALSORT_MODE_RECONSTRUCT);
+  char* base = ws_base(ws);
+  DS_TRY(launch_init(base, L, nullptr, 0, stream));
+  DS_TRY(launch_scan(H, 1, 0, nullptr, U, base, L, true, 1, stream));
+  DS_TRY(launch_fill(H, out, base, L, stream));
+  return DIALSORT_OK;
+}
+
+size_t dialsort_batched_workspace_bytes(const dialsort_desc* descs, uint32_t count) {
+  return batch_workspace_bytes(descs, count);
+}
+
+dialsort_status dialsort_sort_batched(const dialsort_desc* descs, uint32_t count, void* ws, size_t ws_bytes,
+                                      hipStream_t stream) {
+  return batch_run(descs, count, ws, ws_bytes, stream);
+}
+
+dialsort_status dialsort_status_sync(const void* ws, hipStream_t stream) {
+  if (!ws) return DIALSORT_EINVAL;
+  uint32_t st = 0;
+  const char* base = ws_base(const_cast<void*>(ws));
+  hipError_t e = hipMemcpyAsync(&st, base + offsetof(Ctl, status), 4, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    g_last_hip_error = (int)e;
+    return DIALSORT_EHIP;
+  }
+  if (st & ST_RANGE) return DIALSORT_ERANGE;
+  if (st & ST_OVERFLOW) return DIALSORT_EOVERFLOW;
+  if (st) return DIALSORT_EHIP;
+  return DIALSORT_OK;
+}
+
+dialsort_status dialsort_result_total(const void* ws, hipStream_t stream, uint64_t* total) {
+  if (!ws || !total) return DIALSORT_EINVAL;
+  const char* base = ws_base(const_cast<void*>(ws));
+  hipError_t e = hipMemcpyAsync(total, base + offsetof(Ctl, total), 8, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    g_last_hip_error = (int)e;
+    return DIALSORT_EHIP;
+  }
+  return DIALSORT_OK;
+}
+
+const char* dialsort_strerror(dialsort_status status) {
+  switch (status) {
+    case DIALSORT_OK: return "ok";
+    case DIALSORT_EINVAL: return "invalid argument";
+    case DIALSORT_ERANGE: return "key outside [0, U)";
+    case DIALSORT_EOVERFLOW: return "count overflow (n > 2^32-1 or sum(H) > out_cap)";
+    case DIALSORT_EWORKSPACE: return "workspace missing or too small";
+    case DIALSORT_EHIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+int dialsort_last_hip_error(void) { return g_last_hip_error; }
+
+}  // extern "C"

@@ -1,0 +1,186 @@
+// Ingestion into LDS-privatized sub-histograms (DialSort Sec. 3.3, Eq. (1)),
+// for universes that fit in one workgroup's LDS.
+//
+// Workgroup g counts the keys of slab [g*per, min((g+1)*per, n)) into an LDS
+// histogram of the whole universe and writes it out as row g of a partial
+// histogram matrix (or directly as H when there is a single workgroup).  The
+// rows are summed by the scan kernel; no global atomics and no zeroing of H are
+// needed, and the result does not depend on the order in which workgroups run.
+//
+//   * LDS32: U <= 32768, one uint32 counter per bin (up to 128 KiB of LDS).
+//   * LDS16: 32768 < U <= 65536: two 16-bit counters packed per 32-bit word
+//     (128 KiB).  A field that wraps is corrected exactly: every atomic add
+//     returns the old word, from which the adding lane sees whether its field
+//     crossed a multiple of 65536 (and, for the low field, whether the carry into
+//     the high field made that field cross one).  Each crossing is logged as a
+//     +-65536 event for its bin; a low-field carry is taken back out of the high
+//     field with a second atomic.  The field's final value plus 65536 times its
+//     net events is its exact count.  With at most 2^22 keys per workgroup a
+//     workgroup logs at most 256 events (the log holds 512).
+#pragma once
+
+#include "common.hpp"
+#include "crn_wave.hpp"
+
+namespace ds {
+
+// Load up to 4 keys of group [e0, e0+4) clipped at `end`; returns how many are
+// valid (a prefix of v).
+template <bool ALIGNED>
+__device__ __forceinline__ uint32_t load_group(const uint32_t* __restrict__ keys, uint64_t e0, uint64_t end,
+                                               uint32_t v[4]) {
+  if (e0 + 4 <= end) {
+    if constexpr (ALIGNED) {
+      const uint4 q = *reinterpret_cast<const uint4*>(keys + e0);
+      v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    } else {
+      v[0] = keys[e0]; v[1] = keys[e0 + 1]; v[2] = keys[e0 + 2]; v[3] = keys[e0 + 3];
+    }
+    return 4;
+  }
+  uint32_t c = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    v[i] = 0;
+    if (e0 + i < end) { v[i] = keys[e0 + i]; c = i + 1; }
+  }
+  return c;
+}
+
+constexpr int LDS16_EVCAP = 512;
+
+struct Lds32Emit {
+  uint32_t* s;
+  __device__ __forceinline__ void operator()(uint32_t k, uint32_t c) { atomicAdd(&s[k], c); }
+};
+
+struct Lds16Emit {
+  uint32_t* words;   // packed counters: bin 2i in bits 0..15, bin 2i+1 in bits 16..31
+  uint32_t* evflag;  // one bit per bin: the bin has logged events
+  uint32_t* ev;      // event log: bin | (0x80000000 if the event is -65536)
+  uint32_t* nev;
+  __device__ __forceinline__ void log(uint32_t bin, bool neg) {
+    const uint32_t i = atomicAdd(nev, 1u);
+    if (i < LDS16_EVCAP) ev[i] = bin | (neg ? 0x80000000u : 0u);
+    atomicOr(&evflag[bin >> 5], 1u << (bin & 31));
+  }
+  __device__ __forceinline__ void operator()(uint32_t k, uint32_t c) {
+    const uint32_t w = k >> 1;
+    if ((k & 1u) == 0) {
+      const uint32_t old = atomicAdd(&words[w], c);
+      if ((old & 0xFFFFu) + c >= 0x10000u) {  // low field crossed a multiple of 65536
+        log(k, false);
+        if ((old >> 16) == 0xFFFFu) log(k + 1, false);  // its carry wrapped the high field
+        const uint32_t old2 = atomicAdd(&words[w], 0xFFFF0000u);  // take the carry back out
+        if ((old2 >> 16) == 0u) log(k + 1, true);
+      }
+    } else {
+      const uint32_t old = atomicAdd(&words[w], c << 16);
+      if ((old >> 16) + c >= 0x10000u) log(k, false);
+    }
+  }
+};
+
+// NT threads; CAP = LDS words; PACKED selects the 16-bit layout.
+// rows: G rows of `row_stride` uint32 each (row g at rows + g*row_stride).
+template <int NT, int CAP, bool PACKED, int AGG, bool ALIGNED, int UNR>
+__global__ __launch_bounds__(NT) void k_hist_lds(const uint32_t* __restrict__ keys, uint64_t n, uint64_t per,
+                                                 uint32_t umax, uint32_t U, uint32_t* __restrict__ rows,
+                                                 uint64_t row_stride, Ctl* ctl) {
+  __shared__ uint32_t s[CAP];
+  __shared__ uint32_t evflag[PACKED ? 65536 / 32 : 1];
+  __shared__ uint32_t ev[PACKED ? LDS16_EVCAP : 1];
+  __shared__ uint32_t nev;
+  const uint32_t nwords = PACKED ? (U + 1) / 2 : U;
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t i = tid; i < nwords; i += NT) s[i] = 0;
+  if constexpr (PACKED) {
+    for (uint32_t i = tid; i < 65536 / 32; i += NT) evflag[i] = 0;
+    if (tid == 0) nev = 0;
+  }
+  __syncthreads();
+
+  const uint64_t beg = (uint64_t)blockIdx.x * per;
+  const uint64_t end = beg + per < n ? beg + per : n;
+  bool bad = false;
+  WaveAgg st;
+  using Emit = typename std::conditional<PACKED, Lds16Emit, Lds32Emit>::type;
+  Emit emit;
+  if constexpr (PACKED) {
+    emit.words = s; emit.evflag = evflag; emit.ev = ev; emit.nev = &nev;
+  } else {
+    emit.s = s;
+  }
+  // uniform trip count across the workgroup: every lane takes part in the ballots
+  for (uint64_t g0 = beg; g0 < end; g0 += (uint64_t)NT * 4 * UNR) {
+    uint32_t v[UNR][4];
+    uint32_t c[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) c[u] = load_group<ALIGNED>(keys, g0 + ((uint64_t)u * NT + tid) * 4, end, v[u]);
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const bool valid = (uint32_t)i < c[u];
+        const bool ok = valid && v[u][i] <= umax;
+        bad |= valid && !ok;
+        wave_merge<AGG>(v[u][i], ok, st, emit);
+      }
+    }
+  }
+  if (__syncthreads_or(bad) && tid == 0) set_status(ctl, ST_RANGE);
+
+  uint32_t* row = rows + (uint64_t)blockIdx.x * row_stride;
+  if constexpr (!PACKED) {
+    for (uint32_t i = tid; i < U; i += NT) row[i] = s[i];
+  } else {
+    const uint32_t ne = nev < LDS16_EVCAP ? nev : LDS16_EVCAP;
+    if (tid == 0 && nev > LDS16_EVCAP) set_status(ctl, ST_INTERNAL);  // cannot happen within the key bound
+    for (uint32_t w = tid; w < nwords; w += NT) {
+      const uint32_t word = s[w];
+      uint64_t cnt[2] = {word & 0xFFFFu, word >> 16};
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const uint32_t bin = 2 * w + h;
+        if (evflag[bin >> 5] & (1u << (bin & 31))) {
+          for (uint32_t e = 0; e < ne; ++e) {
+            const uint32_t x = ev[e];
+            if ((x & 0x7FFFFFFFu) == bin) cnt[h] += (x & 0x80000000u) ? (uint64_t)-65536ll : 65536ull;
+          }
+        }
+      }
+      row[2 * w] = (uint32_t)cnt[0];
+      if (2 * w + 1 < U) row[2 * w + 1] = (uint32_t)cnt[1];
+    }
+  }
+}
+
+// Direct global atomics into a zeroed H, after the same wave merge.  Used when
+// n is small next to U, or U is too large for the partitioned path.
+struct GlobalEmit {
+  uint32_t* H;
+  __device__ __forceinline__ void operator()(uint32_t k, uint32_t c) { atomicAdd(&H[k], c); }
+};
+
+template <int NT, int AGG, bool ALIGNED>
+__global__ __launch_bounds__(NT) void k_hist_global(const uint32_t* __restrict__ keys, uint64_t n, uint32_t umax,
+                                                    uint32_t* __restrict__ H, Ctl* ctl) {
+  bool bad = false;
+  WaveAgg st;
+  GlobalEmit emit{H};
+  const uint64_t stride = (uint64_t)gridDim.x * NT * 4;
+  for (uint64_t g0 = (uint64_t)blockIdx.x * NT * 4; g0 < n; g0 += stride) {
+    uint32_t v[4];
+    const uint32_t c = load_group<ALIGNED>(keys, g0 + (uint64_t)threadIdx.x * 4, n, v);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const bool valid = (uint32_t)i < c;
+      const bool ok = valid && v[i] <= umax;
+      bad |= valid && !ok;
+      wave_merge<AGG>(v[i], ok, st, emit);
+    }
+  }
+  if (__syncthreads_or(bad) && threadIdx.x == 0) set_status(ctl, ST_RANGE);
+}
+
+}  // namespace ds

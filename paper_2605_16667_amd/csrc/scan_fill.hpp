@@ -1,0 +1,324 @@
+// Ordered projection (DialSort Sec. 3.3, Eq. (2)): emit k exactly H[k] times for
+// k = 0 .. U-1.
+//
+// The paper's sequential projection keeps one output cursor.  In parallel every
+// bin needs its starting position, the exclusive prefix of H; the paper does not
+// say how its 8-thread version splits the scan, so the split here is ours:
+//
+// k_scan: one pass over H with a single-pass decoupled look-back (tile t
+//   publishes its aggregate, then adds its predecessors' aggregates until it
+//   meets an inclusive prefix; tiles are numbered by a ticket taken at start, so
+//   every tile waits only on tiles that are already running).  The same pass can
+//   first sum the partial-histogram rows written by the LDS ingestion kernels
+//   and store the result as H.  Each tile then cuts its output span at the
+//   multiples of C and appends one fill item per piece: (first position, end,
+//   first bin, that bin's run start, end bin).  An item therefore covers at most
+//   C positions and at most one tile of bins, whatever the skew (a hot key of
+//   10^8 copies becomes 10^8 / C items) and however sparse H is.
+//
+// k_fill: persistent workgroups take items.  An item walks its bins, marks the
+//   position where each run begins, and fills its positions by carrying every
+//   marked key forward to the next mark; interior stores are 16-byte coalesced
+//   stores.  Zero bins emit nothing (the presence test of Sec. 2, Table
+//   "tab:comparison", is not an order comparison).
+#pragma once
+
+#include "common.hpp"
+
+namespace ds {
+
+constexpr uint64_t LB_FLAG_A = 1ull << 62;  // aggregate available
+constexpr uint64_t LB_FLAG_P = 2ull << 62;  // inclusive prefix available
+constexpr uint64_t LB_VAL = (1ull << 62) - 1;
+
+// One piece of the projection: output positions [p0, p1) (p1 - p0 <= C, and
+// [p0 & ~3, p1) fits in C), whose first position is covered by bin k with run
+// start o <= p0; the bins to walk are k .. klast (the end of k's scan tile).
+struct FillItem {
+  uint64_t p0, p1, o;
+  uint32_t k, klast;
+};
+static_assert(sizeof(FillItem) == 32, "fill items are 32 bytes");
+
+__device__ __forceinline__ uint64_t wave_sum_sat(uint64_t x) {
+#pragma unroll
+  for (int d = WAVE / 2; d >= 1; d >>= 1) x = sat_add(x, __shfl_xor(x, d, WAVE));
+  return x;
+}
+
+// Decoupled look-back for tile t (called by wave 0 of the block).  Returns the
+// exclusive prefix of tile t in lane 0's view (all lanes get it).
+__device__ __forceinline__ uint64_t lookback(uint64_t* state, uint64_t t) {
+  const int lane = lane_id();
+  uint64_t prefix = 0;
+  int64_t j = (int64_t)t - 1;
+  for (;;) {
+    const int64_t idx = j - lane;
+    uint64_t s;
+    for (;;) {
+      s = idx >= 0 ? ld_acquire_u64(&state[idx]) : LB_FLAG_P;
+      if (!__any((s >> 62) == 0)) break;
+      __builtin_amdgcn_s_sleep(1);
+    }
+    const uint64_t pm = __ballot((s >> 62) == 2);
+    if (pm) {
+      const int p = __ffsll((unsigned long long)pm) - 1;
+      prefix = sat_add(prefix, wave_sum_sat(lane <= p ? (s & LB_VAL) : 0));
+      return prefix;
+    }
+    prefix = sat_add(prefix, wave_sum_sat(s & LB_VAL));
+    j -= WAVE;
+  }
+}
+
+// NT threads, VPT bins per thread (tile = NT*VPT bins).
+// rows: nrows partial rows (row r at rows + r*row_stride); H_out receives their
+// sum when non-null.  FULL: also scan and build the chunk map (chunk = 2^CL2).
+// limit: number of output positions that may be written (n, or out_cap).
+template <int NT, int VPT, bool FULL>
+__global__ __launch_bounds__(NT) void k_scan(const uint32_t* __restrict__ rows, uint32_t nrows, uint64_t row_stride,
+                                             uint32_t* __restrict__ H_out, uint64_t U, Ctl* ctl,
+                                             uint64_t* tile_state, FillItem* __restrict__ items,
+                                             uint32_t item_cap, uint64_t limit, int CL2, int report_overflow) {
+  constexpr int TB = NT * VPT;
+  constexpr int PADW = TB + TB / 32;
+  __shared__ uint32_t tr[VPT > 1 ? PADW : 1];
+  __shared__ uint64_t scan_tmp[NT / WAVE + 1];
+  __shared__ uint64_t s_prefix;
+  __shared__ uint32_t s_tile;
+  // long runs that cross many chunk starts, written cooperatively
+  __shared__ uint32_t lr_bin[NT];
+  __shared__ uint64_t lr_off[NT], lr_c0[NT], lr_cnt[NT];
+  __shared__ uint32_t lr_n;
+  __shared__ uint32_t s_item0;
+  const uint32_t tid = threadIdx.x;
+
+  uint64_t t = blockIdx.x;
+  if constexpr (FULL) {
+    if (tid == 0) s_tile = atomicAdd(&ctl->tile_ticket, 1u);
+    __syncthreads();
+    t = s_tile;
+  }
+  const uint64_t base = t * (uint64_t)TB;
+
+  // 1. sum the rows (striped layout: bin base + j*NT + tid)
+  uint32_t v[VPT];
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    const uint64_t k = base + (uint64_t)j * NT + tid;
+    uint32_t a = 0;
+    if (k < U) {
+      for (uint32_t r = 0; r < nrows; ++r) a += rows[(uint64_t)r * row_stride + k];
+      if (H_out) H_out[k] = a;
+    }
+    v[j] = a;
+  }
+  if constexpr (!FULL) return;
+
+  // 2. blocked layout: thread tid owns bins base + tid*VPT .. + VPT-1
+  if constexpr (VPT > 1) {
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      const uint32_t p = j * NT + tid;
+      tr[p + (p >> 5)] = v[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      const uint32_t p = tid * VPT + j;
+      v[j] = tr[p + (p >> 5)];
+    }
+  }
+  uint64_t tsum = 0;
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) tsum += v[j];
+  uint64_t agg;
+  const uint64_t texcl = block_exclusive_sum<NT>(tsum, scan_tmp, &agg);
+  const uint64_t agg_sat = agg > LB_VAL ? LB_VAL : agg;
+
+  // 3. decoupled look-back across tiles
+  if (tid < WAVE) {
+    if (t == 0) {
+      if (tid == 0) { st_release_u64(&tile_state[0], LB_FLAG_P | agg_sat); s_prefix = 0; }
+    } else {
+      if (tid == 0) st_release_u64(&tile_state[t], LB_FLAG_A | agg_sat);
+      const uint64_t pre = lookback(tile_state, t);
+      if (tid == 0) {
+        st_release_u64(&tile_state[t], LB_FLAG_P | sat_add(pre, agg_sat));
+        s_prefix = pre;
+      }
+    }
+  }
+  __syncthreads();
+  const uint64_t tpre = s_prefix;
+  const uint64_t ntiles = (U + TB - 1) / TB;
+  if (t == ntiles - 1 && tid == 0) {
+    const uint64_t total = sat_add(tpre, agg_sat);
+    const uint64_t lim = total < limit ? total : limit;
+    ctl->total = total;
+    ctl->limit = lim;
+    if (report_overflow && total > limit) set_status(ctl, ST_OVERFLOW);
+  }
+
+  // 4. fill items of this tile: its span [s, e), clipped at limit, cut at the
+  //    multiples of C.  Item 0 starts at s; item j >= 1 at (floor(s/C) + j) * C.
+  const uint64_t C = 1ull << CL2;
+  const uint64_t s0 = tpre < limit ? tpre : limit;
+  const uint64_t e0 = sat_add(tpre, agg_sat) < limit ? sat_add(tpre, agg_sat) : limit;
+  const uint64_t cbase = s0 >> CL2;
+  const uint64_t nit = e0 > s0 ? ((e0 + C - 1) >> CL2) - cbase : 0;
+  if (tid == 0) {
+    lr_n = 0;
+    uint32_t i0 = 0;
+    if (nit) {
+      i0 = atomicAdd(&ctl->nitems, (uint32_t)nit);
+      if ((uint64_t)i0 + nit > item_cap) { set_status(ctl, ST_INTERNAL); i0 = 0xFFFFFFFFu; }
+    }
+    s_item0 = i0;
+  }
+  __syncthreads();
+  const uint32_t item0 = s_item0;
+  const bool emit = nit > 0 && item0 != 0xFFFFFFFFu;
+  const uint32_t klast = (uint32_t)((base + TB < U ? base + TB : U) - 1);
+  uint64_t o = sat_add(tpre, texcl);
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    const uint64_t h = v[j];
+    const uint64_t bin = base + (uint64_t)tid * VPT + j;
+    uint64_t c0 = 0, cnt = 0;
+    if (emit && h > 0 && o < e0) {
+      const uint64_t e = sat_add(o, h) < e0 ? sat_add(o, h) : e0;  // run clipped to the span
+      if (o == s0) {  // the first nonzero bin opens item 0
+        FillItem it;
+        it.p0 = s0; it.p1 = ((cbase + 1) << CL2) < e0 ? ((cbase + 1) << CL2) : e0;
+        it.o = o; it.k = (uint32_t)bin; it.klast = klast;
+        items[item0] = it;
+      }
+      // chunk starts c*C strictly inside the span and inside [o, e)
+      uint64_t lo = (o + C - 1) >> CL2;
+      if (lo < cbase + 1) lo = cbase + 1;
+      const uint64_t hi = (e - 1) >> CL2;
+      c0 = lo;
+      cnt = hi >= lo ? hi - lo + 1 : 0;
+    }
+    if (cnt > 0 && cnt <= 4) {
+      for (uint64_t i = 0; i < cnt; ++i) {
+        const uint64_t c = c0 + i;
+        FillItem it;
+        it.p0 = c << CL2; it.p1 = ((c + 1) << CL2) < e0 ? ((c + 1) << CL2) : e0;
+        it.o = o; it.k = (uint32_t)bin; it.klast = klast;
+        items[item0 + (c - cbase)] = it;
+      }
+    } else if (cnt > 4) {
+      const uint32_t slot = atomicAdd(&lr_n, 1u);
+      lr_bin[slot] = (uint32_t)bin; lr_off[slot] = o; lr_c0[slot] = c0; lr_cnt[slot] = cnt;
+    }
+    // round j of long runs: all threads write their items
+    __syncthreads();
+    const uint32_t nl = lr_n;
+    for (uint32_t e = 0; e < nl; ++e) {
+      const uint32_t b = lr_bin[e];
+      const uint64_t oo = lr_off[e], cc = lr_c0[e], nn = lr_cnt[e];
+      for (uint64_t i = tid; i < nn; i += NT) {
+        const uint64_t c = cc + i;
+        FillItem it;
+        it.p0 = c << CL2; it.p1 = ((c + 1) << CL2) < e0 ? ((c + 1) << CL2) : e0;
+        it.o = oo; it.k = b; it.klast = klast;
+        items[item0 + (c - cbase)] = it;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) lr_n = 0;
+    __syncthreads();
+    o = sat_add(o, h);
+  }
+}
+
+// Persistent fill over the items.  NT threads, C = 2^CL2 = 32*NT local
+// positions (one 32-bit flag word per thread).  Local position i is output
+// position a0 + i with a0 = p0 rounded down to a multiple of 4; an item always
+// fits in [0, C) of that frame.
+template <int NT, int CL2, bool OALIGNED>
+__global__ __launch_bounds__(NT) void k_fill(const uint32_t* __restrict__ H, uint32_t* __restrict__ out,
+                                             const Ctl* ctl, const FillItem* __restrict__ items,
+                                             uint32_t item_cap) {
+  constexpr uint32_t C = 1u << CL2;
+  static_assert(C == 32 * NT, "one 32-bit flag word per thread");
+  __shared__ __align__(16) uint32_t val[C];
+  __shared__ uint32_t flag[NT];
+  __shared__ uint64_t scan_tmp[NT / WAVE + 1];
+  __shared__ int32_t last_idx[NT / WAVE];
+  __shared__ uint32_t carry[NT];
+  const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / WAVE;
+  // a failed invariant (reported as ST_INTERNAL) leaves items unwritten: fill nothing
+  const uint32_t nitems = (ctl->status & ST_INTERNAL) ? 0u : (ctl->nitems < item_cap ? ctl->nitems : item_cap);
+
+  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const FillItem I = items[it];
+    const uint64_t p0 = I.p0, p1 = I.p1;
+    const uint64_t a0 = p0 & ~3ull;
+    const uint32_t lb = (uint32_t)(p0 - a0), le = (uint32_t)(p1 - a0);  // local [lb, le) within [0, C)
+    flag[tid] = 0;
+    __syncthreads();
+    // walk the item's bins, marking run starts inside [p0, p1)
+    uint64_t kb = I.k;
+    uint64_t run = I.o;  // start position of bin kb's run (<= p0)
+    while (run < p1 && kb <= I.klast) {  // uniform: run and kb are block-wide values
+      const uint64_t k = kb + tid;
+      const uint64_t h = k <= I.klast ? H[k] : 0;
+      uint64_t tot;
+      const uint64_t ex = block_exclusive_sum<NT>(h, scan_tmp, &tot);
+      const uint64_t ok = run + ex;
+      if (h > 0 && ok < p1) {
+        const uint32_t pos = ok <= p0 ? lb : (uint32_t)(ok - a0);
+        val[pos] = (uint32_t)k;
+        atomicOr(&flag[pos >> 5], 1u << (pos & 31));
+      }
+      run += tot;
+      kb += NT;
+    }
+    __syncthreads();
+    // carry the last mark forward.  Segment s = local positions [32s, 32s+32)
+    // with flag word flag[s]; carry[s] = key of the last mark before segment s.
+    // Segment 0 always holds the item's first mark (at lb <= 3).
+    const uint32_t f = flag[tid];
+    int32_t inc = f ? (int32_t)tid : -1;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+      const int32_t y = __shfl_up(inc, d, WAVE);
+      if ((int)lane >= d && y > inc) inc = y;
+    }
+    if (lane == WAVE - 1) last_idx[w] = inc;
+    int32_t ex_idx = __shfl_up(inc, 1, WAVE);
+    if (lane == 0) ex_idx = -1;
+    __syncthreads();
+    for (uint32_t q = 0; q < w; ++q) ex_idx = last_idx[q] > ex_idx ? last_idx[q] : ex_idx;
+    uint32_t cin = 0;
+    if (ex_idx >= 0) cin = val[ex_idx * 32 + (31 - __clz(flag[ex_idx]))];
+    carry[tid] = cin;
+    __syncthreads();
+    // every output quad resolves its keys from its segment's flag word
+    const uint32_t nq = (le + 3) >> 2;
+    for (uint32_t q = tid; q < nq; q += NT) {
+      const uint32_t sg = q >> 3, b0 = (q & 7) * 4;
+      const uint32_t fw = flag[sg], ci = carry[sg];
+      uint32_t r[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const uint32_t mm = fw & (0xFFFFFFFFu >> (31 - (b0 + e)));
+        r[e] = mm ? val[sg * 32 + (31 - __clz(mm))] : ci;
+      }
+      const uint32_t i0 = q << 2;
+      if (OALIGNED && i0 >= lb && i0 + 4 <= le) {
+        *reinterpret_cast<uint4*>(out + a0 + i0) = make_uint4(r[0], r[1], r[2], r[3]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (i0 + e >= lb && i0 + e < le) out[a0 + i0 + e] = r[e];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace ds

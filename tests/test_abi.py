@@ -1,0 +1,78 @@
+"""The C-ABI library without a GPU: it loads, exports every symbol declared in
+include/dialsort.h, and rejects bad arguments on the host before anything is
+enqueued (those paths make no HIP call)."""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2605_16667_amd as ds
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "dialsort.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dialsort_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) >= 10
+    lib = ctypes.CDLL(ds.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(ds.EXPORTED) == names
+
+
+def test_workspace_query():
+    assert ds.dialsort_workspace_bytes(10, 0, 1) == 0
+    assert ds.dialsort_workspace_bytes(10, (1 << 32) + 1, 1) == 0
+    for n, U in [(0, 1), (1, 1), (1 << 20, 1 << 16), (10**8, 1 << 24), (1 << 28, 1 << 16), (5, 1 << 32)]:
+        for mode in (0, 1, 2):
+            assert ds.dialsort_workspace_bytes(n, U, mode) >= 512
+
+
+FAKE = 0x100000  # never dereferenced: every call below fails its host checks
+
+
+def test_host_argument_checks():
+    lib = ds._lib
+    big = 1 << 40
+    # U == 0 and U > 2^32
+    assert lib.dialsort_histogram(FAKE, 4, 0, FAKE, FAKE, big, None) == ds.DIALSORT_EINVAL
+    assert lib.dialsort_sort(FAKE, 4, (1 << 32) + 1, FAKE, FAKE, FAKE, big, None) == ds.DIALSORT_EINVAL
+    # null H, null keys with n > 0
+    assert lib.dialsort_histogram(FAKE, 4, 8, None, FAKE, big, None) == ds.DIALSORT_EINVAL
+    assert lib.dialsort_histogram(None, 4, 8, FAKE, FAKE, big, None) == ds.DIALSORT_EINVAL
+    # misaligned pointers
+    assert lib.dialsort_sort(FAKE + 2, 4, 8, FAKE + 4096, FAKE + 8192, FAKE + 16384, big, None) == ds.DIALSORT_EINVAL
+    # n beyond uint32 counters
+    assert lib.dialsort_histogram(FAKE, 1 << 32, 8, FAKE, FAKE, big, None) == ds.DIALSORT_EOVERFLOW
+    # workspace missing / too small
+    assert lib.dialsort_histogram(FAKE, 4, 8, FAKE + 4096, None, big, None) == ds.DIALSORT_EWORKSPACE
+    assert lib.dialsort_histogram(FAKE, 4, 8, FAKE + 4096, FAKE, 16, None) == ds.DIALSORT_EWORKSPACE
+    # out partially overlapping keys; H overlapping keys
+    assert lib.dialsort_sort(FAKE, 100, 8, FAKE + 4096, FAKE + 8, FAKE + 8192, big, None) == ds.DIALSORT_EINVAL
+    assert lib.dialsort_histogram(FAKE, 100, 8, FAKE + 16, FAKE + 8192, big, None) == ds.DIALSORT_EINVAL
+    # reconstruct: out_cap at or beyond 2^62, overlap with H
+    assert lib.dialsort_reconstruct(FAKE, 8, FAKE + 4096, 1 << 62, FAKE, big, None) == ds.DIALSORT_EINVAL
+    assert lib.dialsort_reconstruct(FAKE, 8, FAKE + 16, 4, FAKE + 8192, big, None) == ds.DIALSORT_EINVAL
+
+
+def test_batched_argument_checks():
+    d = (ds.dialsort_desc * 2)()
+    d[0] = ds.dialsort_desc(FAKE, 4, 8, FAKE + 4096, FAKE + 8192)
+    d[1] = ds.dialsort_desc(FAKE, 4, 0, FAKE + 4096, FAKE + 8192)  # U == 0
+    assert ds._lib.dialsort_sort_batched(d, 2, FAKE + 65536, 1 << 40, None) == ds.DIALSORT_EINVAL
+    assert ds._lib.dialsort_batched_workspace_bytes(d, 1) > 0
+
+
+def test_strerror():
+    for s in range(6):
+        assert ds.dialsort_strerror(s)
