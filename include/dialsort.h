@@ -109,6 +109,19 @@ dialsort_status dialsort_status_sync(const void *ws, hipStream_t stream);
  * dialsort_reconstruct or dialsort_sort that used ws (saturated at 2^62 - 1). */
 dialsort_status dialsort_result_total(const void *ws, hipStream_t stream, uint64_t *total);
 
+/* Measurement hook, for benchmarks and profilers.  While set, every later call
+ * on this host thread records events[i] on its stream just before its i-th
+ * kernel launch (i < cap - 1) and one more event after its last launch, and
+ * stores the call's number of launches in *count (if count is not null).  The
+ * caller creates the events (hipEventCreate) and keeps them alive while the hook
+ * is set; events == NULL switches the hook off.  cap < 2 with non-null events is
+ * EINVAL.  The hook never changes what a call computes. */
+dialsort_status dialsort_set_launch_events(hipEvent_t *events, uint32_t cap, uint32_t *count);
+
+/* Kernel name of launch i of the last call on this host thread (NULL when i is
+ * out of range).  Static storage. */
+const char *dialsort_launch_name(uint32_t i);
+
 /* Text for a status code (static storage). */
 const char *dialsort_strerror(dialsort_status status);
 

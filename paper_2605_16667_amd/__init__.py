@@ -53,6 +53,8 @@ def _load() -> ctypes.CDLL:
         "dialsort_result_total": (st, [p, p, ctypes.POINTER(u64)]),
         "dialsort_strerror": (ctypes.c_char_p, [st]),
         "dialsort_last_hip_error": (ctypes.c_int, []),
+        "dialsort_set_launch_events": (st, [p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]),
+        "dialsort_launch_name": (ctypes.c_char_p, [ctypes.c_uint32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -63,7 +65,8 @@ def _load() -> ctypes.CDLL:
 _lib = _load()
 EXPORTED = ("dialsort_workspace_bytes", "dialsort_histogram", "dialsort_reconstruct", "dialsort_sort",
             "dialsort_batched_workspace_bytes", "dialsort_sort_batched", "dialsort_status_sync",
-            "dialsort_result_total", "dialsort_strerror", "dialsort_last_hip_error")
+            "dialsort_result_total", "dialsort_strerror", "dialsort_last_hip_error",
+            "dialsort_set_launch_events", "dialsort_launch_name")
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -148,3 +151,14 @@ def dialsort_result_total(ws: torch.Tensor, stream=None) -> Tuple[int, int]:
     total = ctypes.c_uint64(0)
     st = _lib.dialsort_result_total(_ptr(ws), _stream(stream), ctypes.byref(total))
     return st, total.value
+
+
+def dialsort_set_launch_events(events, cap: int, count) -> int:
+    """events: a ctypes array of hipEvent_t handles (or None to switch off);
+    count: a ctypes.c_uint32 that receives the number of launches per call."""
+    return _lib.dialsort_set_launch_events(events, cap, ctypes.byref(count) if count is not None else None)
+
+
+def dialsort_launch_name(i: int) -> Optional[str]:
+    r = _lib.dialsort_launch_name(i)
+    return r.decode() if r else None

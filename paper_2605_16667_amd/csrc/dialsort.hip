@@ -134,14 +134,43 @@ inline bool overlap(const void* a, size_t abytes, const void* b, size_t bbytes) 
 
 inline char* ws_base(void* ws) { return (char*)align_up((uintptr_t)ws, ALIGN); }
 
-#define DS_LAUNCH(...)                                  \
-  do {                                                  \
-    hipLaunchKernelGGL(__VA_ARGS__);                    \
-    hipError_t e_ = hipGetLastError();                  \
-    if (e_ != hipSuccess) {                             \
-      g_last_hip_error = (int)e_;                       \
-      return DIALSORT_EHIP;                             \
-    }                                                   \
+// Measurement hook (dialsort_set_launch_events): per host thread, an optional
+// caller-owned event array; events[i] is recorded on the launch stream just
+// before launch i of the current call, events[count] after its last launch.
+struct LaunchLog {
+  hipEvent_t* ev = nullptr;
+  uint32_t cap = 0;
+  uint32_t* count = nullptr;
+  uint32_t n = 0;
+  const char* names[64];
+};
+thread_local LaunchLog g_log;
+
+inline void log_launch(const char* name, hipStream_t s) {
+  if (g_log.ev && g_log.n + 1 < g_log.cap) (void)hipEventRecord(g_log.ev[g_log.n], s);
+  if (g_log.n < 64) g_log.names[g_log.n] = name;
+  ++g_log.n;
+}
+
+// Opens a public call: resets the launch log; on close records the end event.
+struct CallScope {
+  hipStream_t s;
+  explicit CallScope(hipStream_t st) : s(st) { g_log.n = 0; }
+  ~CallScope() {
+    if (g_log.ev && g_log.n < g_log.cap) (void)hipEventRecord(g_log.ev[g_log.n], s);
+    if (g_log.count) *g_log.count = g_log.n;
+  }
+};
+
+#define DS_LAUNCH(kernel, grid, block, stream, ...)                      \
+  do {                                                                   \
+    log_launch(#kernel, stream);                                         \
+    hipLaunchKernelGGL(kernel, grid, block, 0, stream, __VA_ARGS__);     \
+    hipError_t e_ = hipGetLastError();                                   \
+    if (e_ != hipSuccess) {                                              \
+      g_last_hip_error = (int)e_;                                        \
+      return DIALSORT_EHIP;                                              \
+    }                                                                    \
   } while (0)
 
 // k_init: clear the control block, the look-back flags, and optionally H.
@@ -157,7 +186,7 @@ __global__ void k_init(Ctl* ctl, uint64_t* tiles, uint64_t ntiles, uint32_t* H, 
 dialsort_status launch_init(char* base, const Layout& L, uint32_t* H, uint64_t nH, hipStream_t s) {
   const uint64_t work = std::max<uint64_t>(std::max<uint64_t>(64, L.scan ? L.scan_tiles : 0), nH);
   const uint32_t grid = (uint32_t)std::min<uint64_t>(cdiv(work, 256), 2048);
-  DS_LAUNCH(k_init, dim3(grid), dim3(256), 0, s, (Ctl*)base, (uint64_t*)(base + L.off_tile),
+  DS_LAUNCH(k_init, dim3(grid), dim3(256), s, (Ctl*)base, (uint64_t*)(base + L.off_tile),
             L.scan ? L.scan_tiles : 0, H, nH);
   return DIALSORT_OK;
 }
@@ -171,30 +200,30 @@ dialsort_status launch_ingest(const uint32_t* keys, uint64_t n, uint64_t U, uint
   uint32_t* rows = L.rows_in_ws ? (uint32_t*)(base + L.off_rows) : H;
   switch (L.kind) {
     case K_LDS32S:
-      if (ka) DS_LAUNCH((k_hist_lds<1024, 4096, false, 1, true, 2>), dim3(L.G), dim3(1024), 0, s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
-      else DS_LAUNCH((k_hist_lds<1024, 4096, false, 1, false, 2>), dim3(L.G), dim3(1024), 0, s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
+      if (ka) DS_LAUNCH((k_hist_lds<1024, 4096, false, 1, true, 2>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
+      else DS_LAUNCH((k_hist_lds<1024, 4096, false, 1, false, 2>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
       break;
     case K_LDS32:
-      if (ka) DS_LAUNCH((k_hist_lds<1024, 32768, false, 1, true, 2>), dim3(L.G), dim3(1024), 0, s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
-      else DS_LAUNCH((k_hist_lds<1024, 32768, false, 1, false, 2>), dim3(L.G), dim3(1024), 0, s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
+      if (ka) DS_LAUNCH((k_hist_lds<1024, 32768, false, 1, true, 2>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
+      else DS_LAUNCH((k_hist_lds<1024, 32768, false, 1, false, 2>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
       break;
     case K_LDS16:
-      if (ka) DS_LAUNCH((k_hist_lds<1024, 32768, true, 1, true, 2>), dim3(L.G), dim3(1024), 0, s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
-      else DS_LAUNCH((k_hist_lds<1024, 32768, true, 1, false, 2>), dim3(L.G), dim3(1024), 0, s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
+      if (ka) DS_LAUNCH((k_hist_lds<1024, 32768, true, 1, true, 2>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
+      else DS_LAUNCH((k_hist_lds<1024, 32768, true, 1, false, 2>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
       break;
     case K_PART: {
       uint16_t* stg = (uint16_t*)(base + L.off_stage);
       uint16_t* seg = (uint16_t*)(base + L.off_seg);
-      if (ka) DS_LAUNCH((k_partition<0, true>), dim3(L.T), dim3(PART_NT), 0, s, keys, n, umax, L.B, stg, seg, L.bstride, ctl);
-      else DS_LAUNCH((k_partition<0, false>), dim3(L.T), dim3(PART_NT), 0, s, keys, n, umax, L.B, stg, seg, L.bstride, ctl);
-      if (aligned16(H)) DS_LAUNCH((k_bucket<1, true>), dim3(L.B), dim3(PART_NT), 0, s, stg, seg, L.bstride, L.T, L.B, U, H);
-      else DS_LAUNCH((k_bucket<1, false>), dim3(L.B), dim3(PART_NT), 0, s, stg, seg, L.bstride, L.T, L.B, U, H);
+      if (ka) DS_LAUNCH((k_partition<0, true>), dim3(L.T), dim3(PART_NT), s, keys, n, umax, L.B, stg, seg, L.bstride, ctl);
+      else DS_LAUNCH((k_partition<0, false>), dim3(L.T), dim3(PART_NT), s, keys, n, umax, L.B, stg, seg, L.bstride, ctl);
+      if (aligned16(H)) DS_LAUNCH((k_bucket<1, true>), dim3(L.B), dim3(PART_NT), s, stg, seg, L.bstride, L.T, L.B, U, H);
+      else DS_LAUNCH((k_bucket<1, false>), dim3(L.B), dim3(PART_NT), s, stg, seg, L.bstride, L.T, L.B, U, H);
       break;
     }
     case K_GLOBAL: {
       const uint32_t grid = (uint32_t)std::min<uint64_t>(cdiv(n, 256 * 4), 4096);
-      if (ka) DS_LAUNCH((k_hist_global<256, 1, true>), dim3(grid), dim3(256), 0, s, keys, n, umax, H, ctl);
-      else DS_LAUNCH((k_hist_global<256, 1, false>), dim3(grid), dim3(256), 0, s, keys, n, umax, H, ctl);
+      if (ka) DS_LAUNCH((k_hist_global<256, 1, true>), dim3(grid), dim3(256), s, keys, n, umax, H, ctl);
+      else DS_LAUNCH((k_hist_global<256, 1, false>), dim3(grid), dim3(256), s, keys, n, umax, H, ctl);
       break;
     }
     default:
@@ -214,14 +243,14 @@ dialsort_status launch_scan(const uint32_t* rows, uint32_t nrows, uint64_t row_s
   const dim3 grid((uint32_t)L.scan_tiles);
   if (full) {
     if (L.scan_vpt == 1)
-      DS_LAUNCH((k_scan<SCAN_NT, 1, true>), grid, dim3(SCAN_NT), 0, s, rows, nrows, row_stride, H_out, U, ctl, tiles, items, icap, L.limit, FILL_CL2, report_overflow);
+      DS_LAUNCH((k_scan<SCAN_NT, 1, true>), grid, dim3(SCAN_NT), s, rows, nrows, row_stride, H_out, U, ctl, tiles, items, icap, L.limit, FILL_CL2, report_overflow);
     else
-      DS_LAUNCH((k_scan<SCAN_NT, 16, true>), grid, dim3(SCAN_NT), 0, s, rows, nrows, row_stride, H_out, U, ctl, tiles, items, icap, L.limit, FILL_CL2, report_overflow);
+      DS_LAUNCH((k_scan<SCAN_NT, 16, true>), grid, dim3(SCAN_NT), s, rows, nrows, row_stride, H_out, U, ctl, tiles, items, icap, L.limit, FILL_CL2, report_overflow);
   } else {
     if (L.scan_vpt == 1)
-      DS_LAUNCH((k_scan<SCAN_NT, 1, false>), grid, dim3(SCAN_NT), 0, s, rows, nrows, row_stride, H_out, U, ctl, tiles, items, icap, L.limit, FILL_CL2, report_overflow);
+      DS_LAUNCH((k_scan<SCAN_NT, 1, false>), grid, dim3(SCAN_NT), s, rows, nrows, row_stride, H_out, U, ctl, tiles, items, icap, L.limit, FILL_CL2, report_overflow);
     else
-      DS_LAUNCH((k_scan<SCAN_NT, 16, false>), grid, dim3(SCAN_NT), 0, s, rows, nrows, row_stride, H_out, U, ctl, tiles, items, icap, L.limit, FILL_CL2, report_overflow);
+      DS_LAUNCH((k_scan<SCAN_NT, 16, false>), grid, dim3(SCAN_NT), s, rows, nrows, row_stride, H_out, U, ctl, tiles, items, icap, L.limit, FILL_CL2, report_overflow);
   }
   return DIALSORT_OK;
 }
@@ -233,9 +262,9 @@ dialsort_status launch_fill(const uint32_t* H, uint32_t* out, char* base, const 
   const uint32_t grid = (uint32_t)std::min<uint64_t>(L.item_cap, 256 * 8);
   const uint32_t icap = (uint32_t)std::min<uint64_t>(L.item_cap, 0xFFFFFFF0ull);
   if (aligned16(out))
-    DS_LAUNCH((k_fill<FILL_NT, FILL_CL2, true>), dim3(grid), dim3(FILL_NT), 0, s, H, out, ctl, items, icap);
+    DS_LAUNCH((k_fill<FILL_NT, FILL_CL2, true>), dim3(grid), dim3(FILL_NT), s, H, out, ctl, items, icap);
   else
-    DS_LAUNCH((k_fill<FILL_NT, FILL_CL2, false>), dim3(grid), dim3(FILL_NT), 0, s, H, out, ctl, items, icap);
+    DS_LAUNCH((k_fill<FILL_NT, FILL_CL2, false>), dim3(grid), dim3(FILL_NT), s, H, out, ctl, items, icap);
   return DIALSORT_OK;
 }
 
@@ -306,7 +335,7 @@ dialsort_status batch_run(const dialsort_desc* d, uint32_t count, void* ws, size
   char* sub = base + ALIGN;
   for (uint32_t i = 0; i < count; ++i) {
     DS_TRY(run_sort(d[i].keys, d[i].n, d[i].U, d[i].H, d[i].out, sub, DIALSORT_MODE_SORT, s));
-    DS_LAUNCH(k_or_status, dim3(1), dim3(64), 0, s, (Ctl*)base, (const Ctl*)sub);
+    DS_LAUNCH(k_or_status, dim3(1), dim3(64), s, (Ctl*)base, (const Ctl*)sub);
   }
   return DIALSORT_OK;
 }
@@ -327,6 +356,7 @@ dialsort_status dialsort_histogram(const uint32_t* keys, uint64_t n, uint64_t U,
   if (n > N_MAX) return DIALSORT_EOVERFLOW;
   if (overlap(keys, n * 4, H, U * 4)) return DIALSORT_EINVAL;
   DS_TRY(check_common(U, ws, ws_bytes, dialsort_workspace_bytes(n, U, DIALSORT_MODE_HISTOGRAM)));
+  CallScope scope(stream);
   return run_sort(keys, n, U, H, nullptr, ws, DIALSORT_MODE_HISTOGRAM, stream);
 }
 
@@ -338,6 +368,7 @@ dialsort_status dialsort_sort(const uint32_t* keys, uint64_t n, uint64_t U, uint
   if (overlap(keys, n * 4, H, U * 4) || overlap(out, n * 4, H, U * 4)) return DIALSORT_EINVAL;
   if (out != keys && overlap(keys, n * 4, out, n * 4)) return DIALSORT_EINVAL;
   DS_TRY(check_common(U, ws, ws_bytes, dialsort_workspace_bytes(n, U, DIALSORT_MODE_SORT)));
+  CallScope scope(stream);
   return run_sort(keys, n, U, H, out, ws, DIALSORT_MODE_SORT, stream);
 }
 
@@ -350,6 +381,7 @@ dialsort_status dialsort_reconstruct(const uint32_t* H, uint64_t U, uint32_t* ou
   DS_TRY(check_common(U, ws, ws_bytes, dialsort_workspace_bytes(out_cap, U, DIALSORT_MODE_RECONSTRUCT)));
   const Layout L = plan(out_cap, U, DIALSORT_MODE_RECONSTRUCT);
   char* base = ws_base(ws);
+  CallScope scope(stream);
   DS_TRY(launch_init(base, L, nullptr, 0, stream));
   DS_TRY(launch_scan(H, 1, 0, nullptr, U, base, L, true, 1, stream));
   DS_TRY(launch_fill(H, out, base, L, stream));
@@ -362,7 +394,20 @@ size_t dialsort_batched_workspace_bytes(const dialsort_desc* descs, uint32_t cou
 
 dialsort_status dialsort_sort_batched(const dialsort_desc* descs, uint32_t count, void* ws, size_t ws_bytes,
                                       hipStream_t stream) {
+  CallScope scope(stream);
   return batch_run(descs, count, ws, ws_bytes, stream);
+}
+
+dialsort_status dialsort_set_launch_events(hipEvent_t* events, uint32_t cap, uint32_t* count) {
+  if (events && cap < 2) return DIALSORT_EINVAL;
+  g_log.ev = events;
+  g_log.cap = events ? cap : 0;
+  g_log.count = events ? count : nullptr;
+  return DIALSORT_OK;
+}
+
+const char* dialsort_launch_name(uint32_t i) {
+  return i < g_log.n && i < 64 ? g_log.names[i] : nullptr;
 }
 
 dialsort_status dialsort_status_sync(const void* ws, hipStream_t stream) {
