@@ -6,9 +6,9 @@
 // block and the look-back tile flags, and zeroes H only where H is accumulated
 // with atomics):
 //   LDS32 / LDS16 (U <= 65536):  k_hist_lds -> [k_scan: sum rows into H]
-//   PART (65536 < U <= 2^28):     k_partition -> k_bucket
-//   GLOBAL (tiny n, or U > 2^28): k_hist_global
-//   sort adds                      k_scan (look-back + chunk map) -> k_fill
+//   PART (65536 < U <= 2^29):     k_partition -> k_bucket (H, and fill items)
+//   GLOBAL (tiny n, or U > 2^29): k_hist_global
+//   sort adds                      [k_scan: look-back scan + fill items] -> k_fill
 //   reconstruct                    k_init -> k_scan -> k_fill
 #include <hip/hip_runtime.h>
 
@@ -80,7 +80,7 @@ Layout plan(uint64_t n, uint64_t U, int mode) {
     L.kind = K_NONE;
   } else if (n == 0) {
     L.kind = K_EMPTY;
-  } else if (U > (uint64_t)PART_W * PART_BMAX || (U > 65536 && n < (uint64_t)PART_TK)) {
+  } else if (U > PART_UMAX || (U > 65536 && n < (uint64_t)PART_TK)) {
     L.kind = K_GLOBAL;
   } else if (U <= 4096) {
     L.kind = K_LDS32S;
@@ -103,13 +103,14 @@ Layout plan(uint64_t n, uint64_t U, int mode) {
     L.rows_in_ws = L.G > 1;
     L.row_stride = align_up(U + 1, 64);
   }
-  // scan tiles (also used to sum partial rows in histogram mode)
+  // scan tiles (also used to sum partial rows in histogram mode); the
+  // partitioned path projects bucket by bucket and needs no scan
   L.scan_vpt = (L.rows_in_ws && L.G >= 8) ? 1 : 16;
-  L.scan_tiles = cdiv(U, (uint64_t)SCAN_NT * L.scan_vpt);
+  L.scan_tiles = L.kind == K_PART ? 0 : cdiv(U, (uint64_t)SCAN_NT * L.scan_vpt);
   if (L.scan) {
     L.off_tile = off; off = align_up(off + L.scan_tiles * 8, ALIGN);
-    // at most one item per tile plus one per chunk start
-    L.item_cap = L.scan_tiles + cdiv(L.limit, 1ull << FILL_CL2) + 2;
+    // at most one item per scan tile (or heavy bucket) plus one per chunk start
+    L.item_cap = (L.kind == K_PART ? L.B : L.scan_tiles) + cdiv(L.limit, 1ull << FILL_CL2) + 2;
     L.off_items = off; off = align_up(off + L.item_cap * sizeof(FillItem), ALIGN);
   }
   if (L.rows_in_ws) {
@@ -200,30 +201,45 @@ dialsort_status launch_ingest(const uint32_t* keys, uint64_t n, uint64_t U, uint
   uint32_t* rows = L.rows_in_ws ? (uint32_t*)(base + L.off_rows) : H;
   switch (L.kind) {
     case K_LDS32S:
-      if (ka) DS_LAUNCH((k_hist_lds<1024, 4096, false, 1, true, 2>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
-      else DS_LAUNCH((k_hist_lds<1024, 4096, false, 1, false, 2>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
+      if (ka) DS_LAUNCH((k_hist_lds<1024, 4096, false, 3, true, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
+      else DS_LAUNCH((k_hist_lds<1024, 4096, false, 3, false, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
       break;
     case K_LDS32:
-      if (ka) DS_LAUNCH((k_hist_lds<1024, 32768, false, 1, true, 2>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
-      else DS_LAUNCH((k_hist_lds<1024, 32768, false, 1, false, 2>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
+      if (ka) DS_LAUNCH((k_hist_lds<1024, 32768, false, 3, true, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
+      else DS_LAUNCH((k_hist_lds<1024, 32768, false, 3, false, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
       break;
     case K_LDS16:
-      if (ka) DS_LAUNCH((k_hist_lds<1024, 32768, true, 1, true, 2>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
-      else DS_LAUNCH((k_hist_lds<1024, 32768, true, 1, false, 2>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
+      if (ka) DS_LAUNCH((k_hist_lds<1024, 32768, true, 3, true, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
+      else DS_LAUNCH((k_hist_lds<1024, 32768, true, 3, false, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
       break;
     case K_PART: {
       uint16_t* stg = (uint16_t*)(base + L.off_stage);
       uint16_t* seg = (uint16_t*)(base + L.off_seg);
-      if (ka) DS_LAUNCH((k_partition<0, true>), dim3(L.T), dim3(PART_NT), s, keys, n, umax, L.B, stg, seg, L.bstride, ctl);
-      else DS_LAUNCH((k_partition<0, false>), dim3(L.T), dim3(PART_NT), s, keys, n, umax, L.B, stg, seg, L.bstride, ctl);
-      if (aligned16(H)) DS_LAUNCH((k_bucket<1, true>), dim3(L.B), dim3(PART_NT), s, stg, seg, L.bstride, L.T, L.B, U, H);
-      else DS_LAUNCH((k_bucket<1, false>), dim3(L.B), dim3(PART_NT), s, stg, seg, L.bstride, L.T, L.B, U, H);
+      if (L.B <= 1024) {
+        if (ka) DS_LAUNCH((k_partition<1024, 3, true>), dim3(L.T), dim3(P1_NT), s, keys, n, umax, L.B, stg, seg, L.bstride, ctl);
+        else DS_LAUNCH((k_partition<1024, 3, false>), dim3(L.T), dim3(P1_NT), s, keys, n, umax, L.B, stg, seg, L.bstride, ctl);
+      } else {
+        if (ka) DS_LAUNCH((k_partition<PART_BMAX, 3, true>), dim3(L.T), dim3(P1_NT), s, keys, n, umax, L.B, stg, seg, L.bstride, ctl);
+        else DS_LAUNCH((k_partition<PART_BMAX, 3, false>), dim3(L.T), dim3(P1_NT), s, keys, n, umax, L.B, stg, seg, L.bstride, ctl);
+      }
+      FillItem* items = (FillItem*)(base + L.off_items);
+      const uint32_t icap = (uint32_t)std::min<uint64_t>(L.item_cap, 0xFFFFFFF0ull);
+      const bool ha = aligned16(H);
+#define DS_BUCKET(HA, FULL)                                                                                      \
+  DS_LAUNCH((k_bucket<3, HA, FULL>), dim3(L.B), dim3(PART_NT), s, stg, seg, L.bstride, L.T, L.B, U, H, ctl, items, \
+            icap, FILL_CL2)
+      if (!L.scan) {
+        if (ha) DS_BUCKET(true, false); else DS_BUCKET(false, false);
+      } else {
+        if (ha) DS_BUCKET(true, true); else DS_BUCKET(false, true);
+      }
+#undef DS_BUCKET
       break;
     }
     case K_GLOBAL: {
       const uint32_t grid = (uint32_t)std::min<uint64_t>(cdiv(n, 256 * 4), 4096);
-      if (ka) DS_LAUNCH((k_hist_global<256, 1, true>), dim3(grid), dim3(256), s, keys, n, umax, H, ctl);
-      else DS_LAUNCH((k_hist_global<256, 1, false>), dim3(grid), dim3(256), s, keys, n, umax, H, ctl);
+      if (ka) DS_LAUNCH((k_hist_global<256, 3, true>), dim3(grid), dim3(256), s, keys, n, umax, H, ctl);
+      else DS_LAUNCH((k_hist_global<256, 3, false>), dim3(grid), dim3(256), s, keys, n, umax, H, ctl);
       break;
     }
     default:
@@ -294,8 +310,9 @@ dialsort_status run_sort(const uint32_t* keys, uint64_t n, uint64_t U, uint32_t*
     if (L.rows_in_ws) DS_TRY(launch_scan(rows, nrows, L.row_stride, H, U, base, L, false, 0, s));
     return DIALSORT_OK;
   }
-  DS_TRY(launch_scan(rows, nrows, L.rows_in_ws ? L.row_stride : 0, L.rows_in_ws ? H : nullptr, U, base, L,
-                     true, 0, s));
+  if (L.kind != K_PART)
+    DS_TRY(launch_scan(rows, nrows, L.rows_in_ws ? L.row_stride : 0, L.rows_in_ws ? H : nullptr, U, base, L,
+                       true, 0, s));
   DS_TRY(launch_fill(H, out, base, L, s));
   return DIALSORT_OK;
 }

@@ -15,9 +15,12 @@
 //     the high field made that field cross one).  Each crossing is logged as a
 //     +-65536 event for its bin; a low-field carry is taken back out of the high
 //     field with a second atomic.  The field's final value plus 65536 times its
-//     net events is its exact count.  With at most 2^22 keys per workgroup a
-//     workgroup logs at most 256 events (the log holds 512).
+//     net events is its exact count, in whatever order the adds land.  With at
+//     most 2^22 keys per workgroup a workgroup logs at most 256 events (the log
+//     holds 512).
 #pragma once
+
+#include <type_traits>
 
 #include "common.hpp"
 #include "crn_wave.hpp"
@@ -49,37 +52,34 @@ __device__ __forceinline__ uint32_t load_group(const uint32_t* __restrict__ keys
 
 constexpr int LDS16_EVCAP = 512;
 
-struct Lds32Emit {
-  uint32_t* s;
-  __device__ __forceinline__ void operator()(uint32_t k, uint32_t c) { atomicAdd(&s[k], c); }
-};
-
-struct Lds16Emit {
-  uint32_t* words;   // packed counters: bin 2i in bits 0..15, bin 2i+1 in bits 16..31
+// Event log of the packed counters (rare path).
+struct Lds16Log {
   uint32_t* evflag;  // one bit per bin: the bin has logged events
-  uint32_t* ev;      // event log: bin | (0x80000000 if the event is -65536)
+  uint32_t* ev;      // bin | (0x80000000 if the event is -65536)
   uint32_t* nev;
-  __device__ __forceinline__ void log(uint32_t bin, bool neg) {
+  __device__ __forceinline__ void log(uint32_t bin, bool neg) const {
     const uint32_t i = atomicAdd(nev, 1u);
     if (i < LDS16_EVCAP) ev[i] = bin | (neg ? 0x80000000u : 0u);
     atomicOr(&evflag[bin >> 5], 1u << (bin & 31));
   }
-  __device__ __forceinline__ void operator()(uint32_t k, uint32_t c) {
-    const uint32_t w = k >> 1;
-    if ((k & 1u) == 0) {
-      const uint32_t old = atomicAdd(&words[w], c);
-      if ((old & 0xFFFFu) + c >= 0x10000u) {  // low field crossed a multiple of 65536
-        log(k, false);
-        if ((old >> 16) == 0xFFFFu) log(k + 1, false);  // its carry wrapped the high field
-        const uint32_t old2 = atomicAdd(&words[w], 0xFFFF0000u);  // take the carry back out
-        if ((old2 >> 16) == 0u) log(k + 1, true);
-      }
-    } else {
-      const uint32_t old = atomicAdd(&words[w], c << 16);
-      if ((old >> 16) + c >= 0x10000u) log(k, false);
-    }
-  }
 };
+
+// The add of count c to bin k returned `old`; log the crossings it caused.
+__device__ __noinline__ void lds16_crossing(uint32_t* words, uint32_t k, uint32_t c, uint32_t old,
+                                            uint32_t* evflag, uint32_t* ev, uint32_t* nev) {
+  Lds16Log L;
+  L.evflag = evflag;
+  L.ev = ev;
+  L.nev = nev;
+  if ((k & 1u) == 0) {
+    L.log(k, false);                                  // the low field crossed
+    if ((old >> 16) == 0xFFFFu) L.log(k + 1, false);  // its carry wrapped the high field
+    const uint32_t old2 = atomicAdd(&words[k >> 1], 0xFFFF0000u);  // take the carry back out
+    if ((old2 >> 16) == 0u) L.log(k + 1, true);
+  } else {
+    L.log(k, false);
+  }
+}
 
 // NT threads; CAP = LDS words; PACKED selects the 16-bit layout.
 // rows: G rows of `row_stride` uint32 each (row g at rows + g*row_stride).
@@ -104,27 +104,42 @@ __global__ __launch_bounds__(NT) void k_hist_lds(const uint32_t* __restrict__ ke
   const uint64_t end = beg + per < n ? beg + per : n;
   bool bad = false;
   WaveAgg st;
-  using Emit = typename std::conditional<PACKED, Lds16Emit, Lds32Emit>::type;
-  Emit emit;
-  if constexpr (PACKED) {
-    emit.words = s; emit.evflag = evflag; emit.ev = ev; emit.nev = &nev;
-  } else {
-    emit.s = s;
-  }
   // uniform trip count across the workgroup: every lane takes part in the ballots
   for (uint64_t g0 = beg; g0 < end; g0 += (uint64_t)NT * 4 * UNR) {
     uint32_t v[UNR][4];
-    uint32_t c[UNR];
+    uint32_t nv[UNR];
 #pragma unroll
-    for (int u = 0; u < UNR; ++u) c[u] = load_group<ALIGNED>(keys, g0 + ((uint64_t)u * NT + tid) * 4, end, v[u]);
+    for (int u = 0; u < UNR; ++u) nv[u] = load_group<ALIGNED>(keys, g0 + ((uint64_t)u * NT + tid) * 4, end, v[u]);
+    uint32_t cc[UNR][4];
+    uint32_t old[UNR][4];
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const bool valid = (uint32_t)i < c[u];
+        const bool valid = (uint32_t)i < nv[u];
         const bool ok = valid && v[u][i] <= umax;
         bad |= valid && !ok;
-        wave_merge<AGG>(v[u][i], ok, st, emit);
+        WaveGroups g;
+        const uint32_t c = wave_merge_count<AGG>(v[u][i], ok, st, g);
+        cc[u][i] = c;
+        old[u][i] = 0;
+        if constexpr (!PACKED) {
+          if (c) atomicAdd(&s[v[u][i]], c);
+        } else {
+          if (c) old[u][i] = atomicAdd(&s[v[u][i] >> 1], c << ((v[u][i] & 1u) << 4));
+        }
+      }
+    }
+    if constexpr (PACKED) {
+      // crossing checks after every add of the iteration has been issued
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint32_t c = cc[u][i], k = v[u][i];
+          const uint32_t field = (old[u][i] >> ((k & 1u) << 4)) & 0xFFFFu;
+          if (c && field + c >= 0x10000u) lds16_crossing(s, k, c, old[u][i], evflag, ev, &nev);
+        }
       }
     }
   }
@@ -157,17 +172,11 @@ __global__ __launch_bounds__(NT) void k_hist_lds(const uint32_t* __restrict__ ke
 
 // Direct global atomics into a zeroed H, after the same wave merge.  Used when
 // n is small next to U, or U is too large for the partitioned path.
-struct GlobalEmit {
-  uint32_t* H;
-  __device__ __forceinline__ void operator()(uint32_t k, uint32_t c) { atomicAdd(&H[k], c); }
-};
-
 template <int NT, int AGG, bool ALIGNED>
 __global__ __launch_bounds__(NT) void k_hist_global(const uint32_t* __restrict__ keys, uint64_t n, uint32_t umax,
                                                     uint32_t* __restrict__ H, Ctl* ctl) {
   bool bad = false;
   WaveAgg st;
-  GlobalEmit emit{H};
   const uint64_t stride = (uint64_t)gridDim.x * NT * 4;
   for (uint64_t g0 = (uint64_t)blockIdx.x * NT * 4; g0 < n; g0 += stride) {
     uint32_t v[4];
@@ -177,7 +186,7 @@ __global__ __launch_bounds__(NT) void k_hist_global(const uint32_t* __restrict__
       const bool valid = (uint32_t)i < c;
       const bool ok = valid && v[i] <= umax;
       bad |= valid && !ok;
-      wave_merge<AGG>(v[i], ok, st, emit);
+      wave_count<AGG>(H, v[i], ok, st);
     }
   }
   if (__syncthreads_or(bad) && threadIdx.x == 0) set_status(ctl, ST_RANGE);

@@ -1,74 +1,100 @@
-// U-range-partitioned ingestion for universes larger than one workgroup's LDS.
+// U-range-partitioned ingestion and projection for universes larger than one
+// workgroup's LDS.
 //
 // The paper leaves large universes to a "hierarchical" scheme it lists as future
 // work (Sec. 16 and Sec. 17); this two-pass design is ours.  The universe is cut
-// into B buckets of W = 2^15 consecutive keys (bucket of x = x >> 15).
+// into B buckets of W = 2^16 consecutive keys (bucket of x = x >> 16).
 //
-// Pass 1 (k_partition): workgroup t takes tile t of TK = 32768 keys, ranks every
-// key inside its bucket with LDS atomics (after the wavefront equality merge),
-// and writes the tile's keys grouped by bucket as uint16 bucket-relative keys
-// (x & 0x7FFF) into its own slice of the staging buffer, plus the tile's B+1
-// segment starts.  Staging stays tile-major, so every write is a coalesced
-// 16-byte store and no global counter is needed.
+// Pass 1 (k_partition): workgroup t takes tile t of TK = 8192 keys, counts them
+// per bucket, scans the counts and places every key at a cursor of its bucket
+// (LDS atomics, after the wavefront equality merge).  It writes the tile's keys
+// grouped by bucket as uint16 bucket-relative keys (x & 0xFFFF) into its own
+// slice of the staging buffer, plus the tile's B+1 segment starts seg[t][0..B]
+// (seg[t][B] = number of valid keys of the tile).  Staging stays tile-major, so
+// every write is a coalesced 16-byte store and no global counter is needed.
 //
-// Pass 2 (k_bucket): workgroup b gathers segment b of every tile (16-lane groups
-// each read 8-byte words of one segment), counts the relative keys into an LDS
-// histogram of W bins, and stores bins [b*W, min((b+1)*W, U)) of H.  H is written
-// exactly once with plain stores: no zeroing, no global atomics.  Buckets are
-// mapped so that each XCD (blockIdx mod 8) takes a contiguous range of buckets,
+// Pass 2 (k_bucket): workgroup b first sums seg[t][b] over all tiles -- the number
+// of keys in buckets before b, i.e. where bucket b's sorted run starts -- and its
+// own segment sizes.  It then gathers segment b of every tile (each lane owns
+// whole segments, loads them as aligned 16-byte quads and prefetches the next
+// step while counting the current one) into a packed LDS histogram of W bins
+// (two 16-bit fields per word, with the exact crossing accounting of the LDS16
+// ingestion path), and stores bins [b*W, min((b+1)*W, U)) of H: written once,
+// with plain stores, no zeroing and no global atomics.  For the projection
+// (Eq. (2)) each thread takes 64 consecutive bins; a block scan of their sums
+// gives every thread where its stretch of the bucket's run starts, and it
+// appends the fill items (tile-by-chunk pieces of the output, see scan_fill.hpp)
+// that start there.  k_fill then writes the whole output with many workgroups
+// per CU and fully coalesced stores, whatever the skew.  A bucket with more than
+// 2^22 keys is counted in two halves with 32-bit LDS counters (reading its
+// segments twice), which keeps the packed path's event log bounded.  Buckets are
+// mapped so that each XCD (blockIdx mod 8) takes a contiguous range of them,
 // which keeps neighbouring segments and segment-table lines in one L2.
 #pragma once
 
 #include "common.hpp"
 #include "crn_wave.hpp"
 #include "hist_lds.hpp"
+#include "scan_fill.hpp"
 
 namespace ds {
 
-constexpr int PART_LOG2W = 15;
+constexpr int PART_LOG2W = 16;
 constexpr uint32_t PART_W = 1u << PART_LOG2W;
-constexpr int PART_TK = 32768;   // keys per pass-1 tile (segment starts fit in uint16)
-constexpr int PART_NT = 1024;
+constexpr int PART_TK = 8192;    // keys per pass-1 tile (segment starts fit in uint16)
+constexpr int PART_NT = 1024;   // pass-2 workgroup
+constexpr int P1_NT = 512;      // pass-1 workgroup
 constexpr uint32_t PART_BMAX = 8192;
+constexpr uint64_t PART_UMAX = (uint64_t)PART_W * PART_BMAX;  // 2^29
 
-// seg: T rows of `bstride` uint16 (bstride >= B + 1, multiple of 8).
-template <int AGG, bool ALIGNED>
-__global__ __launch_bounds__(PART_NT) void k_partition(const uint32_t* __restrict__ keys, uint64_t n, uint32_t umax,
-                                                       uint32_t B, uint16_t* __restrict__ staging,
-                                                       uint16_t* __restrict__ seg, uint32_t bstride, Ctl* ctl) {
-  constexpr int GPT = PART_TK / 4 / PART_NT;  // key groups of 4 per thread
-  __shared__ uint32_t cnt[PART_BMAX + 1];
+// ---------------------------------------------------------------------------
+// Pass 1
+// ---------------------------------------------------------------------------
+// seg: T rows of `bstride` uint16 (bstride >= B + 1, multiple of 8).  Invalid
+// keys are parked as 0xFFFFFFFF (U <= 2^29 here, so no valid key has that value).
+template <int BMAXT, int AGG, bool ALIGNED>
+__global__ __launch_bounds__(P1_NT) void k_partition(const uint32_t* __restrict__ keys, uint64_t n,
+                                                          uint32_t umax, uint32_t B,
+                                                          uint16_t* __restrict__ staging,
+                                                          uint16_t* __restrict__ seg, uint32_t bstride, Ctl* ctl) {
+  constexpr int GPT = PART_TK / 4 / P1_NT;  // key groups of 4 per thread
+  __shared__ uint32_t cnt[BMAXT + 1];
   __shared__ __align__(16) uint16_t stage[PART_TK];
-  __shared__ uint32_t scan_tmp[PART_NT / WAVE + 1];
+  __shared__ uint32_t scan_tmp[P1_NT / WAVE + 1];
   const uint32_t tid = threadIdx.x;
   const uint64_t tb = (uint64_t)blockIdx.x * PART_TK;
   const uint64_t te = tb + PART_TK < n ? tb + PART_TK : n;
 
-  for (uint32_t i = tid; i <= B; i += PART_NT) cnt[i] = 0;
-  __syncthreads();
+  for (uint32_t i = tid; i <= B; i += P1_NT) cnt[i] = 0;
 
   uint32_t v[GPT][4];
-  uint32_t rk[GPT][4];
-  bool okf[GPT][4];
   bool bad = false;
-  WaveAgg st;
 #pragma unroll
   for (int u = 0; u < GPT; ++u) {
-    const uint32_t c = load_group<ALIGNED>(keys, tb + ((uint64_t)u * PART_NT + tid) * 4, te, v[u]);
+    const uint32_t c = load_group<ALIGNED>(keys, tb + ((uint64_t)u * P1_NT + tid) * 4, te, v[u]);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const bool valid = (uint32_t)i < c;
       const bool ok = valid && v[u][i] <= umax;
       bad |= valid && !ok;
-      okf[u][i] = ok;
-      rk[u][i] = wave_rank<AGG>(cnt, ok ? (v[u][i] >> PART_LOG2W) : 0u, ok, st);
+      if (!ok) v[u][i] = 0xFFFFFFFFu;
+    }
+  }
+  __syncthreads();
+  WaveAgg st;
+#pragma unroll
+  for (int u = 0; u < GPT; ++u) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const bool ok = v[u][i] != 0xFFFFFFFFu;
+      wave_count<AGG>(cnt, ok ? (v[u][i] >> PART_LOG2W) : 0u, ok, st);
     }
   }
   if (__syncthreads_or(bad) && tid == 0) set_status(ctl, ST_RANGE);
 
-  // exclusive scan of the B+1 counters (counter B stays 0, so cnt[B] becomes the
+  // exclusive scan of the B+1 counters (counter B stays 0, so the total is the
   // number of valid keys); each thread owns a run of CPT counters
-  constexpr int CPT = (PART_BMAX + 1 + PART_NT - 1) / PART_NT;
+  constexpr int CPT = (BMAXT + 1 + P1_NT - 1) / P1_NT;
   uint32_t loc[CPT];
   uint32_t sum = 0;
 #pragma unroll
@@ -78,92 +104,398 @@ __global__ __launch_bounds__(PART_NT) void k_partition(const uint32_t* __restric
     sum += loc[j];
   }
   uint32_t total;
-  uint32_t pre = block_exclusive_sum<PART_NT>(sum, scan_tmp, &total);
+  uint32_t pre = block_exclusive_sum<P1_NT>(sum, scan_tmp, &total);
+  uint16_t* srow = seg + (uint64_t)blockIdx.x * bstride;
 #pragma unroll
   for (int j = 0; j < CPT; ++j) {
     const uint32_t i = tid * CPT + j;
-    if (i <= B) cnt[i] = pre;
+    if (i <= B) { cnt[i] = pre; srow[i] = (uint16_t)pre; }
     pre += loc[j];
   }
   __syncthreads();
 
-  // place the relative keys of valid keys in bucket order
+  // place the relative keys at cursors taken from the bucket starts
+  WaveAgg st2;
 #pragma unroll
   for (int u = 0; u < GPT; ++u) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      if (okf[u][i]) {
-        const uint32_t x = v[u][i];
-        stage[cnt[x >> PART_LOG2W] + rk[u][i]] = (uint16_t)(x & (PART_W - 1));
-      }
+      const uint32_t x = v[u][i];
+      const bool ok = x != 0xFFFFFFFFu;
+      const uint32_t pos = wave_rank<AGG>(cnt, ok ? (x >> PART_LOG2W) : 0u, ok, st2);
+      if (ok) stage[pos] = (uint16_t)(x & (PART_W - 1));
     }
   }
   __syncthreads();
 
   // tile slice of staging: the valid keys, bucket-major, as 16-byte stores
-  const uint32_t nvalid = cnt[B];
   uint16_t* dst = staging + tb;
-  const uint32_t n8 = (nvalid + 7) / 8;
-  for (uint32_t i = tid; i < n8; i += PART_NT)
+  const uint32_t n8 = (total + 7) / 8;
+  for (uint32_t i = tid; i < n8; i += P1_NT)
     reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(stage)[i];
-  uint16_t* srow = seg + (uint64_t)blockIdx.x * bstride;
-  for (uint32_t i = tid; i <= B; i += PART_NT) srow[i] = (uint16_t)cnt[i];
 }
 
-// Pass 2.  T tiles; H receives bins [b*W, min((b+1)*W, U)).
-template <int AGG, bool HALIGNED>
+// ---------------------------------------------------------------------------
+// Pass 2 helpers
+// ---------------------------------------------------------------------------
+
+constexpr int BK_SQ = 4;            // 16-byte quads (8 keys each) per lane per gather step
+constexpr uint32_t BK_LRCAP = 512;  // long-run list entries
+constexpr uint64_t BK_PACKMAX = 1ull << 22;  // keys per bucket on the packed path
+constexpr uint32_t BK_WPW = PART_W / 2 + PART_W / 64;  // padded packed words
+
+// padded word index: one spare word per 32 keeps per-thread runs of 32 words on
+// distinct banks
+__device__ __forceinline__ uint32_t pw(uint32_t w) { return w + (w >> 5); }
+
+// LDS state of k_bucket
+struct BucketSmem {
+  uint32_t s[BK_WPW];  // packed counters (or uint32 counters of a half) at padded index
+  uint32_t evflag[PART_W / 32];
+  uint32_t ev[LDS16_EVCAP];
+  uint32_t nev;
+  uint32_t lr_k[BK_LRCAP], lr_n[BK_LRCAP];
+  uint64_t lr_o[BK_LRCAP], lr_c[BK_LRCAP];
+  uint64_t red[PART_NT / WAVE + 1];
+  uint32_t n, item0;
+};
+
+// Gather the segments of bucket b and count their relative keys.  PACKED: into
+// the packed 16-bit fields (all W keys).  Otherwise: 32-bit counters for the
+// keys whose relative value lies in half `half` (x >> 15 == half).
+// Each lane owns whole segments (tiles tid, tid + NT, ...): it loads its segment
+// as aligned 16-byte quads of 8 keys, BK_SQ quads per step, and prefetches the
+// bounds of its next segment while it works on the current one, so the
+// segment-table loads never sit on the critical path.
+template <int AGG, bool PACKED>
+__device__ __forceinline__ void bucket_gather(BucketSmem& S, const uint16_t* __restrict__ staging,
+                                              const uint16_t* __restrict__ seg, uint32_t bstride, uint32_t T,
+                                              uint32_t b, uint32_t half) {
+  Lds16Log L;
+  L.evflag = S.evflag;
+  L.ev = S.ev;
+  L.nev = &S.nev;
+  WaveAgg st;
+  const uint32_t tid = threadIdx.x;
+  const uint4* sq = reinterpret_cast<const uint4*>(staging);
+  uint32_t t = tid;
+  uint32_t nlo = 0, nhi = 0;  // prefetched bounds of tile t
+  if (t < T) { const uint16_t* row = seg + (uint64_t)t * bstride; nlo = row[b]; nhi = row[b + 1]; }
+  uint64_t lo = 0, hi = 0, qn = 0;  // current segment [lo, hi) and its next quad
+  auto open = [&]() {
+    const uint64_t tbase = (uint64_t)t * PART_TK;
+    lo = tbase + nlo;
+    hi = tbase + nhi;
+    qn = lo >> 3;
+    const uint32_t tn = t + PART_NT;
+    if (tn < T) { const uint16_t* row = seg + (uint64_t)tn * bstride; nlo = row[b]; nhi = row[b + 1]; }
+  };
+  auto advance = [&]() {
+    while (t < T && (qn << 3) >= hi) {
+      t += PART_NT;
+      if (t < T) open();
+    }
+  };
+  auto load = [&](uint4* d, bool has) {
+#pragma unroll
+    for (int j = 0; j < BK_SQ; ++j) {
+      d[j] = make_uint4(0, 0, 0, 0);
+      if (has && ((qn + j) << 3) < hi) d[j] = sq[qn + j];
+    }
+  };
+  if (t < T) open();
+  advance();
+  bool has = t < T;
+  uint4 d[BK_SQ];
+  load(d, has);
+  uint64_t clo = lo, chi = hi, cq = qn;  // the segment of the step in flight
+  for (;;) {
+    if (!__any(has)) break;
+    // issue the next step's loads before working on this one
+    qn += BK_SQ;
+    advance();
+    const bool hasn = t < T;
+    uint4 dn[BK_SQ];
+    load(dn, hasn);
+#pragma unroll
+    for (int j = 0; j < BK_SQ; ++j) {
+      const uint32_t wds[4] = {d[j].x, d[j].y, d[j].z, d[j].w};
+      uint32_t kk[8], cc[8], old[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const uint64_t idx = ((cq + j) << 3) + e;
+        const uint32_t x = (wds[e >> 1] >> ((e & 1) << 4)) & 0xFFFFu;
+        bool ok = has && idx >= clo && idx < chi;
+        if (!PACKED) ok = ok && (x >> 15) == half;
+        WaveGroups g;
+        const uint32_t n = wave_merge_count<AGG>(x, ok, st, g);
+        kk[e] = x;
+        cc[e] = n;
+        old[e] = 0;
+        if (PACKED) {
+          if (n) old[e] = atomicAdd(&S.s[pw(x >> 1)], n << ((x & 1u) << 4));
+        } else {
+          if (n) atomicAdd(&S.s[pw(x & 0x7FFFu)], n);
+        }
+      }
+      if (PACKED) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const uint32_t n = cc[e], x = kk[e];
+          const uint32_t field = (old[e] >> ((x & 1u) << 4)) & 0xFFFFu;
+          if (n && field + n >= 0x10000u) {
+            // the same crossing accounting as the LDS16 ingestion path, on the
+            // padded word of bin x
+            if ((x & 1u) == 0) {
+              L.log(x, false);
+              if ((old[e] >> 16) == 0xFFFFu) L.log(x + 1, false);
+              const uint32_t old2 = atomicAdd(&S.s[pw(x >> 1)], 0xFFFF0000u);
+              if ((old2 >> 16) == 0u) L.log(x + 1, true);
+            } else {
+              L.log(x, false);
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < BK_SQ; ++j) d[j] = dn[j];
+    has = hasn;
+    clo = lo;
+    chi = hi;
+    cq = qn;
+  }
+}
+
+// Exact count of relative bin k on the packed path.
+__device__ __forceinline__ uint32_t packed_count(const BucketSmem& S, uint32_t k, uint32_t ne) {
+  const uint32_t word = S.s[pw(k >> 1)];
+  uint32_t c = (word >> ((k & 1u) << 4)) & 0xFFFFu;
+  if (S.evflag[k >> 5] & (1u << (k & 31))) {
+    for (uint32_t e = 0; e < ne; ++e) {
+      const uint32_t x = S.ev[e];
+      if ((x & 0x7FFFFFFFu) == k) c += (x & 0x80000000u) ? (uint32_t)-65536 : 65536u;
+    }
+  }
+  return c;
+}
+
+// Block sum over PART_NT threads (result in every thread).
+__device__ __forceinline__ uint64_t block_sum(BucketSmem& S, uint64_t x) {
+  const uint32_t lane = lane_id(), w = threadIdx.x / WAVE;
+  x = wave_sum(x);
+  __syncthreads();
+  if (lane == 0) S.red[w] = x;
+  __syncthreads();
+  uint64_t a = 0;
+  for (uint32_t i = 0; i < PART_NT / WAVE; ++i) a += S.red[i];
+  return a;
+}
+
+// Append fill items for this thread's bins: the thread owns NB consecutive bins
+// starting at relative bin j0, whose counts come from count(j); o0 is the
+// absolute position where its stretch starts.  The span of the bucket part being
+// emitted is [sp0, sp1); item0 is the index of its first item.
+template <uint32_t NB, typename CountF>
+__device__ __forceinline__ void emit_items(BucketSmem& S, FillItem* __restrict__ items, uint32_t item0, int CL2,
+                                           uint64_t sp0, uint64_t sp1, uint64_t hb, uint32_t j0, uint32_t nb_valid,
+                                           uint64_t o0, uint32_t klast, CountF count) {
+  const uint32_t tid = threadIdx.x;
+  const uint64_t C = 1ull << CL2;
+  const uint64_t cb = sp0 >> CL2;
+  // chunk starts c*C strictly inside the span and inside the run [o, o+h)
+  auto starts = [&](uint64_t o, uint64_t h, uint64_t& lo, uint64_t& cntc) {
+    lo = 0; cntc = 0;
+    if (h > 0) {
+      lo = (o + C - 1) >> CL2;
+      if (lo < cb + 1) lo = cb + 1;
+      const uint64_t hi = (o + h - 1) >> CL2;
+      cntc = hi >= lo ? hi - lo + 1 : 0;
+    }
+  };
+  uint64_t o = o0;
+  bool anylong = false;
+  for (uint32_t j = 0; j < NB; ++j) {
+    const uint32_t i = j0 + j;
+    const uint64_t h = i < nb_valid ? count(i) : 0u;
+    if (h > 0 && o == sp0) {  // the span's first nonzero bin opens item 0
+      FillItem it;
+      it.p0 = sp0; it.p1 = ((cb + 1) << CL2) < sp1 ? ((cb + 1) << CL2) : sp1;
+      it.o = o; it.k = (uint32_t)(hb + i); it.klast = klast;
+      items[item0] = it;
+    }
+    uint64_t lo, cntc;
+    starts(o, h, lo, cntc);
+    if (cntc > 4) {
+      anylong = true;  // written below by the whole block
+    } else {
+      for (uint64_t c = lo; c < lo + cntc; ++c) {
+        FillItem it;
+        it.p0 = c << CL2; it.p1 = ((c + 1) << CL2) < sp1 ? ((c + 1) << CL2) : sp1;
+        it.o = o; it.k = (uint32_t)(hb + i); it.klast = klast;
+        items[item0 + (c - cb)] = it;
+      }
+    }
+    o += h;
+  }
+  // runs that cross more than 4 chunk starts (rare): one bin per thread per
+  // round through the long-run list, all threads writing the items
+  if (!__syncthreads_or(anylong)) return;
+  o = o0;
+  for (uint32_t j = 0; j < NB; ++j) {
+    const uint32_t i = j0 + j;
+    const uint64_t h = i < nb_valid ? count(i) : 0u;
+    uint64_t lo, cntc;
+    starts(o, h, lo, cntc);
+    bool pending = cntc > 4;
+    while (__syncthreads_or(pending)) {
+      if (tid == 0) S.n = 0;
+      __syncthreads();
+      if (pending) {
+        const uint32_t slot = atomicAdd(&S.n, 1u);
+        if (slot < BK_LRCAP) {
+          S.lr_o[slot] = o; S.lr_c[slot] = lo; S.lr_n[slot] = (uint32_t)cntc; S.lr_k[slot] = (uint32_t)(hb + i);
+          pending = false;
+        }
+      }
+      __syncthreads();
+      const uint32_t nl = S.n < BK_LRCAP ? S.n : BK_LRCAP;
+      for (uint32_t e2 = 0; e2 < nl; ++e2) {
+        const uint64_t oo = S.lr_o[e2], cc = S.lr_c[e2], nn = S.lr_n[e2];
+        const uint32_t kk = S.lr_k[e2];
+        for (uint64_t x = tid; x < nn; x += PART_NT) {
+          const uint64_t c = cc + x;
+          FillItem it;
+          it.p0 = c << CL2; it.p1 = ((c + 1) << CL2) < sp1 ? ((c + 1) << CL2) : sp1;
+          it.o = oo; it.k = kk; it.klast = klast;
+          items[item0 + (c - cb)] = it;
+        }
+      }
+      __syncthreads();
+    }
+    o += h;
+  }
+}
+
+// Reserve the items of span [sp0, sp1) (thread 0) and broadcast the first index.
+__device__ __forceinline__ uint32_t reserve_items(BucketSmem& S, Ctl* ctl, uint64_t sp0, uint64_t sp1,
+                                                  uint32_t item_cap, int CL2) {
+  const uint64_t C = 1ull << CL2;
+  const uint64_t nit = sp1 > sp0 ? ((sp1 + C - 1) >> CL2) - (sp0 >> CL2) : 0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t i0 = 0;
+    if (nit) {
+      i0 = atomicAdd(&ctl->nitems, (uint32_t)nit);
+      if ((uint64_t)i0 + nit > item_cap) { set_status(ctl, ST_INTERNAL); i0 = 0xFFFFFFFFu; }
+    }
+    S.item0 = i0;
+  }
+  __syncthreads();
+  return S.item0;
+}
+
+// ---------------------------------------------------------------------------
+// Pass 2
+// ---------------------------------------------------------------------------
+// T tiles; H receives bins [b*W, min((b+1)*W, U)).  FULL also appends the fill
+// items of the bucket's sorted run for k_fill.
+template <int AGG, bool HALIGNED, bool FULL>
 __global__ __launch_bounds__(PART_NT) void k_bucket(const uint16_t* __restrict__ staging,
                                                     const uint16_t* __restrict__ seg, uint32_t bstride,
-                                                    uint32_t T, uint32_t B, uint64_t U, uint32_t* __restrict__ H) {
-  __shared__ __align__(16) uint32_t s[PART_W];
+                                                    uint32_t T, uint32_t B, uint64_t U, uint32_t* __restrict__ H,
+                                                    Ctl* ctl, FillItem* __restrict__ items, uint32_t item_cap,
+                                                    int CL2) {
+  __shared__ __align__(16) BucketSmem S;
   const uint32_t tid = threadIdx.x;
   // XCD-aware bucket order: blocks are dispatched round-robin over 8 XCDs
   uint32_t b = blockIdx.x;
   if ((B & 7u) == 0) b = (blockIdx.x & 7u) * (B >> 3) + (blockIdx.x >> 3);
-
-  for (uint32_t i = tid; i < PART_W; i += PART_NT) s[i] = 0;
-  __syncthreads();
-
-  Lds32Emit emit{s};
-  WaveAgg st;
-  constexpr uint32_t NG = PART_NT / 16;  // 16-lane groups
-  const uint32_t gid = tid >> 4, l16 = tid & 15;
-  uint32_t t = gid;
-  uint64_t q = 0, qlo = 0, qhi = 0;  // uint16 indices into staging
-  auto open_tile = [&](uint32_t tt) {
-    const uint16_t* row = seg + (uint64_t)tt * bstride;
-    const uint64_t base = (uint64_t)tt * PART_TK;
-    qlo = base + row[b];
-    qhi = base + row[b + 1];
-    q = (qlo & ~3ull) + 4ull * l16;
-  };
-  if (t < T) open_tile(t);
-  for (;;) {
-    while (t < T && q >= qhi) {
-      t += NG;
-      if (t < T) open_tile(t);
-    }
-    const bool has = t < T;
-    if (!__any(has)) break;
-    uint2 w = make_uint2(0, 0);
-    if (has) w = *reinterpret_cast<const uint2*>(staging + q);
-    const uint32_t r[4] = {w.x & 0xFFFFu, w.x >> 16, w.y & 0xFFFFu, w.y >> 16};
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const bool ok = has && (q + i >= qlo) && (q + i < qhi);
-      wave_merge<AGG>(r[i], ok, st, emit);
-    }
-    q += 64;
-  }
-  __syncthreads();
-
   const uint64_t hb = (uint64_t)b * PART_W;
   const uint32_t cnt = (uint32_t)(U - hb < PART_W ? U - hb : PART_W);
-  if (HALIGNED && cnt == PART_W) {
-    for (uint32_t i = tid; i < PART_W / 4; i += PART_NT)
-      reinterpret_cast<uint4*>(H + hb)[i] = reinterpret_cast<const uint4*>(s)[i];
-  } else {
-    for (uint32_t i = tid; i < cnt; i += PART_NT) H[hb + i] = s[i];
+  const uint32_t klast = (uint32_t)(hb + cnt - 1);
+
+  // where the bucket's run starts (keys of earlier buckets) and its length
+  uint64_t mb = 0, mt = 0;
+  for (uint32_t tt = tid; tt < T; tt += PART_NT) {
+    const uint16_t* row = seg + (uint64_t)tt * bstride;
+    const uint32_t lo = row[b], hi = row[b + 1];
+    mb += lo;
+    mt += hi - lo;
+  }
+  const uint64_t base = block_sum(S, mb);
+  const uint64_t total = block_sum(S, mt);
+
+  if (total <= BK_PACKMAX) {
+    // ---- packed path: one gather, 16-bit fields + crossing events ----------
+    for (uint32_t i = tid; i < BK_WPW; i += PART_NT) S.s[i] = 0;
+    for (uint32_t i = tid; i < PART_W / 32; i += PART_NT) S.evflag[i] = 0;
+    if (tid == 0) { S.nev = 0; S.n = 0; }
+    __syncthreads();
+    bucket_gather<AGG, true>(S, staging, seg, bstride, T, b, 0);
+    __syncthreads();
+    const uint32_t ne = S.nev < LDS16_EVCAP ? S.nev : LDS16_EVCAP;
+    if (tid == 0 && S.nev > LDS16_EVCAP) set_status(ctl, ST_INTERNAL);  // cannot happen within BK_PACKMAX
+    // H: two bins per packed word
+    for (uint32_t wv = tid; wv < (cnt + 1) / 2; wv += PART_NT) {
+      const uint32_t k = 2 * wv;
+      const uint32_t c0 = packed_count(S, k, ne), c1 = packed_count(S, k + 1, ne);
+      if (HALIGNED && k + 1 < cnt) {
+        *reinterpret_cast<uint2*>(H + hb + k) = make_uint2(c0, c1);
+      } else {
+        H[hb + k] = c0;
+        if (k + 1 < cnt) H[hb + k + 1] = c1;
+      }
+    }
+    if constexpr (!FULL) return;
+    if (total == 0) return;
+
+    // each thread owns 64 consecutive bins; a block scan of their sums tells it
+    // where its stretch of the bucket's run starts, and it appends the fill
+    // items that start in that stretch
+    constexpr uint32_t NB = PART_W / PART_NT;  // 64
+    const uint32_t j0 = tid * NB;
+    uint32_t sum = 0;
+    for (uint32_t j = 0; j < NB; ++j) {
+      const uint32_t i = j0 + j;
+      sum += i < cnt ? packed_count(S, i, ne) : 0u;
+    }
+    uint64_t tot;
+    const uint64_t pre = block_exclusive_sum<PART_NT>((uint64_t)sum, S.red, &tot);
+    auto count = [&](uint32_t i) -> uint32_t { return packed_count(S, i, ne); };
+    const uint32_t item0 = reserve_items(S, ctl, base, base + total, item_cap, CL2);
+    if (item0 == 0xFFFFFFFFu) return;
+    emit_items<NB>(S, items, item0, CL2, base, base + total, hb, j0, cnt, base + pre, klast, count);
+    return;
+  }
+
+  // ---- heavy bucket: two halves of 2^15 bins with 32-bit counters -----------
+  uint64_t hbase = base;  // where the current half's run starts
+  for (uint32_t half = 0; half < 2; ++half) {
+    const uint32_t hb0 = half << 15;
+    if (hb0 >= cnt) break;
+    const uint32_t hcnt = cnt - hb0 < (1u << 15) ? cnt - hb0 : (1u << 15);
+    __syncthreads();
+    for (uint32_t i = tid; i < BK_WPW; i += PART_NT) S.s[i] = 0;
+    if (tid == 0) S.n = 0;
+    __syncthreads();
+    bucket_gather<AGG, false>(S, staging, seg, bstride, T, b, half);
+    __syncthreads();
+    for (uint32_t i = tid; i < hcnt; i += PART_NT) H[hb + hb0 + i] = S.s[pw(i)];
+    if (FULL) {
+      constexpr uint32_t NB = (1u << 15) / PART_NT;  // 32
+      const uint32_t j0 = tid * NB;
+      uint32_t sum = 0;
+      for (uint32_t j = 0; j < NB; ++j) sum += j0 + j < hcnt ? S.s[pw(j0 + j)] : 0u;
+      uint64_t htot;
+      const uint64_t pre = block_exclusive_sum<PART_NT>((uint64_t)sum, S.red, &htot);
+      const uint32_t item0 = reserve_items(S, ctl, hbase, hbase + htot, item_cap, CL2);
+      if (item0 != 0xFFFFFFFFu && htot) {
+        auto count = [&](uint32_t i) -> uint32_t { return S.s[pw(i)]; };
+        emit_items<NB>(S, items, item0, CL2, hbase, hbase + htot, hb + hb0, j0, hcnt, hbase + pre, klast, count);
+      }
+      hbase += htot;
+    }
   }
 }
 

@@ -108,6 +108,7 @@ __global__ __launch_bounds__(NT) void k_scan(const uint32_t* __restrict__ rows, 
     const uint64_t k = base + (uint64_t)j * NT + tid;
     uint32_t a = 0;
     if (k < U) {
+#pragma unroll 8
       for (uint32_t r = 0; r < nrows; ++r) a += rows[(uint64_t)r * row_stride + k];
       if (H_out) H_out[k] = a;
     }
@@ -180,26 +181,32 @@ __global__ __launch_bounds__(NT) void k_scan(const uint32_t* __restrict__ rows, 
   const uint32_t item0 = s_item0;
   const bool emit = nit > 0 && item0 != 0xFFFFFFFFu;
   const uint32_t klast = (uint32_t)((base + TB < U ? base + TB : U) - 1);
-  uint64_t o = sat_add(tpre, texcl);
-#pragma unroll
-  for (int j = 0; j < VPT; ++j) {
-    const uint64_t h = v[j];
-    const uint64_t bin = base + (uint64_t)tid * VPT + j;
-    uint64_t c0 = 0, cnt = 0;
+  // chunk starts c*C strictly inside the span and inside bin's run [o, o+h)
+  auto starts = [&](uint64_t o, uint64_t h, uint64_t& c0, uint64_t& cnt) {
+    c0 = 0; cnt = 0;
     if (emit && h > 0 && o < e0) {
       const uint64_t e = sat_add(o, h) < e0 ? sat_add(o, h) : e0;  // run clipped to the span
-      if (o == s0) {  // the first nonzero bin opens item 0
-        FillItem it;
-        it.p0 = s0; it.p1 = ((cbase + 1) << CL2) < e0 ? ((cbase + 1) << CL2) : e0;
-        it.o = o; it.k = (uint32_t)bin; it.klast = klast;
-        items[item0] = it;
-      }
-      // chunk starts c*C strictly inside the span and inside [o, e)
       uint64_t lo = (o + C - 1) >> CL2;
       if (lo < cbase + 1) lo = cbase + 1;
       const uint64_t hi = (e - 1) >> CL2;
       c0 = lo;
       cnt = hi >= lo ? hi - lo + 1 : 0;
+    }
+  };
+  const uint64_t o_first = sat_add(tpre, texcl);
+  uint64_t o = o_first;
+  uint32_t pending = 0;  // bit j: bin j's run crosses more than 4 chunk starts
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    const uint64_t h = v[j];
+    const uint64_t bin = base + (uint64_t)tid * VPT + j;
+    uint64_t c0, cnt;
+    starts(o, h, c0, cnt);
+    if (emit && h > 0 && o < e0 && o == s0) {  // the first nonzero bin opens item 0
+      FillItem it;
+      it.p0 = s0; it.p1 = ((cbase + 1) << CL2) < e0 ? ((cbase + 1) << CL2) : e0;
+      it.o = o; it.k = (uint32_t)bin; it.klast = klast;
+      items[item0] = it;
     }
     if (cnt > 0 && cnt <= 4) {
       for (uint64_t i = 0; i < cnt; ++i) {
@@ -209,28 +216,39 @@ __global__ __launch_bounds__(NT) void k_scan(const uint32_t* __restrict__ rows, 
         it.o = o; it.k = (uint32_t)bin; it.klast = klast;
         items[item0 + (c - cbase)] = it;
       }
-    } else if (cnt > 4) {
-      const uint32_t slot = atomicAdd(&lr_n, 1u);
-      lr_bin[slot] = (uint32_t)bin; lr_off[slot] = o; lr_c0[slot] = c0; lr_cnt[slot] = cnt;
     }
-    // round j of long runs: all threads write their items
-    __syncthreads();
-    const uint32_t nl = lr_n;
-    for (uint32_t e = 0; e < nl; ++e) {
-      const uint32_t b = lr_bin[e];
-      const uint64_t oo = lr_off[e], cc = lr_c0[e], nn = lr_cnt[e];
-      for (uint64_t i = tid; i < nn; i += NT) {
-        const uint64_t c = cc + i;
-        FillItem it;
-        it.p0 = c << CL2; it.p1 = ((c + 1) << CL2) < e0 ? ((c + 1) << CL2) : e0;
-        it.o = oo; it.k = b; it.klast = klast;
-        items[item0 + (c - cbase)] = it;
-      }
-    }
-    __syncthreads();
-    if (tid == 0) lr_n = 0;
-    __syncthreads();
+    if (cnt > 4) pending |= 1u << j;
     o = sat_add(o, h);
+  }
+  // runs that cross many chunk starts: their items are written by the whole block
+  if (__syncthreads_or(pending != 0)) {
+    o = o_first;
+    for (int j = 0; j < VPT; ++j) {
+      if ((pending >> j) & 1u) {
+        uint64_t c0, cnt;
+        starts(o, v[j], c0, cnt);
+        const uint32_t slot = atomicAdd(&lr_n, 1u);
+        lr_bin[slot] = (uint32_t)(base + (uint64_t)tid * VPT + j);
+        lr_off[slot] = o; lr_c0[slot] = c0; lr_cnt[slot] = cnt;
+      }
+      o = sat_add(o, v[j]);
+      __syncthreads();
+      const uint32_t nl = lr_n;
+      for (uint32_t e = 0; e < nl; ++e) {
+        const uint32_t b = lr_bin[e];
+        const uint64_t oo = lr_off[e], cc = lr_c0[e], nn = lr_cnt[e];
+        for (uint64_t i = tid; i < nn; i += NT) {
+          const uint64_t c = cc + i;
+          FillItem it;
+          it.p0 = c << CL2; it.p1 = ((c + 1) << CL2) < e0 ? ((c + 1) << CL2) : e0;
+          it.o = oo; it.k = b; it.klast = klast;
+          items[item0 + (c - cbase)] = it;
+        }
+      }
+      __syncthreads();
+      if (tid == 0) lr_n = 0;
+      __syncthreads();
+    }
   }
 }
 
@@ -264,18 +282,27 @@ __global__ __launch_bounds__(NT) void k_fill(const uint32_t* __restrict__ H, uin
     uint64_t kb = I.k;
     uint64_t run = I.o;  // start position of bin kb's run (<= p0)
     while (run < p1 && kb <= I.klast) {  // uniform: run and kb are block-wide values
-      const uint64_t k = kb + tid;
-      const uint64_t h = k <= I.klast ? H[k] : 0;
+      const uint64_t k0 = kb + 4ull * tid;
+      uint32_t h[4];
+      uint64_t tsum = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        h[j] = k0 + j <= I.klast ? H[k0 + j] : 0u;
+        tsum += h[j];
+      }
       uint64_t tot;
-      const uint64_t ex = block_exclusive_sum<NT>(h, scan_tmp, &tot);
-      const uint64_t ok = run + ex;
-      if (h > 0 && ok < p1) {
-        const uint32_t pos = ok <= p0 ? lb : (uint32_t)(ok - a0);
-        val[pos] = (uint32_t)k;
-        atomicOr(&flag[pos >> 5], 1u << (pos & 31));
+      uint64_t ok = run + block_exclusive_sum<NT>(tsum, scan_tmp, &tot);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (h[j] > 0 && ok < p1) {
+          const uint32_t pos = ok <= p0 ? lb : (uint32_t)(ok - a0);
+          val[pos] = (uint32_t)(k0 + j);
+          atomicOr(&flag[pos >> 5], 1u << (pos & 31));
+        }
+        ok += h[j];
       }
       run += tot;
-      kb += NT;
+      kb += 4ull * NT;
     }
     __syncthreads();
     // carry the last mark forward.  Segment s = local positions [32s, 32s+32)
