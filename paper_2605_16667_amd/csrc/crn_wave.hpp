@@ -154,4 +154,40 @@ __device__ __forceinline__ uint32_t wave_rank(uint32_t* cnt, uint32_t b, bool ac
   }
 }
 
+// Ranking in two phases, so that the atomics of many slots are in flight at
+// once: wave_rank_issue() merges one slot and issues its atomic, returning the
+// old counter value (valid for lanes that added) plus, for members of a merged
+// group, the lane that added for them and their position in the group;
+// wave_rank_finish() turns that into the lane's rank once the atomics are back.
+struct RankTicket {
+  uint32_t old;   // counter value returned to this lane (if it added)
+  uint32_t src;   // lane whose old value applies to this lane
+  uint32_t off;   // position within the merged group
+  bool grouped;   // wave-uniform: this slot merged a group
+};
+
+template <int AGG>
+__device__ __forceinline__ RankTicket wave_rank_issue(uint32_t* cnt, uint32_t b, bool act, WaveAgg& st) {
+  WaveGroups g;
+  const uint32_t c = wave_merge_count<AGG>(b, act, st, g);
+  RankTicket tk;
+  tk.old = 0;
+  if (c) tk.old = atomicAdd(&cnt[b], c);
+  const uint32_t lane = lane_id();
+  tk.src = lane;
+  tk.off = 0;
+  tk.grouped = (g.m1 | g.m2) != 0;
+  if (tk.grouped) {
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    if ((g.m1 >> lane) & 1ull) { tk.src = g.l1; tk.off = (uint32_t)__popcll(g.m1 & below); }
+    if ((g.m2 >> lane) & 1ull) { tk.src = g.l2; tk.off = (uint32_t)__popcll(g.m2 & below); }
+  }
+  return tk;
+}
+
+__device__ __forceinline__ uint32_t wave_rank_finish(const RankTicket& tk) {
+  if (!tk.grouped) return tk.old;
+  return (uint32_t)__shfl((int)tk.old, (int)tk.src, WAVE) + tk.off;
+}
+
 }  // namespace ds

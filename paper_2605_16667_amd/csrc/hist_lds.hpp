@@ -131,14 +131,24 @@ __global__ __launch_bounds__(NT) void k_hist_lds(const uint32_t* __restrict__ ke
       }
     }
     if constexpr (PACKED) {
-      // crossing checks after every add of the iteration has been issued
+      // crossing checks after every add of the iteration has been issued: a
+      // field crossed iff its old value plus the add exceeds 0xFFFF, so one OR
+      // over the iteration tells whether any did
+      uint32_t anyx = 0;
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const uint32_t c = cc[u][i], k = v[u][i];
-          const uint32_t field = (old[u][i] >> ((k & 1u) << 4)) & 0xFFFFu;
-          if (c && field + c >= 0x10000u) lds16_crossing(s, k, c, old[u][i], evflag, ev, &nev);
+        for (int i = 0; i < 4; ++i) anyx |= __builtin_amdgcn_ubfe(old[u][i], (v[u][i] & 1u) << 4, 16) + cc[u][i];
+      }
+      if (anyx > 0xFFFFu) {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const uint32_t c = cc[u][i], k = v[u][i];
+            const uint32_t field = __builtin_amdgcn_ubfe(old[u][i], (k & 1u) << 4, 16);
+            if (c && field + c >= 0x10000u) lds16_crossing(s, k, c, old[u][i], evflag, ev, &nev);
+          }
         }
       }
     }

@@ -114,16 +114,26 @@ __global__ __launch_bounds__(P1_NT) void k_partition(const uint32_t* __restrict_
   }
   __syncthreads();
 
-  // place the relative keys at cursors taken from the bucket starts
+  // place the relative keys at cursors taken from the bucket starts: all
+  // cursor atomics first, then the stores
   WaveAgg st2;
+  RankTicket tk[GPT][4];
 #pragma unroll
   for (int u = 0; u < GPT; ++u) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const uint32_t x = v[u][i];
       const bool ok = x != 0xFFFFFFFFu;
-      const uint32_t pos = wave_rank<AGG>(cnt, ok ? (x >> PART_LOG2W) : 0u, ok, st2);
-      if (ok) stage[pos] = (uint16_t)(x & (PART_W - 1));
+      tk[u][i] = wave_rank_issue<AGG>(cnt, ok ? (x >> PART_LOG2W) : 0u, ok, st2);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < GPT; ++u) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t x = v[u][i];
+      const uint32_t pos = wave_rank_finish(tk[u][i]);
+      if (x != 0xFFFFFFFFu) stage[pos] = (uint16_t)(x & (PART_W - 1));
     }
   }
   __syncthreads();
@@ -178,29 +188,31 @@ __device__ __forceinline__ void bucket_gather(BucketSmem& S, const uint16_t* __r
   WaveAgg st;
   const uint32_t tid = threadIdx.x;
   const uint4* sq = reinterpret_cast<const uint4*>(staging);
+  // cursor: tile t, segment [s16, e16) as tile-local key indices (< 2^13), next
+  // quad at tile-local key index ql (a multiple of 8); 32-bit arithmetic only
   uint32_t t = tid;
-  uint32_t nlo = 0, nhi = 0;  // prefetched bounds of tile t
-  if (t < T) { const uint16_t* row = seg + (uint64_t)t * bstride; nlo = row[b]; nhi = row[b + 1]; }
-  uint64_t lo = 0, hi = 0, qn = 0;  // current segment [lo, hi) and its next quad
+  uint32_t ns = 0, ne = 0;  // prefetched bounds of tile t
+  if (t < T) { const uint16_t* row = seg + (uint64_t)t * bstride; ns = row[b]; ne = row[b + 1]; }
+  uint32_t s16 = 0, e16 = 0, ql = 0;
   auto open = [&]() {
-    const uint64_t tbase = (uint64_t)t * PART_TK;
-    lo = tbase + nlo;
-    hi = tbase + nhi;
-    qn = lo >> 3;
+    s16 = ns;
+    e16 = ne;
+    ql = ns & ~7u;
     const uint32_t tn = t + PART_NT;
-    if (tn < T) { const uint16_t* row = seg + (uint64_t)tn * bstride; nlo = row[b]; nhi = row[b + 1]; }
+    if (tn < T) { const uint16_t* row = seg + (uint64_t)tn * bstride; ns = row[b]; ne = row[b + 1]; }
   };
   auto advance = [&]() {
-    while (t < T && (qn << 3) >= hi) {
+    while (t < T && ql >= e16) {
       t += PART_NT;
       if (t < T) open();
     }
   };
   auto load = [&](uint4* d, bool has) {
+    const uint64_t q0 = (((uint64_t)t * PART_TK) + ql) >> 3;
 #pragma unroll
     for (int j = 0; j < BK_SQ; ++j) {
       d[j] = make_uint4(0, 0, 0, 0);
-      if (has && ((qn + j) << 3) < hi) d[j] = sq[qn + j];
+      if (has && ql + 8u * j < e16) d[j] = sq[q0 + j];
     }
   };
   if (t < T) open();
@@ -208,24 +220,28 @@ __device__ __forceinline__ void bucket_gather(BucketSmem& S, const uint16_t* __r
   bool has = t < T;
   uint4 d[BK_SQ];
   load(d, has);
-  uint64_t clo = lo, chi = hi, cq = qn;  // the segment of the step in flight
+  uint32_t cs = s16, ce = e16, cq = ql;  // the segment of the step in flight
   for (;;) {
     if (!__any(has)) break;
     // issue the next step's loads before working on this one
-    qn += BK_SQ;
+    ql += 8u * BK_SQ;
     advance();
     const bool hasn = t < T;
     uint4 dn[BK_SQ];
     load(dn, hasn);
 #pragma unroll
     for (int j = 0; j < BK_SQ; ++j) {
+      // valid keys of this quad: tile-local indices [cs, ce) within [q, q + 8)
+      const int32_t q = (int32_t)(cq + 8u * j);
+      const int32_t lob = max((int32_t)cs - q, 0), hib = min((int32_t)ce - q, 8);
+      uint32_t qm = hib > lob ? ((1u << hib) - 1u) & ~((1u << lob) - 1u) : 0u;
+      qm = has ? qm : 0u;
       const uint32_t wds[4] = {d[j].x, d[j].y, d[j].z, d[j].w};
       uint32_t kk[8], cc[8], old[8];
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const uint64_t idx = ((cq + j) << 3) + e;
-        const uint32_t x = (wds[e >> 1] >> ((e & 1) << 4)) & 0xFFFFu;
-        bool ok = has && idx >= clo && idx < chi;
+        const uint32_t x = (e & 1) ? (wds[e >> 1] >> 16) : (wds[e >> 1] & 0xFFFFu);
+        bool ok = (qm >> e) & 1u;
         if (!PACKED) ok = ok && (x >> 15) == half;
         WaveGroups g;
         const uint32_t n = wave_merge_count<AGG>(x, ok, st, g);
@@ -233,26 +249,35 @@ __device__ __forceinline__ void bucket_gather(BucketSmem& S, const uint16_t* __r
         cc[e] = n;
         old[e] = 0;
         if (PACKED) {
-          if (n) old[e] = atomicAdd(&S.s[pw(x >> 1)], n << ((x & 1u) << 4));
+          const uint32_t sh = (x & 1u) << 4;
+          if (n) old[e] = atomicAdd(&S.s[pw(x >> 1)], n << sh);
         } else {
           if (n) atomicAdd(&S.s[pw(x & 0x7FFFu)], n);
         }
       }
       if (PACKED) {
+        // a field crossed a multiple of 65536 iff its old value plus the add
+        // exceeds 0xFFFF; check the quad at once, handle crossings rarely
+        uint32_t anyx = 0;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const uint32_t n = cc[e], x = kk[e];
-          const uint32_t field = (old[e] >> ((x & 1u) << 4)) & 0xFFFFu;
-          if (n && field + n >= 0x10000u) {
-            // the same crossing accounting as the LDS16 ingestion path, on the
-            // padded word of bin x
-            if ((x & 1u) == 0) {
-              L.log(x, false);
-              if ((old[e] >> 16) == 0xFFFFu) L.log(x + 1, false);
-              const uint32_t old2 = atomicAdd(&S.s[pw(x >> 1)], 0xFFFF0000u);
-              if ((old2 >> 16) == 0u) L.log(x + 1, true);
-            } else {
-              L.log(x, false);
+        for (int e = 0; e < 8; ++e)
+          anyx |= __builtin_amdgcn_ubfe(old[e], (kk[e] & 1u) << 4, 16) + cc[e];
+        if (anyx > 0xFFFFu) {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const uint32_t n = cc[e], x = kk[e];
+            const uint32_t field = __builtin_amdgcn_ubfe(old[e], (x & 1u) << 4, 16);
+            if (n && field + n >= 0x10000u) {
+              // the same crossing accounting as the LDS16 ingestion path, on
+              // the padded word of bin x
+              if ((x & 1u) == 0) {
+                L.log(x, false);
+                if ((old[e] >> 16) == 0xFFFFu) L.log(x + 1, false);
+                const uint32_t old2 = atomicAdd(&S.s[pw(x >> 1)], 0xFFFF0000u);
+                if ((old2 >> 16) == 0u) L.log(x + 1, true);
+              } else {
+                L.log(x, false);
+              }
             }
           }
         }
@@ -261,9 +286,9 @@ __device__ __forceinline__ void bucket_gather(BucketSmem& S, const uint16_t* __r
 #pragma unroll
     for (int j = 0; j < BK_SQ; ++j) d[j] = dn[j];
     has = hasn;
-    clo = lo;
-    chi = hi;
-    cq = qn;
+    cs = s16;
+    ce = e16;
+    cq = ql;
   }
 }
 
@@ -293,13 +318,13 @@ __device__ __forceinline__ uint64_t block_sum(BucketSmem& S, uint64_t x) {
 }
 
 // Append fill items for this thread's bins: the thread owns NB consecutive bins
-// starting at relative bin j0, whose counts come from count(j); o0 is the
-// absolute position where its stretch starts.  The span of the bucket part being
+// starting at relative bin j0, whose counts come from count(j) and sum to len;
+// o0 is the absolute position where its stretch starts.  The span of the bucket part being
 // emitted is [sp0, sp1); item0 is the index of its first item.
 template <uint32_t NB, typename CountF>
 __device__ __forceinline__ void emit_items(BucketSmem& S, FillItem* __restrict__ items, uint32_t item0, int CL2,
                                            uint64_t sp0, uint64_t sp1, uint64_t hb, uint32_t j0, uint32_t nb_valid,
-                                           uint64_t o0, uint32_t klast, CountF count) {
+                                           uint64_t o0, uint64_t len, uint32_t klast, CountF count) {
   const uint32_t tid = threadIdx.x;
   const uint64_t C = 1ull << CL2;
   const uint64_t cb = sp0 >> CL2;
@@ -313,30 +338,40 @@ __device__ __forceinline__ void emit_items(BucketSmem& S, FillItem* __restrict__
       cntc = hi >= lo ? hi - lo + 1 : 0;
     }
   };
+  // Only a thread whose stretch [o0, o0 + len) holds the span start or a chunk
+  // start c*C (c > cb) has items to write; the others skip their bins.
   uint64_t o = o0;
   bool anylong = false;
-  for (uint32_t j = 0; j < NB; ++j) {
-    const uint32_t i = j0 + j;
-    const uint64_t h = i < nb_valid ? count(i) : 0u;
-    if (h > 0 && o == sp0) {  // the span's first nonzero bin opens item 0
-      FillItem it;
-      it.p0 = sp0; it.p1 = ((cb + 1) << CL2) < sp1 ? ((cb + 1) << CL2) : sp1;
-      it.o = o; it.k = (uint32_t)(hb + i); it.klast = klast;
-      items[item0] = it;
-    }
+  bool mine = false;
+  {
     uint64_t lo, cntc;
-    starts(o, h, lo, cntc);
-    if (cntc > 4) {
-      anylong = true;  // written below by the whole block
-    } else {
-      for (uint64_t c = lo; c < lo + cntc; ++c) {
+    starts(o0, len, lo, cntc);
+    mine = (len > 0) && (o0 == sp0 || cntc > 0);
+  }
+  if (mine) {
+    for (uint32_t j = 0; j < NB; ++j) {
+      const uint32_t i = j0 + j;
+      const uint64_t h = i < nb_valid ? count(i) : 0u;
+      if (h > 0 && o == sp0) {  // the span's first nonzero bin opens item 0
         FillItem it;
-        it.p0 = c << CL2; it.p1 = ((c + 1) << CL2) < sp1 ? ((c + 1) << CL2) : sp1;
+        it.p0 = sp0; it.p1 = ((cb + 1) << CL2) < sp1 ? ((cb + 1) << CL2) : sp1;
         it.o = o; it.k = (uint32_t)(hb + i); it.klast = klast;
-        items[item0 + (c - cb)] = it;
+        items[item0] = it;
       }
+      uint64_t lo, cntc;
+      starts(o, h, lo, cntc);
+      if (cntc > 4) {
+        anylong = true;  // written below by the whole block
+      } else {
+        for (uint64_t c = lo; c < lo + cntc; ++c) {
+          FillItem it;
+          it.p0 = c << CL2; it.p1 = ((c + 1) << CL2) < sp1 ? ((c + 1) << CL2) : sp1;
+          it.o = o; it.k = (uint32_t)(hb + i); it.klast = klast;
+          items[item0 + (c - cb)] = it;
+        }
+      }
+      o += h;
     }
-    o += h;
   }
   // runs that cross more than 4 chunk starts (rare): one bin per thread per
   // round through the long-run list, all threads writing the items
@@ -344,7 +379,7 @@ __device__ __forceinline__ void emit_items(BucketSmem& S, FillItem* __restrict__
   o = o0;
   for (uint32_t j = 0; j < NB; ++j) {
     const uint32_t i = j0 + j;
-    const uint64_t h = i < nb_valid ? count(i) : 0u;
+    const uint64_t h = (anylong && i < nb_valid) ? count(i) : 0u;
     uint64_t lo, cntc;
     starts(o, h, lo, cntc);
     bool pending = cntc > 4;
@@ -436,10 +471,16 @@ __global__ __launch_bounds__(PART_NT) void k_bucket(const uint16_t* __restrict__
     __syncthreads();
     const uint32_t ne = S.nev < LDS16_EVCAP ? S.nev : LDS16_EVCAP;
     if (tid == 0 && S.nev > LDS16_EVCAP) set_status(ctl, ST_INTERNAL);  // cannot happen within BK_PACKMAX
-    // H: two bins per packed word
+    // H: two bins per packed word; bins with logged crossings (flag bit set)
+    // take the slow exact count
     for (uint32_t wv = tid; wv < (cnt + 1) / 2; wv += PART_NT) {
       const uint32_t k = 2 * wv;
-      const uint32_t c0 = packed_count(S, k, ne), c1 = packed_count(S, k + 1, ne);
+      const uint32_t word = S.s[pw(wv)];
+      uint32_t c0 = word & 0xFFFFu, c1 = word >> 16;
+      if ((S.evflag[k >> 5] >> (k & 31)) & 3u) {
+        c0 = packed_count(S, k, ne);
+        c1 = packed_count(S, k + 1, ne);
+      }
       if (HALIGNED && k + 1 < cnt) {
         *reinterpret_cast<uint2*>(H + hb + k) = make_uint2(c0, c1);
       } else {
@@ -456,16 +497,27 @@ __global__ __launch_bounds__(PART_NT) void k_bucket(const uint16_t* __restrict__
     constexpr uint32_t NB = PART_W / PART_NT;  // 64
     const uint32_t j0 = tid * NB;
     uint32_t sum = 0;
-    for (uint32_t j = 0; j < NB; ++j) {
-      const uint32_t i = j0 + j;
-      sum += i < cnt ? packed_count(S, i, ne) : 0u;
+    // whole words when none of the thread's 64 bins logged a crossing; bins at
+    // or beyond cnt are never counted (keys there are out of range), so their
+    // fields are zero
+    if ((S.evflag[j0 >> 5] | S.evflag[(j0 >> 5) + 1]) == 0u) {
+#pragma unroll 8
+      for (uint32_t w = 0; w < NB / 2; ++w) {
+        const uint32_t word = S.s[pw((j0 >> 1) + w)];
+        sum += (word & 0xFFFFu) + (word >> 16);
+      }
+    } else {
+      for (uint32_t j = 0; j < NB; ++j) {
+        const uint32_t i = j0 + j;
+        sum += i < cnt ? packed_count(S, i, ne) : 0u;
+      }
     }
     uint64_t tot;
     const uint64_t pre = block_exclusive_sum<PART_NT>((uint64_t)sum, S.red, &tot);
     auto count = [&](uint32_t i) -> uint32_t { return packed_count(S, i, ne); };
     const uint32_t item0 = reserve_items(S, ctl, base, base + total, item_cap, CL2);
     if (item0 == 0xFFFFFFFFu) return;
-    emit_items<NB>(S, items, item0, CL2, base, base + total, hb, j0, cnt, base + pre, klast, count);
+    emit_items<NB>(S, items, item0, CL2, base, base + total, hb, j0, cnt, base + pre, sum, klast, count);
     return;
   }
 
@@ -492,7 +544,7 @@ __global__ __launch_bounds__(PART_NT) void k_bucket(const uint16_t* __restrict__
       const uint32_t item0 = reserve_items(S, ctl, hbase, hbase + htot, item_cap, CL2);
       if (item0 != 0xFFFFFFFFu && htot) {
         auto count = [&](uint32_t i) -> uint32_t { return S.s[pw(i)]; };
-        emit_items<NB>(S, items, item0, CL2, hbase, hbase + htot, hb + hb0, j0, hcnt, hbase + pre, klast, count);
+        emit_items<NB>(S, items, item0, CL2, hbase, hbase + htot, hb + hb0, j0, hcnt, hbase + pre, sum, klast, count);
       }
       hbase += htot;
     }

@@ -262,12 +262,18 @@ __global__ __launch_bounds__(NT) void k_fill(const uint32_t* __restrict__ H, uin
                                              uint32_t item_cap) {
   constexpr uint32_t C = 1u << CL2;
   static_assert(C == 32 * NT, "one 32-bit flag word per thread");
-  __shared__ __align__(16) uint32_t val[C];
+  // val[0, C): the key marked at each run start; val[C + s]: the key carried
+  // into segment s (the last mark before it)
+  __shared__ __align__(16) uint32_t val[C + NT];
   __shared__ uint32_t flag[NT];
   __shared__ uint64_t scan_tmp[NT / WAVE + 1];
   __shared__ int32_t last_idx[NT / WAVE];
-  __shared__ uint32_t carry[NT];
   const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / WAVE;
+  // output quads q = tid + k*NT all sit at the same offset b0 = 4 (q mod 8)
+  // inside their 32-position segment: the masks of positions <= b0 + e are fixed
+  const uint32_t b0 = (tid & 7u) * 4u;
+  const uint32_t mk0 = 0xFFFFFFFFu >> (31u - b0), mk1 = 0xFFFFFFFFu >> (30u - b0);
+  const uint32_t mk2 = 0xFFFFFFFFu >> (29u - b0), mk3 = 0xFFFFFFFFu >> (28u - b0);
   // a failed invariant (reported as ST_INTERNAL) leaves items unwritten: fill nothing
   const uint32_t nitems = (ctl->status & ST_INTERNAL) ? 0u : (ctl->nitems < item_cap ? ctl->nitems : item_cap);
 
@@ -306,7 +312,7 @@ __global__ __launch_bounds__(NT) void k_fill(const uint32_t* __restrict__ H, uin
     }
     __syncthreads();
     // carry the last mark forward.  Segment s = local positions [32s, 32s+32)
-    // with flag word flag[s]; carry[s] = key of the last mark before segment s.
+    // with flag word flag[s]; val[C + s] = key of the last mark before segment s.
     // Segment 0 always holds the item's first mark (at lb <= 3).
     const uint32_t f = flag[tid];
     int32_t inc = f ? (int32_t)tid : -1;
@@ -322,26 +328,34 @@ __global__ __launch_bounds__(NT) void k_fill(const uint32_t* __restrict__ H, uin
     for (uint32_t q = 0; q < w; ++q) ex_idx = last_idx[q] > ex_idx ? last_idx[q] : ex_idx;
     uint32_t cin = 0;
     if (ex_idx >= 0) cin = val[ex_idx * 32 + (31 - __clz(flag[ex_idx]))];
-    carry[tid] = cin;
+    val[C + tid] = cin;
     __syncthreads();
-    // every output quad resolves its keys from its segment's flag word
+    // every output quad resolves its keys from its segment's flag word: the
+    // key at position p is the last mark at or before p in the segment, else
+    // the segment's carried key
     const uint32_t nq = (le + 3) >> 2;
     for (uint32_t q = tid; q < nq; q += NT) {
-      const uint32_t sg = q >> 3, b0 = (q & 7) * 4;
-      const uint32_t fw = flag[sg], ci = carry[sg];
-      uint32_t r[4];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const uint32_t mm = fw & (0xFFFFFFFFu >> (31 - (b0 + e)));
-        r[e] = mm ? val[sg * 32 + (31 - __clz(mm))] : ci;
+      const uint32_t sg = q >> 3;
+      const uint32_t fw = flag[sg];
+      uint32_t r0, r1, r2, r3;
+      if (fw == 0) {
+        r0 = r1 = r2 = r3 = val[C + sg];
+      } else {
+        const uint32_t base = sg * 32u + 31u;
+        const uint32_t m0 = fw & mk0, m1 = fw & mk1, m2 = fw & mk2, m3 = fw & mk3;
+        r0 = val[m0 ? base - __clz(m0) : C + sg];
+        r1 = val[m1 ? base - __clz(m1) : C + sg];
+        r2 = val[m2 ? base - __clz(m2) : C + sg];
+        r3 = val[m3 ? base - __clz(m3) : C + sg];
       }
       const uint32_t i0 = q << 2;
       if (OALIGNED && i0 >= lb && i0 + 4 <= le) {
-        *reinterpret_cast<uint4*>(out + a0 + i0) = make_uint4(r[0], r[1], r[2], r[3]);
+        *reinterpret_cast<uint4*>(out + a0 + i0) = make_uint4(r0, r1, r2, r3);
       } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (i0 + e >= lb && i0 + e < le) out[a0 + i0 + e] = r[e];
+        if (i0 >= lb && i0 < le) out[a0 + i0] = r0;
+        if (i0 + 1 >= lb && i0 + 1 < le) out[a0 + i0 + 1] = r1;
+        if (i0 + 2 >= lb && i0 + 2 < le) out[a0 + i0 + 2] = r2;
+        if (i0 + 3 >= lb && i0 + 3 < le) out[a0 + i0 + 3] = r3;
       }
     }
     __syncthreads();
