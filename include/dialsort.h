@@ -91,15 +91,108 @@ dialsort_status dialsort_reconstruct(const uint32_t *H, uint64_t U, uint32_t *ou
 dialsort_status dialsort_sort(const uint32_t *keys, uint64_t n, uint64_t U, uint32_t *H,
                               uint32_t *out, void *ws, size_t ws_bytes, hipStream_t stream);
 
-/* Workspace for dialsort_sort_batched over these descriptors. */
+/* ---- Batches of independent arrays ------------------------------------------
+ *
+ * A batch is a host array of `count` descriptors, each an independent
+ * dialsort_sort problem with its own n, U, H and output.  Every array's H and
+ * output equal what dialsort_sort gives for it alone (the batch shares no
+ * counters between arrays).  The first device-detected error of any array is
+ * reported by dialsort_status_sync() on the batch workspace, after which the
+ * contents of every H and output of the batch are unspecified.  Batching is not
+ * part of the paper, which sorts one array; it applies the method of Sec. 3.3
+ * to many arrays at once.
+ *
+ * The fused form runs the whole batch as ONE persistent kernel launch (plus a
+ * small launch that clears its counters) over a table of work units: every
+ * array's ingestion (Eq. (1)), then its counting and scan, then its projection
+ * (Eq. (2)), with per-array completion counters ordering the phases.  It takes
+ * arrays with U <= 1024 * 2^log2_width whose keys, H and output are 16-byte
+ * aligned; dialsort_batch_prepare() rejects any other array with EINVAL, and
+ * dialsort_sort_batched() then falls back to the per-array launch sequences of
+ * dialsort_sort_each(). */
+
+/* Tuning parameters of the fused launch. */
+typedef struct dialsort_batch_config {
+    uint32_t block;       /* threads per workgroup: 512 or 1024 */
+    uint32_t log2_width;  /* U-partition width W = 2^log2_width bins, 14..16: an
+                             array with U <= W is counted in LDS sub-histograms,
+                             a larger one through the U-range-partitioned path
+                             with buckets of W bins */
+    uint64_t chunk_keys;  /* keys per private LDS sub-histogram, a power of two
+                             in [2^16, 2^22]: an array with U <= W gets
+                             ceil(n / chunk_keys) private copies (privatization
+                             depth), summed before its scan */
+} dialsort_batch_config;
+
+/* A prepared batch: plain data, owned by the caller, filled by
+ * dialsort_batch_prepare().  It refers to the workspace and to the device
+ * buffers named by the descriptors, which must stay allocated while the plan
+ * is launched. */
+typedef struct dialsort_batch_plan {
+    dialsort_batch_config config;
+    uint32_t count;         /* arrays */
+    uint32_t units;         /* work units of one launch */
+    uint32_t grid;          /* persistent workgroups */
+    uint32_t reserved;
+    uint64_t units_offset;  /* where the unit table sits in the workspace */
+    void *ws;
+    size_t ws_bytes;
+} dialsort_batch_plan;
+
+/* Workspace for any of the batched calls over these descriptors (every
+ * configuration and the per-array form); 0 if some U is 0 or above 2^32. */
 size_t dialsort_batched_workspace_bytes(const dialsort_desc *descs, uint32_t count);
 
-/* dialsort_sort on every descriptor (host array of count entries) as one
- * persistent device launch.  Each array's H and out equal what dialsort_sort
- * gives for it alone.  The first device-detected error of any array is reported
- * by dialsort_status_sync().  descs is read during the call only. */
+/* Plans the fused launch of a batch with `config` (NULL: the configuration
+ * that dialsort_batch_autotune() found for a batch of these sizes on this
+ * device, else the built-in default) and copies its tables into ws.  This call
+ * synchronises `stream` (the tables are uploaded from host memory).  descs is
+ * read during the call only.  Errors: EINVAL (bad descriptor, array outside
+ * the fused form, bad config), EWORKSPACE, EHIP. */
+dialsort_status dialsort_batch_prepare(const dialsort_desc *descs, uint32_t count,
+                                       const dialsort_batch_config *config, void *ws,
+                                       size_t ws_bytes, hipStream_t stream,
+                                       dialsort_batch_plan *plan);
+
+/* Enqueues the prepared batch on `stream`: two kernel launches, no host
+ * synchronisation, no allocation and no copy, so the call may be captured into
+ * a HIP graph (hipStreamBeginCapture) and replayed; each launch recomputes
+ * every H and output from the keys.  One plan (one workspace) must not be
+ * launched twice concurrently. */
+dialsort_status dialsort_batch_launch(const dialsort_batch_plan *plan, hipStream_t stream);
+
+/* Prepare + launch in one call (synchronises `stream` for the table upload),
+ * falling back to dialsort_sort_each() when some array is outside the fused
+ * form. */
 dialsort_status dialsort_sort_batched(const dialsort_desc *descs, uint32_t count, void *ws,
                                       size_t ws_bytes, hipStream_t stream);
+
+/* The plain form: dialsort_sort's own launch sequence for every array in turn,
+ * stream-ordered, in one shared sub-workspace (about four launches per array). */
+dialsort_status dialsort_sort_each(const dialsort_desc *descs, uint32_t count, void *ws,
+                                   size_t ws_bytes, hipStream_t stream);
+
+/* Times every candidate configuration (block 512/1024 x log2_width 14/15/16 x
+ * chunk_keys 2^18/2^20/2^22, those that take every array) on this batch --
+ * each candidate runs the whole batch three times, so every H and output is
+ * written -- stores the fastest in *best and remembers it for batches of the
+ * same sizes on this device (the library's only state).  Synchronises
+ * `stream`.  ws as for dialsort_batched_workspace_bytes(). */
+dialsort_status dialsort_batch_autotune(const dialsort_desc *descs, uint32_t count, void *ws,
+                                        size_t ws_bytes, hipStream_t stream,
+                                        dialsort_batch_config *best);
+
+/* The configuration dialsort_batch_prepare() would use for config == NULL. */
+dialsort_status dialsort_batch_default_config(const dialsort_desc *descs, uint32_t count,
+                                              dialsort_batch_config *config);
+
+/* After a launch of `plan` has been enqueued: waits for `stream` and stores,
+ * for the first `count` arrays, the time in ms from the start of the launch's
+ * first work unit to the end of the array's last one (array_ms[i]), and in
+ * *launch_ms (if not NULL) the time to the end of the last unit of the whole
+ * launch.  Read from the device wall clock. */
+dialsort_status dialsort_batch_times(const dialsort_batch_plan *plan, hipStream_t stream,
+                                     double *array_ms, uint32_t count, double *launch_ms);
 
 /* Waits for `stream` and returns the device-detected status of the last call
  * that used ws (DIALSORT_OK, DIALSORT_ERANGE or DIALSORT_EOVERFLOW). */

@@ -37,6 +37,16 @@ class dialsort_desc(ctypes.Structure):
                 ("H", ctypes.c_void_p), ("out", ctypes.c_void_p)]
 
 
+class dialsort_batch_config(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_uint32), ("log2_width", ctypes.c_uint32), ("chunk_keys", ctypes.c_uint64)]
+
+
+class dialsort_batch_plan(ctypes.Structure):
+    _fields_ = [("config", dialsort_batch_config), ("count", ctypes.c_uint32), ("units", ctypes.c_uint32),
+                ("grid", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("units_offset", ctypes.c_uint64),
+                ("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t)]
+
+
 def _load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2605_16667_amd.build.build()")
@@ -49,6 +59,17 @@ def _load() -> ctypes.CDLL:
         "dialsort_sort": (st, [p, u64, u64, p, p, p, sz, p]),
         "dialsort_batched_workspace_bytes": (sz, [ctypes.POINTER(dialsort_desc), ctypes.c_uint32]),
         "dialsort_sort_batched": (st, [ctypes.POINTER(dialsort_desc), ctypes.c_uint32, p, sz, p]),
+        "dialsort_sort_each": (st, [ctypes.POINTER(dialsort_desc), ctypes.c_uint32, p, sz, p]),
+        "dialsort_batch_prepare": (st, [ctypes.POINTER(dialsort_desc), ctypes.c_uint32,
+                                        ctypes.POINTER(dialsort_batch_config), p, sz, p,
+                                        ctypes.POINTER(dialsort_batch_plan)]),
+        "dialsort_batch_launch": (st, [ctypes.POINTER(dialsort_batch_plan), p]),
+        "dialsort_batch_autotune": (st, [ctypes.POINTER(dialsort_desc), ctypes.c_uint32, p, sz, p,
+                                         ctypes.POINTER(dialsort_batch_config)]),
+        "dialsort_batch_default_config": (st, [ctypes.POINTER(dialsort_desc), ctypes.c_uint32,
+                                               ctypes.POINTER(dialsort_batch_config)]),
+        "dialsort_batch_times": (st, [ctypes.POINTER(dialsort_batch_plan), p, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.c_uint32, ctypes.POINTER(ctypes.c_double)]),
         "dialsort_status_sync": (st, [p, p]),
         "dialsort_result_total": (st, [p, p, ctypes.POINTER(u64)]),
         "dialsort_strerror": (ctypes.c_char_p, [st]),
@@ -64,7 +85,9 @@ def _load() -> ctypes.CDLL:
 
 _lib = _load()
 EXPORTED = ("dialsort_workspace_bytes", "dialsort_histogram", "dialsort_reconstruct", "dialsort_sort",
-            "dialsort_batched_workspace_bytes", "dialsort_sort_batched", "dialsort_status_sync",
+            "dialsort_batched_workspace_bytes", "dialsort_sort_batched", "dialsort_sort_each",
+            "dialsort_batch_prepare", "dialsort_batch_launch", "dialsort_batch_autotune",
+            "dialsort_batch_default_config", "dialsort_batch_times", "dialsort_status_sync",
             "dialsort_result_total", "dialsort_strerror", "dialsort_last_hip_error",
             "dialsort_set_launch_events", "dialsort_launch_name")
 
@@ -141,6 +164,47 @@ def dialsort_batched_workspace_bytes(descs, count: int) -> int:
 
 def dialsort_sort_batched(descs, count: int, ws: torch.Tensor, stream=None) -> int:
     return _lib.dialsort_sort_batched(descs, count, _ptr(ws), ws.numel(), _stream(stream))
+
+
+def dialsort_sort_each(descs, count: int, ws: torch.Tensor, stream=None) -> int:
+    return _lib.dialsort_sort_each(descs, count, _ptr(ws), ws.numel(), _stream(stream))
+
+
+def batch_config(block: int, log2_width: int, chunk_keys: int) -> dialsort_batch_config:
+    return dialsort_batch_config(block, log2_width, chunk_keys)
+
+
+def dialsort_batch_prepare(descs, count: int, config: Optional[dialsort_batch_config], ws: torch.Tensor,
+                           stream=None) -> Tuple[int, dialsort_batch_plan]:
+    plan = dialsort_batch_plan()
+    cfg = ctypes.byref(config) if config is not None else None
+    st = _lib.dialsort_batch_prepare(descs, count, cfg, _ptr(ws), ws.numel(), _stream(stream), ctypes.byref(plan))
+    return st, plan
+
+
+def dialsort_batch_launch(plan: dialsort_batch_plan, stream=None) -> int:
+    return _lib.dialsort_batch_launch(ctypes.byref(plan), _stream(stream))
+
+
+def dialsort_batch_autotune(descs, count: int, ws: torch.Tensor, stream=None) -> Tuple[int, dialsort_batch_config]:
+    best = dialsort_batch_config()
+    st = _lib.dialsort_batch_autotune(descs, count, _ptr(ws), ws.numel(), _stream(stream), ctypes.byref(best))
+    return st, best
+
+
+def dialsort_batch_default_config(descs, count: int) -> Tuple[int, dialsort_batch_config]:
+    cfg = dialsort_batch_config()
+    st = _lib.dialsort_batch_default_config(descs, count, ctypes.byref(cfg))
+    return st, cfg
+
+
+def dialsort_batch_times(plan: dialsort_batch_plan, count: int, stream=None):
+    """(status, per-array completion times in ms, whole-launch time in ms) of the
+    last launch of `plan`."""
+    arr = (ctypes.c_double * max(count, 1))()
+    tot = ctypes.c_double(0.0)
+    st = _lib.dialsort_batch_times(ctypes.byref(plan), _stream(stream), arr, count, ctypes.byref(tot))
+    return st, list(arr[:count]), tot.value
 
 
 def dialsort_status_sync(ws: torch.Tensor, stream=None) -> int:

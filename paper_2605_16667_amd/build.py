@@ -7,7 +7,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "csrc", "dialsort.hip")
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("dialsort.hip", "batch.hip")]
 LIB = os.path.join(HERE, "libdialsort.so")
 
 HIPCC_FLAGS = [
@@ -20,7 +20,7 @@ HIPCC_FLAGS = [
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, "-o", tmp, SRC]
+    cmd = [hipcc, *HIPCC_FLAGS, "-o", tmp, *SRCS]
     res = subprocess.run(cmd, capture_output=True, text=True)
     noise = "is not a recognized feature for this target"
     err = "\n".join(l for l in res.stderr.splitlines() if noise not in l)

@@ -17,22 +17,24 @@
 
 #include "../../include/dialsort.h"
 #include "common.hpp"
+#include "host_common.hpp"
 #include "hist_lds.hpp"
 #include "partition.hpp"
 #include "scan_fill.hpp"
 
 using namespace ds;
+using namespace dsh;
+
+namespace dsh {
+thread_local int g_last_hip_error = 0;
+thread_local LaunchLog g_log;
+}  // namespace dsh
 
 namespace {
-
-thread_local int g_last_hip_error = 0;
 
 constexpr int FILL_NT = 256;
 constexpr int FILL_CL2 = 13;  // chunk of 8192 positions
 constexpr int SCAN_NT = 256;
-constexpr uint64_t U_MAX = 1ull << 32;
-constexpr uint64_t N_MAX = 0xFFFFFFFFull;
-constexpr size_t ALIGN = 256;
 
 enum Kind { K_EMPTY, K_LDS32S, K_LDS32, K_LDS16, K_PART, K_GLOBAL, K_NONE };
 
@@ -50,9 +52,6 @@ struct Layout {
   uint64_t item_cap = 0;
   size_t off_tile = 0, off_items = 0, off_rows = 0, off_stage = 0, off_seg = 0, bytes = 0;
 };
-
-inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-inline uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 
 // Choose the number of LDS workgroups: enough to stream the keys at full
 // bandwidth, few enough that the partial rows stay small next to the keys.
@@ -109,8 +108,10 @@ Layout plan(uint64_t n, uint64_t U, int mode) {
   L.scan_tiles = L.kind == K_PART ? 0 : cdiv(U, (uint64_t)SCAN_NT * L.scan_vpt);
   if (L.scan) {
     L.off_tile = off; off = align_up(off + L.scan_tiles * 8, ALIGN);
-    // at most one item per scan tile (or heavy bucket) plus one per chunk start
-    L.item_cap = (L.kind == K_PART ? L.B : L.scan_tiles) + cdiv(L.limit, 1ull << FILL_CL2) + 2;
+    // one item per chunk of output positions, plus one per span boundary that
+    // splits a chunk: spans are the scan tiles, or the buckets of the
+    // partitioned path (two spans for a bucket counted in two halves)
+    L.item_cap = (L.kind == K_PART ? 2ull * L.B : L.scan_tiles) + cdiv(L.limit, 1ull << FILL_CL2) + 2;
     L.off_items = off; off = align_up(off + L.item_cap * sizeof(FillItem), ALIGN);
   }
   if (L.rows_in_ws) {
@@ -123,56 +124,6 @@ Layout plan(uint64_t n, uint64_t U, int mode) {
   L.bytes = off + ALIGN;  // slack for aligning the caller's pointer
   return L;
 }
-
-inline bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
-inline bool aligned4(const void* p) { return ((uintptr_t)p & 3) == 0; }
-
-inline bool overlap(const void* a, size_t abytes, const void* b, size_t bbytes) {
-  if (!abytes || !bbytes) return false;
-  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
-  return x < y + bbytes && y < x + abytes;
-}
-
-inline char* ws_base(void* ws) { return (char*)align_up((uintptr_t)ws, ALIGN); }
-
-// Measurement hook (dialsort_set_launch_events): per host thread, an optional
-// caller-owned event array; events[i] is recorded on the launch stream just
-// before launch i of the current call, events[count] after its last launch.
-struct LaunchLog {
-  hipEvent_t* ev = nullptr;
-  uint32_t cap = 0;
-  uint32_t* count = nullptr;
-  uint32_t n = 0;
-  const char* names[64];
-};
-thread_local LaunchLog g_log;
-
-inline void log_launch(const char* name, hipStream_t s) {
-  if (g_log.ev && g_log.n + 1 < g_log.cap) (void)hipEventRecord(g_log.ev[g_log.n], s);
-  if (g_log.n < 64) g_log.names[g_log.n] = name;
-  ++g_log.n;
-}
-
-// Opens a public call: resets the launch log; on close records the end event.
-struct CallScope {
-  hipStream_t s;
-  explicit CallScope(hipStream_t st) : s(st) { g_log.n = 0; }
-  ~CallScope() {
-    if (g_log.ev && g_log.n < g_log.cap) (void)hipEventRecord(g_log.ev[g_log.n], s);
-    if (g_log.count) *g_log.count = g_log.n;
-  }
-};
-
-#define DS_LAUNCH(kernel, grid, block, stream, ...)                      \
-  do {                                                                   \
-    log_launch(#kernel, stream);                                         \
-    hipLaunchKernelGGL(kernel, grid, block, 0, stream, __VA_ARGS__);     \
-    hipError_t e_ = hipGetLastError();                                   \
-    if (e_ != hipSuccess) {                                              \
-      g_last_hip_error = (int)e_;                                        \
-      return DIALSORT_EHIP;                                              \
-    }                                                                    \
-  } while (0)
 
 // k_init: clear the control block, the look-back flags, and optionally H.
 __global__ void k_init(Ctl* ctl, uint64_t* tiles, uint64_t ntiles, uint32_t* H, uint64_t nH) {
@@ -284,12 +235,6 @@ dialsort_status launch_fill(const uint32_t* H, uint32_t* out, char* base, const 
   return DIALSORT_OK;
 }
 
-#define DS_TRY(x)                          \
-  do {                                     \
-    dialsort_status st_ = (x);             \
-    if (st_ != DIALSORT_OK) return st_;    \
-  } while (0)
-
 dialsort_status check_common(uint64_t U, const void* ws, size_t ws_bytes, size_t need) {
   if (U == 0 || U > U_MAX) return DIALSORT_EINVAL;
   if (!ws || ws_bytes < need) return DIALSORT_EWORKSPACE;
@@ -321,6 +266,10 @@ __global__ void k_or_status(Ctl* dst, const Ctl* src) {
   if (threadIdx.x == 0 && src->status) atomicOr(&dst->status, src->status);
 }
 
+}  // namespace
+
+namespace dsh {
+
 dialsort_status check_desc(const dialsort_desc& d) {
   if (d.U == 0 || d.U > U_MAX || !d.H || (d.n && (!d.keys || !d.out))) return DIALSORT_EINVAL;
   if (!aligned4(d.keys) || !aligned4(d.H) || !aligned4(d.out)) return DIALSORT_EINVAL;
@@ -330,9 +279,7 @@ dialsort_status check_desc(const dialsort_desc& d) {
   return DIALSORT_OK;
 }
 
-// Batched form, stream-ordered: every array runs its own launch sequence in a
-// shared sub-workspace, and its device status is folded into the batch status.
-size_t batch_workspace_bytes(const dialsort_desc* d, uint32_t count) {
+size_t loop_workspace_bytes(const dialsort_desc* d, uint32_t count) {
   size_t mx = 0;
   for (uint32_t i = 0; i < count; ++i) {
     if (d[i].U == 0 || d[i].U > U_MAX) return 0;
@@ -341,10 +288,10 @@ size_t batch_workspace_bytes(const dialsort_desc* d, uint32_t count) {
   return 2 * ALIGN + mx;
 }
 
-dialsort_status batch_run(const dialsort_desc* d, uint32_t count, void* ws, size_t ws_bytes, hipStream_t s) {
+dialsort_status loop_run(const dialsort_desc* d, uint32_t count, void* ws, size_t ws_bytes, hipStream_t s) {
   if (count && !d) return DIALSORT_EINVAL;
   for (uint32_t i = 0; i < count; ++i) DS_TRY(check_desc(d[i]));
-  if (!ws || ws_bytes < batch_workspace_bytes(d, count)) return DIALSORT_EWORKSPACE;
+  if (!ws || ws_bytes < loop_workspace_bytes(d, count)) return DIALSORT_EWORKSPACE;
   char* base = ws_base(ws);
   Layout L0;
   L0.scan = false;
@@ -357,7 +304,7 @@ dialsort_status batch_run(const dialsort_desc* d, uint32_t count, void* ws, size
   return DIALSORT_OK;
 }
 
-}  // namespace
+}  // namespace dsh
 
 extern "C" {
 
@@ -403,16 +350,6 @@ dialsort_status dialsort_reconstruct(const uint32_t* H, uint64_t U, uint32_t* ou
   DS_TRY(launch_scan(H, 1, 0, nullptr, U, base, L, true, 1, stream));
   DS_TRY(launch_fill(H, out, base, L, stream));
   return DIALSORT_OK;
-}
-
-size_t dialsort_batched_workspace_bytes(const dialsort_desc* descs, uint32_t count) {
-  return batch_workspace_bytes(descs, count);
-}
-
-dialsort_status dialsort_sort_batched(const dialsort_desc* descs, uint32_t count, void* ws, size_t ws_bytes,
-                                      hipStream_t stream) {
-  CallScope scope(stream);
-  return batch_run(descs, count, ws, ws_bytes, stream);
 }
 
 dialsort_status dialsort_set_launch_events(hipEvent_t* events, uint32_t cap, uint32_t* count) {

@@ -64,8 +64,9 @@ struct Lds16Log {
   }
 };
 
-// The add of count c to bin k returned `old`; log the crossings it caused.
-__device__ __noinline__ void lds16_crossing(uint32_t* words, uint32_t k, uint32_t c, uint32_t old,
+// The add of count c to bin k (packed word `word`) returned `old`; log the
+// crossings it caused.
+__device__ __noinline__ void lds16_crossing(uint32_t* words, uint32_t word, uint32_t k, uint32_t c, uint32_t old,
                                             uint32_t* evflag, uint32_t* ev, uint32_t* nev) {
   Lds16Log L;
   L.evflag = evflag;
@@ -74,34 +75,45 @@ __device__ __noinline__ void lds16_crossing(uint32_t* words, uint32_t k, uint32_
   if ((k & 1u) == 0) {
     L.log(k, false);                                  // the low field crossed
     if ((old >> 16) == 0xFFFFu) L.log(k + 1, false);  // its carry wrapped the high field
-    const uint32_t old2 = atomicAdd(&words[k >> 1], 0xFFFF0000u);  // take the carry back out
+    const uint32_t old2 = atomicAdd(&words[word], 0xFFFF0000u);  // take the carry back out
     if ((old2 >> 16) == 0u) L.log(k + 1, true);
   } else {
     L.log(k, false);
   }
 }
 
-// NT threads; CAP = LDS words; PACKED selects the 16-bit layout.
-// rows: G rows of `row_stride` uint32 each (row g at rows + g*row_stride).
-template <int NT, int CAP, bool PACKED, int AGG, bool ALIGNED, int UNR>
-__global__ __launch_bounds__(NT) void k_hist_lds(const uint32_t* __restrict__ keys, uint64_t n, uint64_t per,
-                                                 uint32_t umax, uint32_t U, uint32_t* __restrict__ rows,
-                                                 uint64_t row_stride, Ctl* ctl) {
-  __shared__ uint32_t s[CAP];
-  __shared__ uint32_t evflag[PACKED ? 65536 / 32 : 1];
-  __shared__ uint32_t ev[PACKED ? LDS16_EVCAP : 1];
-  __shared__ uint32_t nev;
+// LDS state of one ingestion slab: CAP counter words (PAD: one spare word per
+// 32, see pw()), plus the crossing log of the packed layout.
+template <int CAP, bool PACKED>
+struct HistSmem {
+  uint32_t s[CAP];
+  uint32_t evflag[PACKED ? 65536 / 32 : 1];
+  uint32_t ev[PACKED ? LDS16_EVCAP : 1];
+  uint32_t nev;
+};
+
+// padded word index: one spare word per 32 keeps per-thread runs of 32
+// consecutive words on distinct banks
+__device__ __forceinline__ uint32_t pw(uint32_t w) { return w + (w >> 5); }
+
+// Count keys [beg, end) into S (NT threads) and write the U exact counts to row.
+// The word of bin x is x (uint32 counters) or x >> 1 (packed), at pw() of it
+// when PAD.  A key > umax sets ST_RANGE in *status.
+template <int NT, bool PACKED, bool PAD, int AGG, bool ALIGNED, int UNR, typename SM>
+__device__ __forceinline__ void hist_slab(SM& S, const uint32_t* __restrict__ keys, uint64_t beg, uint64_t end,
+                                          uint32_t umax, uint32_t U, uint32_t* __restrict__ row,
+                                          uint32_t* status) {
+  auto wi = [](uint32_t w) { return PAD ? pw(w) : w; };
   const uint32_t nwords = PACKED ? (U + 1) / 2 : U;
+  const uint32_t zwords = PAD ? pw(nwords - 1) + 1 : nwords;
   const uint32_t tid = threadIdx.x;
-  for (uint32_t i = tid; i < nwords; i += NT) s[i] = 0;
+  for (uint32_t i = tid; i < zwords; i += NT) S.s[i] = 0;
   if constexpr (PACKED) {
-    for (uint32_t i = tid; i < 65536 / 32; i += NT) evflag[i] = 0;
-    if (tid == 0) nev = 0;
+    for (uint32_t i = tid; i < 65536 / 32; i += NT) S.evflag[i] = 0;
+    if (tid == 0) S.nev = 0;
   }
   __syncthreads();
 
-  const uint64_t beg = (uint64_t)blockIdx.x * per;
-  const uint64_t end = beg + per < n ? beg + per : n;
   bool bad = false;
   WaveAgg st;
   // uniform trip count across the workgroup: every lane takes part in the ballots
@@ -124,9 +136,9 @@ __global__ __launch_bounds__(NT) void k_hist_lds(const uint32_t* __restrict__ ke
         cc[u][i] = c;
         old[u][i] = 0;
         if constexpr (!PACKED) {
-          if (c) atomicAdd(&s[v[u][i]], c);
+          if (c) atomicAdd(&S.s[wi(v[u][i])], c);
         } else {
-          if (c) old[u][i] = atomicAdd(&s[v[u][i] >> 1], c << ((v[u][i] & 1u) << 4));
+          if (c) old[u][i] = atomicAdd(&S.s[wi(v[u][i] >> 1)], c << ((v[u][i] & 1u) << 4));
         }
       }
     }
@@ -147,30 +159,31 @@ __global__ __launch_bounds__(NT) void k_hist_lds(const uint32_t* __restrict__ ke
           for (int i = 0; i < 4; ++i) {
             const uint32_t c = cc[u][i], k = v[u][i];
             const uint32_t field = __builtin_amdgcn_ubfe(old[u][i], (k & 1u) << 4, 16);
-            if (c && field + c >= 0x10000u) lds16_crossing(s, k, c, old[u][i], evflag, ev, &nev);
+            if (c && field + c >= 0x10000u) lds16_crossing(S.s, wi(k >> 1), k, c, old[u][i], S.evflag, S.ev, &S.nev);
           }
         }
       }
     }
   }
-  if (__syncthreads_or(bad) && tid == 0) set_status(ctl, ST_RANGE);
+  if (__syncthreads_or(bad) && tid == 0) atomicOr(status, ST_RANGE);
 
-  uint32_t* row = rows + (uint64_t)blockIdx.x * row_stride;
   if constexpr (!PACKED) {
-    for (uint32_t i = tid; i < U; i += NT) row[i] = s[i];
+    for (uint32_t i = tid; i < U; i += NT) row[i] = S.s[wi(i)];
   } else {
-    const uint32_t ne = nev < LDS16_EVCAP ? nev : LDS16_EVCAP;
-    if (tid == 0 && nev > LDS16_EVCAP) set_status(ctl, ST_INTERNAL);  // cannot happen within the key bound
+    const uint32_t ne = S.nev < LDS16_EVCAP ? S.nev : LDS16_EVCAP;
+    if (tid == 0 && S.nev > LDS16_EVCAP) atomicOr(status, ST_INTERNAL);  // cannot happen within the key bound
     for (uint32_t w = tid; w < nwords; w += NT) {
-      const uint32_t word = s[w];
+      const uint32_t word = S.s[wi(w)];
       uint64_t cnt[2] = {word & 0xFFFFu, word >> 16};
+      if ((S.evflag[(2 * w) >> 5] >> ((2 * w) & 31)) & 3u) {
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const uint32_t bin = 2 * w + h;
-        if (evflag[bin >> 5] & (1u << (bin & 31))) {
-          for (uint32_t e = 0; e < ne; ++e) {
-            const uint32_t x = ev[e];
-            if ((x & 0x7FFFFFFFu) == bin) cnt[h] += (x & 0x80000000u) ? (uint64_t)-65536ll : 65536ull;
+        for (int h = 0; h < 2; ++h) {
+          const uint32_t bin = 2 * w + h;
+          if (S.evflag[bin >> 5] & (1u << (bin & 31))) {
+            for (uint32_t e = 0; e < ne; ++e) {
+              const uint32_t x = S.ev[e];
+              if ((x & 0x7FFFFFFFu) == bin) cnt[h] += (x & 0x80000000u) ? (uint64_t)-65536ll : 65536ull;
+            }
           }
         }
       }
@@ -178,6 +191,19 @@ __global__ __launch_bounds__(NT) void k_hist_lds(const uint32_t* __restrict__ ke
       if (2 * w + 1 < U) row[2 * w + 1] = (uint32_t)cnt[1];
     }
   }
+}
+
+// NT threads; CAP = LDS words; PACKED selects the 16-bit layout.
+// rows: G rows of `row_stride` uint32 each (row g at rows + g*row_stride).
+template <int NT, int CAP, bool PACKED, int AGG, bool ALIGNED, int UNR>
+__global__ __launch_bounds__(NT) void k_hist_lds(const uint32_t* __restrict__ keys, uint64_t n, uint64_t per,
+                                                 uint32_t umax, uint32_t U, uint32_t* __restrict__ rows,
+                                                 uint64_t row_stride, Ctl* ctl) {
+  __shared__ HistSmem<CAP, PACKED> S;
+  const uint64_t beg = (uint64_t)blockIdx.x * per;
+  const uint64_t end = beg + per < n ? beg + per : n;
+  hist_slab<NT, PACKED, false, AGG, ALIGNED, UNR>(S, keys, beg, end, umax, U, rows + (uint64_t)blockIdx.x * row_stride,
+                                                  &ctl->status);
 }
 
 // Direct global atomics into a zeroed H, after the same wave merge.  Used when

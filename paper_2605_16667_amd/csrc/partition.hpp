@@ -39,39 +39,46 @@
 
 namespace ds {
 
-constexpr int PART_LOG2W = 16;
+constexpr int PART_LOG2W = 16;   // bucket width of the single-array path
 constexpr uint32_t PART_W = 1u << PART_LOG2W;
 constexpr int PART_TK = 8192;    // keys per pass-1 tile (segment starts fit in uint16)
-constexpr int PART_NT = 1024;   // pass-2 workgroup
-constexpr int P1_NT = 512;      // pass-1 workgroup
+constexpr int PART_NT = 1024;    // pass-2 workgroup
+constexpr int P1_NT = 512;       // pass-1 workgroup
 constexpr uint32_t PART_BMAX = 8192;
 constexpr uint64_t PART_UMAX = (uint64_t)PART_W * PART_BMAX;  // 2^29
 
 // ---------------------------------------------------------------------------
 // Pass 1
 // ---------------------------------------------------------------------------
-// seg: T rows of `bstride` uint16 (bstride >= B + 1, multiple of 8).  Invalid
-// keys are parked as 0xFFFFFFFF (U <= 2^29 here, so no valid key has that value).
-template <int BMAXT, int AGG, bool ALIGNED>
-__global__ __launch_bounds__(P1_NT) void k_partition(const uint32_t* __restrict__ keys, uint64_t n,
-                                                          uint32_t umax, uint32_t B,
-                                                          uint16_t* __restrict__ staging,
-                                                          uint16_t* __restrict__ seg, uint32_t bstride, Ctl* ctl) {
-  constexpr int GPT = PART_TK / 4 / P1_NT;  // key groups of 4 per thread
-  __shared__ uint32_t cnt[BMAXT + 1];
-  __shared__ __align__(16) uint16_t stage[PART_TK];
-  __shared__ uint32_t scan_tmp[P1_NT / WAVE + 1];
+template <int NT, int BMAXT>
+struct PartSmem {
+  uint32_t cnt[BMAXT + 1];
+  __align__(16) uint16_t stage[PART_TK];
+  uint32_t scan_tmp[NT / WAVE + 1];
+};
+
+// Tile `tile` of TK keys (NT threads).  seg: T rows of `bstride` uint16
+// (bstride >= B + 1, multiple of 8).  Invalid keys are parked as 0xFFFFFFFF
+// (U <= 2^29 here, so no valid key has that value).  Bucket of x: x >> LOG2W.
+template <int NT, int BMAXT, int AGG, bool ALIGNED, int LOG2W>
+__device__ __forceinline__ void partition_tile(PartSmem<NT, BMAXT>& S, const uint32_t* __restrict__ keys, uint64_t n,
+                                               uint32_t umax, uint32_t B, uint16_t* __restrict__ staging,
+                                               uint16_t* __restrict__ seg, uint32_t bstride, uint32_t* status,
+                                               uint32_t tile) {
+  constexpr int GPT = PART_TK / 4 / NT;  // key groups of 4 per thread
+  static_assert(GPT >= 1, "a tile gives every thread at least one group");
+  constexpr uint32_t WM = (1u << LOG2W) - 1;
   const uint32_t tid = threadIdx.x;
-  const uint64_t tb = (uint64_t)blockIdx.x * PART_TK;
+  const uint64_t tb = (uint64_t)tile * PART_TK;
   const uint64_t te = tb + PART_TK < n ? tb + PART_TK : n;
 
-  for (uint32_t i = tid; i <= B; i += P1_NT) cnt[i] = 0;
+  for (uint32_t i = tid; i <= B; i += NT) S.cnt[i] = 0;
 
   uint32_t v[GPT][4];
   bool bad = false;
 #pragma unroll
   for (int u = 0; u < GPT; ++u) {
-    const uint32_t c = load_group<ALIGNED>(keys, tb + ((uint64_t)u * P1_NT + tid) * 4, te, v[u]);
+    const uint32_t c = load_group<ALIGNED>(keys, tb + ((uint64_t)u * NT + tid) * 4, te, v[u]);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const bool valid = (uint32_t)i < c;
@@ -87,29 +94,29 @@ __global__ __launch_bounds__(P1_NT) void k_partition(const uint32_t* __restrict_
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const bool ok = v[u][i] != 0xFFFFFFFFu;
-      wave_count<AGG>(cnt, ok ? (v[u][i] >> PART_LOG2W) : 0u, ok, st);
+      wave_count<AGG>(S.cnt, ok ? (v[u][i] >> LOG2W) : 0u, ok, st);
     }
   }
-  if (__syncthreads_or(bad) && tid == 0) set_status(ctl, ST_RANGE);
+  if (__syncthreads_or(bad) && tid == 0) atomicOr(status, ST_RANGE);
 
   // exclusive scan of the B+1 counters (counter B stays 0, so the total is the
   // number of valid keys); each thread owns a run of CPT counters
-  constexpr int CPT = (BMAXT + 1 + P1_NT - 1) / P1_NT;
+  constexpr int CPT = (BMAXT + 1 + NT - 1) / NT;
   uint32_t loc[CPT];
   uint32_t sum = 0;
 #pragma unroll
   for (int j = 0; j < CPT; ++j) {
     const uint32_t i = tid * CPT + j;
-    loc[j] = i <= B ? cnt[i] : 0;
+    loc[j] = i <= B ? S.cnt[i] : 0;
     sum += loc[j];
   }
   uint32_t total;
-  uint32_t pre = block_exclusive_sum<P1_NT>(sum, scan_tmp, &total);
-  uint16_t* srow = seg + (uint64_t)blockIdx.x * bstride;
+  uint32_t pre = block_exclusive_sum<NT>(sum, S.scan_tmp, &total);
+  uint16_t* srow = seg + (uint64_t)tile * bstride;
 #pragma unroll
   for (int j = 0; j < CPT; ++j) {
     const uint32_t i = tid * CPT + j;
-    if (i <= B) { cnt[i] = pre; srow[i] = (uint16_t)pre; }
+    if (i <= B) { S.cnt[i] = pre; srow[i] = (uint16_t)pre; }
     pre += loc[j];
   }
   __syncthreads();
@@ -124,7 +131,7 @@ __global__ __launch_bounds__(P1_NT) void k_partition(const uint32_t* __restrict_
     for (int i = 0; i < 4; ++i) {
       const uint32_t x = v[u][i];
       const bool ok = x != 0xFFFFFFFFu;
-      tk[u][i] = wave_rank_issue<AGG>(cnt, ok ? (x >> PART_LOG2W) : 0u, ok, st2);
+      tk[u][i] = wave_rank_issue<AGG>(S.cnt, ok ? (x >> LOG2W) : 0u, ok, st2);
     }
   }
 #pragma unroll
@@ -133,7 +140,7 @@ __global__ __launch_bounds__(P1_NT) void k_partition(const uint32_t* __restrict_
     for (int i = 0; i < 4; ++i) {
       const uint32_t x = v[u][i];
       const uint32_t pos = wave_rank_finish(tk[u][i]);
-      if (x != 0xFFFFFFFFu) stage[pos] = (uint16_t)(x & (PART_W - 1));
+      if (x != 0xFFFFFFFFu) S.stage[pos] = (uint16_t)(x & WM);
     }
   }
   __syncthreads();
@@ -141,8 +148,19 @@ __global__ __launch_bounds__(P1_NT) void k_partition(const uint32_t* __restrict_
   // tile slice of staging: the valid keys, bucket-major, as 16-byte stores
   uint16_t* dst = staging + tb;
   const uint32_t n8 = (total + 7) / 8;
-  for (uint32_t i = tid; i < n8; i += P1_NT)
-    reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(stage)[i];
+  for (uint32_t i = tid; i < n8; i += NT)
+    reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(S.stage)[i];
+  __syncthreads();  // S is reused by the caller's next tile
+}
+
+template <int BMAXT, int AGG, bool ALIGNED>
+__global__ __launch_bounds__(P1_NT) void k_partition(const uint32_t* __restrict__ keys, uint64_t n,
+                                                     uint32_t umax, uint32_t B,
+                                                     uint16_t* __restrict__ staging,
+                                                     uint16_t* __restrict__ seg, uint32_t bstride, Ctl* ctl) {
+  __shared__ PartSmem<P1_NT, BMAXT> S;
+  partition_tile<P1_NT, BMAXT, AGG, ALIGNED, PART_LOG2W>(S, keys, n, umax, B, staging, seg, bstride, &ctl->status,
+                                                         blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -152,33 +170,38 @@ __global__ __launch_bounds__(P1_NT) void k_partition(const uint32_t* __restrict_
 constexpr int BK_SQ = 4;            // 16-byte quads (8 keys each) per lane per gather step
 constexpr uint32_t BK_LRCAP = 512;  // long-run list entries
 constexpr uint64_t BK_PACKMAX = 1ull << 22;  // keys per bucket on the packed path
-constexpr uint32_t BK_WPW = PART_W / 2 + PART_W / 64;  // padded packed words
 
-// padded word index: one spare word per 32 keeps per-thread runs of 32 words on
-// distinct banks
-__device__ __forceinline__ uint32_t pw(uint32_t w) { return w + (w >> 5); }
-
-// LDS state of k_bucket
-struct BucketSmem {
-  uint32_t s[BK_WPW];  // packed counters (or uint32 counters of a half) at padded index
-  uint32_t evflag[PART_W / 32];
-  uint32_t ev[LDS16_EVCAP];
+// LDS state of a bucket (or of a row sum): counters of one bucket of W = 2^LOG2W
+// bins -- packed 16-bit pairs when LOG2W == 16, else one uint32 per bin -- at
+// padded word indices, the crossing log of the packed layout, the long-run list
+// of the item emitter and block-reduction space.
+template <int NT, int LOG2W>
+struct BinSmem {
+  static constexpr bool PACKED = LOG2W == 16;
+  static constexpr uint32_t WORDS = PACKED ? (1u << 15) : (1u << LOG2W);
+  static constexpr uint32_t WPW = WORDS + WORDS / 32;
+  uint32_t s[WPW];
+  uint32_t evflag[PACKED ? 65536 / 32 : 1];
+  uint32_t ev[PACKED ? LDS16_EVCAP : 1];
   uint32_t nev;
   uint32_t lr_k[BK_LRCAP], lr_n[BK_LRCAP];
   uint64_t lr_o[BK_LRCAP], lr_c[BK_LRCAP];
-  uint64_t red[PART_NT / WAVE + 1];
+  uint64_t red[NT / WAVE + 1];
   uint32_t n, item0;
 };
 
-// Gather the segments of bucket b and count their relative keys.  PACKED: into
-// the packed 16-bit fields (all W keys).  Otherwise: 32-bit counters for the
-// keys whose relative value lies in half `half` (x >> 15 == half).
+enum GatherMode { GM_PACKED, GM_HALF, GM_DIRECT };
+
+// Gather the segments of bucket b and count their relative keys.  GM_PACKED:
+// into the packed 16-bit fields (W = 2^16).  GM_HALF: 32-bit counters for the
+// keys whose relative value lies in half `half` (x >> 15 == half, W = 2^16).
+// GM_DIRECT: 32-bit counters for all keys (W <= 2^15).
 // Each lane owns whole segments (tiles tid, tid + NT, ...): it loads its segment
 // as aligned 16-byte quads of 8 keys, BK_SQ quads per step, and prefetches the
 // bounds of its next segment while it works on the current one, so the
 // segment-table loads never sit on the critical path.
-template <int AGG, bool PACKED>
-__device__ __forceinline__ void bucket_gather(BucketSmem& S, const uint16_t* __restrict__ staging,
+template <int NT, int LOG2W, int AGG, GatherMode GM>
+__device__ __forceinline__ void bucket_gather(BinSmem<NT, LOG2W>& S, const uint16_t* __restrict__ staging,
                                               const uint16_t* __restrict__ seg, uint32_t bstride, uint32_t T,
                                               uint32_t b, uint32_t half) {
   Lds16Log L;
@@ -195,15 +218,16 @@ __device__ __forceinline__ void bucket_gather(BucketSmem& S, const uint16_t* __r
   if (t < T) { const uint16_t* row = seg + (uint64_t)t * bstride; ns = row[b]; ne = row[b + 1]; }
   uint32_t s16 = 0, e16 = 0, ql = 0;
   auto open = [&]() {
-    s16 = ns;
-    e16 = ne;
-    ql = ns & ~7u;
-    const uint32_t tn = t + PART_NT;
+    // a segment never leaves its tile's slice of staging
+    e16 = ne < (uint32_t)PART_TK ? ne : (uint32_t)PART_TK;
+    s16 = ns < e16 ? ns : e16;
+    ql = s16 & ~7u;
+    const uint32_t tn = t + NT;
     if (tn < T) { const uint16_t* row = seg + (uint64_t)tn * bstride; ns = row[b]; ne = row[b + 1]; }
   };
   auto advance = [&]() {
     while (t < T && ql >= e16) {
-      t += PART_NT;
+      t += NT;
       if (t < T) open();
     }
   };
@@ -242,20 +266,22 @@ __device__ __forceinline__ void bucket_gather(BucketSmem& S, const uint16_t* __r
       for (int e = 0; e < 8; ++e) {
         const uint32_t x = (e & 1) ? (wds[e >> 1] >> 16) : (wds[e >> 1] & 0xFFFFu);
         bool ok = (qm >> e) & 1u;
-        if (!PACKED) ok = ok && (x >> 15) == half;
+        if (GM == GM_HALF) ok = ok && (x >> 15) == half;
         WaveGroups g;
         const uint32_t n = wave_merge_count<AGG>(x, ok, st, g);
         kk[e] = x;
         cc[e] = n;
         old[e] = 0;
-        if (PACKED) {
+        if (GM == GM_PACKED) {
           const uint32_t sh = (x & 1u) << 4;
           if (n) old[e] = atomicAdd(&S.s[pw(x >> 1)], n << sh);
-        } else {
+        } else if (GM == GM_HALF) {
           if (n) atomicAdd(&S.s[pw(x & 0x7FFFu)], n);
+        } else {
+          if (n) atomicAdd(&S.s[pw(x)], n);
         }
       }
-      if (PACKED) {
+      if (GM == GM_PACKED) {
         // a field crossed a multiple of 65536 iff its old value plus the add
         // exceeds 0xFFFF; check the quad at once, handle crossings rarely
         uint32_t anyx = 0;
@@ -293,7 +319,8 @@ __device__ __forceinline__ void bucket_gather(BucketSmem& S, const uint16_t* __r
 }
 
 // Exact count of relative bin k on the packed path.
-__device__ __forceinline__ uint32_t packed_count(const BucketSmem& S, uint32_t k, uint32_t ne) {
+template <typename SM>
+__device__ __forceinline__ uint32_t packed_count(const SM& S, uint32_t k, uint32_t ne) {
   const uint32_t word = S.s[pw(k >> 1)];
   uint32_t c = (word >> ((k & 1u) << 4)) & 0xFFFFu;
   if (S.evflag[k >> 5] & (1u << (k & 31))) {
@@ -305,15 +332,16 @@ __device__ __forceinline__ uint32_t packed_count(const BucketSmem& S, uint32_t k
   return c;
 }
 
-// Block sum over PART_NT threads (result in every thread).
-__device__ __forceinline__ uint64_t block_sum(BucketSmem& S, uint64_t x) {
+// Block sum over NT threads (result in every thread).
+template <int NT, typename SM>
+__device__ __forceinline__ uint64_t block_sum(SM& S, uint64_t x) {
   const uint32_t lane = lane_id(), w = threadIdx.x / WAVE;
   x = wave_sum(x);
   __syncthreads();
   if (lane == 0) S.red[w] = x;
   __syncthreads();
   uint64_t a = 0;
-  for (uint32_t i = 0; i < PART_NT / WAVE; ++i) a += S.red[i];
+  for (uint32_t i = 0; i < NT / WAVE; ++i) a += S.red[i];
   return a;
 }
 
@@ -321,8 +349,8 @@ __device__ __forceinline__ uint64_t block_sum(BucketSmem& S, uint64_t x) {
 // starting at relative bin j0, whose counts come from count(j) and sum to len;
 // o0 is the absolute position where its stretch starts.  The span of the bucket part being
 // emitted is [sp0, sp1); item0 is the index of its first item.
-template <uint32_t NB, typename CountF>
-__device__ __forceinline__ void emit_items(BucketSmem& S, FillItem* __restrict__ items, uint32_t item0, int CL2,
+template <int NT, uint32_t NB, typename SM, typename CountF>
+__device__ __forceinline__ void emit_items(SM& S, FillItem* __restrict__ items, uint32_t item0, int CL2,
                                            uint64_t sp0, uint64_t sp1, uint64_t hb, uint32_t j0, uint32_t nb_valid,
                                            uint64_t o0, uint64_t len, uint32_t klast, CountF count) {
   const uint32_t tid = threadIdx.x;
@@ -398,7 +426,7 @@ __device__ __forceinline__ void emit_items(BucketSmem& S, FillItem* __restrict__
       for (uint32_t e2 = 0; e2 < nl; ++e2) {
         const uint64_t oo = S.lr_o[e2], cc = S.lr_c[e2], nn = S.lr_n[e2];
         const uint32_t kk = S.lr_k[e2];
-        for (uint64_t x = tid; x < nn; x += PART_NT) {
+        for (uint64_t x = tid; x < nn; x += NT) {
           const uint64_t c = cc + x;
           FillItem it;
           it.p0 = c << CL2; it.p1 = ((c + 1) << CL2) < sp1 ? ((c + 1) << CL2) : sp1;
@@ -413,16 +441,17 @@ __device__ __forceinline__ void emit_items(BucketSmem& S, FillItem* __restrict__
 }
 
 // Reserve the items of span [sp0, sp1) (thread 0) and broadcast the first index.
-__device__ __forceinline__ uint32_t reserve_items(BucketSmem& S, Ctl* ctl, uint64_t sp0, uint64_t sp1,
-                                                  uint32_t item_cap, int CL2) {
+template <typename SM>
+__device__ __forceinline__ uint32_t reserve_items(SM& S, uint32_t* status, uint32_t* nitems, uint64_t sp0,
+                                                  uint64_t sp1, uint32_t item_cap, int CL2) {
   const uint64_t C = 1ull << CL2;
   const uint64_t nit = sp1 > sp0 ? ((sp1 + C - 1) >> CL2) - (sp0 >> CL2) : 0;
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t i0 = 0;
     if (nit) {
-      i0 = atomicAdd(&ctl->nitems, (uint32_t)nit);
-      if ((uint64_t)i0 + nit > item_cap) { set_status(ctl, ST_INTERNAL); i0 = 0xFFFFFFFFu; }
+      i0 = atomicAdd(nitems, (uint32_t)nit);
+      if ((uint64_t)i0 + nit > item_cap) { atomicOr(status, ST_INTERNAL); i0 = 0xFFFFFFFFu; }
     }
     S.item0 = i0;
   }
@@ -430,77 +459,27 @@ __device__ __forceinline__ uint32_t reserve_items(BucketSmem& S, Ctl* ctl, uint6
   return S.item0;
 }
 
-// ---------------------------------------------------------------------------
-// Pass 2
-// ---------------------------------------------------------------------------
-// T tiles; H receives bins [b*W, min((b+1)*W, U)).  FULL also appends the fill
-// items of the bucket's sorted run for k_fill.
-template <int AGG, bool HALIGNED, bool FULL>
-__global__ __launch_bounds__(PART_NT) void k_bucket(const uint16_t* __restrict__ staging,
-                                                    const uint16_t* __restrict__ seg, uint32_t bstride,
-                                                    uint32_t T, uint32_t B, uint64_t U, uint32_t* __restrict__ H,
-                                                    Ctl* ctl, FillItem* __restrict__ items, uint32_t item_cap,
-                                                    int CL2) {
-  __shared__ __align__(16) BucketSmem S;
+// Project the counts held in S: the piece covers relative bins [0, pcnt) of
+// absolute first bin hb, counts at S.s[pw(i)] (uint32) or from the packed
+// fields (PACKED; ne = logged events), and its run starts at output position
+// base.  Each thread owns NB consecutive bins; a block scan of their sums tells
+// it where its stretch starts and it appends the fill items that start there.
+// Returns the piece's total.
+template <int NT, uint32_t NB, bool PACKED, typename SM>
+__device__ __forceinline__ uint64_t project_piece(SM& S, uint32_t* status, uint32_t* nitems, FillItem* items,
+                                                  uint32_t item_cap, int CL2, uint64_t base, uint64_t hb,
+                                                  uint32_t pcnt, uint32_t klast, uint32_t ne) {
   const uint32_t tid = threadIdx.x;
-  // XCD-aware bucket order: blocks are dispatched round-robin over 8 XCDs
-  uint32_t b = blockIdx.x;
-  if ((B & 7u) == 0) b = (blockIdx.x & 7u) * (B >> 3) + (blockIdx.x >> 3);
-  const uint64_t hb = (uint64_t)b * PART_W;
-  const uint32_t cnt = (uint32_t)(U - hb < PART_W ? U - hb : PART_W);
-  const uint32_t klast = (uint32_t)(hb + cnt - 1);
-
-  // where the bucket's run starts (keys of earlier buckets) and its length
-  uint64_t mb = 0, mt = 0;
-  for (uint32_t tt = tid; tt < T; tt += PART_NT) {
-    const uint16_t* row = seg + (uint64_t)tt * bstride;
-    const uint32_t lo = row[b], hi = row[b + 1];
-    mb += lo;
-    mt += hi - lo;
-  }
-  const uint64_t base = block_sum(S, mb);
-  const uint64_t total = block_sum(S, mt);
-
-  if (total <= BK_PACKMAX) {
-    // ---- packed path: one gather, 16-bit fields + crossing events ----------
-    for (uint32_t i = tid; i < BK_WPW; i += PART_NT) S.s[i] = 0;
-    for (uint32_t i = tid; i < PART_W / 32; i += PART_NT) S.evflag[i] = 0;
-    if (tid == 0) { S.nev = 0; S.n = 0; }
-    __syncthreads();
-    bucket_gather<AGG, true>(S, staging, seg, bstride, T, b, 0);
-    __syncthreads();
-    const uint32_t ne = S.nev < LDS16_EVCAP ? S.nev : LDS16_EVCAP;
-    if (tid == 0 && S.nev > LDS16_EVCAP) set_status(ctl, ST_INTERNAL);  // cannot happen within BK_PACKMAX
-    // H: two bins per packed word; bins with logged crossings (flag bit set)
-    // take the slow exact count
-    for (uint32_t wv = tid; wv < (cnt + 1) / 2; wv += PART_NT) {
-      const uint32_t k = 2 * wv;
-      const uint32_t word = S.s[pw(wv)];
-      uint32_t c0 = word & 0xFFFFu, c1 = word >> 16;
-      if ((S.evflag[k >> 5] >> (k & 31)) & 3u) {
-        c0 = packed_count(S, k, ne);
-        c1 = packed_count(S, k + 1, ne);
-      }
-      if (HALIGNED && k + 1 < cnt) {
-        *reinterpret_cast<uint2*>(H + hb + k) = make_uint2(c0, c1);
-      } else {
-        H[hb + k] = c0;
-        if (k + 1 < cnt) H[hb + k + 1] = c1;
-      }
-    }
-    if constexpr (!FULL) return;
-    if (total == 0) return;
-
-    // each thread owns 64 consecutive bins; a block scan of their sums tells it
-    // where its stretch of the bucket's run starts, and it appends the fill
-    // items that start in that stretch
-    constexpr uint32_t NB = PART_W / PART_NT;  // 64
-    const uint32_t j0 = tid * NB;
-    uint32_t sum = 0;
-    // whole words when none of the thread's 64 bins logged a crossing; bins at
-    // or beyond cnt are never counted (keys there are out of range), so their
+  const uint32_t j0 = tid * NB;
+  uint32_t sum = 0;
+  if constexpr (PACKED) {
+    // whole words when none of the thread's bins logged a crossing; bins at or
+    // beyond pcnt are never counted (keys there are out of range), so their
     // fields are zero
-    if ((S.evflag[j0 >> 5] | S.evflag[(j0 >> 5) + 1]) == 0u) {
+    uint32_t fl = 0;
+#pragma unroll
+    for (uint32_t f = 0; f < NB / 32; ++f) fl |= S.evflag[(j0 >> 5) + f];
+    if (fl == 0u) {
 #pragma unroll 8
       for (uint32_t w = 0; w < NB / 2; ++w) {
         const uint32_t word = S.s[pw((j0 >> 1) + w)];
@@ -509,44 +488,168 @@ __global__ __launch_bounds__(PART_NT) void k_bucket(const uint16_t* __restrict__
     } else {
       for (uint32_t j = 0; j < NB; ++j) {
         const uint32_t i = j0 + j;
-        sum += i < cnt ? packed_count(S, i, ne) : 0u;
+        sum += i < pcnt ? packed_count(S, i, ne) : 0u;
       }
     }
-    uint64_t tot;
-    const uint64_t pre = block_exclusive_sum<PART_NT>((uint64_t)sum, S.red, &tot);
-    auto count = [&](uint32_t i) -> uint32_t { return packed_count(S, i, ne); };
-    const uint32_t item0 = reserve_items(S, ctl, base, base + total, item_cap, CL2);
-    if (item0 == 0xFFFFFFFFu) return;
-    emit_items<NB>(S, items, item0, CL2, base, base + total, hb, j0, cnt, base + pre, sum, klast, count);
-    return;
+  } else {
+#pragma unroll 8
+    for (uint32_t j = 0; j < NB; ++j) sum += j0 + j < pcnt ? S.s[pw(j0 + j)] : 0u;
   }
+  uint64_t tot;
+  const uint64_t pre = block_exclusive_sum<NT>((uint64_t)sum, S.red, &tot);
+  if (tot == 0) return 0;
+  const uint32_t item0 = reserve_items(S, status, nitems, base, base + tot, item_cap, CL2);
+  if (item0 == 0xFFFFFFFFu) return tot;
+  if constexpr (PACKED) {
+    auto count = [&](uint32_t i) -> uint32_t { return packed_count(S, i, ne); };
+    emit_items<NT, NB>(S, items, item0, CL2, base, base + tot, hb, j0, pcnt, base + pre, sum, klast, count);
+  } else {
+    auto count = [&](uint32_t i) -> uint32_t { return S.s[pw(i)]; };
+    emit_items<NT, NB>(S, items, item0, CL2, base, base + tot, hb, j0, pcnt, base + pre, sum, klast, count);
+  }
+  return tot;
+}
 
-  // ---- heavy bucket: two halves of 2^15 bins with 32-bit counters -----------
-  uint64_t hbase = base;  // where the current half's run starts
-  for (uint32_t half = 0; half < 2; ++half) {
-    const uint32_t hb0 = half << 15;
-    if (hb0 >= cnt) break;
-    const uint32_t hcnt = cnt - hb0 < (1u << 15) ? cnt - hb0 : (1u << 15);
+// ---------------------------------------------------------------------------
+// Pass 2
+// ---------------------------------------------------------------------------
+// Bucket b of W = 2^LOG2W bins (T tiles): H receives bins [b*W, min((b+1)*W, U)).
+// FULL also appends the fill items of the bucket's sorted run.
+template <int NT, int LOG2W, int AGG, bool HALIGNED, bool FULL>
+__device__ __forceinline__ void bucket_body(BinSmem<NT, LOG2W>& S, const uint16_t* __restrict__ staging,
+                                            const uint16_t* __restrict__ seg, uint32_t bstride, uint32_t T,
+                                            uint64_t U, uint32_t* __restrict__ H, uint32_t* status,
+                                            uint32_t* nitems, FillItem* __restrict__ items, uint32_t item_cap,
+                                            int CL2, uint32_t b) {
+  constexpr uint32_t W = 1u << LOG2W;
+  using SM = BinSmem<NT, LOG2W>;
+  const uint32_t tid = threadIdx.x;
+  const uint64_t hb = (uint64_t)b * W;
+  const uint32_t cnt = (uint32_t)(U - hb < W ? U - hb : W);
+  const uint32_t klast = (uint32_t)(hb + cnt - 1);
+
+  // where the bucket's run starts (keys of earlier buckets) and its length
+  uint64_t mb = 0, mt = 0;
+  for (uint32_t tt = tid; tt < T; tt += NT) {
+    const uint16_t* row = seg + (uint64_t)tt * bstride;
+    const uint32_t lo = row[b], hi = row[b + 1];
+    mb += lo;
+    mt += hi - lo;
+  }
+  const uint64_t base = block_sum<NT>(S, mb);
+  const uint64_t total = block_sum<NT>(S, mt);
+
+  if constexpr (!SM::PACKED) {
+    // ---- W <= 2^15: one gather into 32-bit counters -------------------------
+    for (uint32_t i = tid; i < SM::WPW; i += NT) S.s[i] = 0;
     __syncthreads();
-    for (uint32_t i = tid; i < BK_WPW; i += PART_NT) S.s[i] = 0;
-    if (tid == 0) S.n = 0;
+    bucket_gather<NT, LOG2W, AGG, GM_DIRECT>(S, staging, seg, bstride, T, b, 0);
     __syncthreads();
-    bucket_gather<AGG, false>(S, staging, seg, bstride, T, b, half);
-    __syncthreads();
-    for (uint32_t i = tid; i < hcnt; i += PART_NT) H[hb + hb0 + i] = S.s[pw(i)];
-    if (FULL) {
-      constexpr uint32_t NB = (1u << 15) / PART_NT;  // 32
-      const uint32_t j0 = tid * NB;
-      uint32_t sum = 0;
-      for (uint32_t j = 0; j < NB; ++j) sum += j0 + j < hcnt ? S.s[pw(j0 + j)] : 0u;
-      uint64_t htot;
-      const uint64_t pre = block_exclusive_sum<PART_NT>((uint64_t)sum, S.red, &htot);
-      const uint32_t item0 = reserve_items(S, ctl, hbase, hbase + htot, item_cap, CL2);
-      if (item0 != 0xFFFFFFFFu && htot) {
-        auto count = [&](uint32_t i) -> uint32_t { return S.s[pw(i)]; };
-        emit_items<NB>(S, items, item0, CL2, hbase, hbase + htot, hb + hb0, j0, hcnt, hbase + pre, sum, klast, count);
+    for (uint32_t i = tid; i < cnt; i += NT) H[hb + i] = S.s[pw(i)];
+    if constexpr (FULL) {
+      if (total) project_piece<NT, W / NT, false>(S, status, nitems, items, item_cap, CL2, base, hb, cnt, klast, 0);
+    }
+    return;
+  } else {
+    if (total <= BK_PACKMAX) {
+      // ---- packed path: one gather, 16-bit fields + crossing events --------
+      for (uint32_t i = tid; i < SM::WPW; i += NT) S.s[i] = 0;
+      for (uint32_t i = tid; i < W / 32; i += NT) S.evflag[i] = 0;
+      if (tid == 0) { S.nev = 0; S.n = 0; }
+      __syncthreads();
+      bucket_gather<NT, LOG2W, AGG, GM_PACKED>(S, staging, seg, bstride, T, b, 0);
+      __syncthreads();
+      const uint32_t ne = S.nev < LDS16_EVCAP ? S.nev : LDS16_EVCAP;
+      if (tid == 0 && S.nev > LDS16_EVCAP) atomicOr(status, ST_INTERNAL);  // cannot happen within BK_PACKMAX
+      // H: two bins per packed word; bins with logged crossings (flag bit set)
+      // take the slow exact count
+      for (uint32_t wv = tid; wv < (cnt + 1) / 2; wv += NT) {
+        const uint32_t k = 2 * wv;
+        const uint32_t word = S.s[pw(wv)];
+        uint32_t c0 = word & 0xFFFFu, c1 = word >> 16;
+        if ((S.evflag[k >> 5] >> (k & 31)) & 3u) {
+          c0 = packed_count(S, k, ne);
+          c1 = packed_count(S, k + 1, ne);
+        }
+        if (HALIGNED && k + 1 < cnt) {
+          *reinterpret_cast<uint2*>(H + hb + k) = make_uint2(c0, c1);
+        } else {
+          H[hb + k] = c0;
+          if (k + 1 < cnt) H[hb + k + 1] = c1;
+        }
       }
-      hbase += htot;
+      if constexpr (FULL) {
+        if (total) project_piece<NT, W / NT, true>(S, status, nitems, items, item_cap, CL2, base, hb, cnt, klast, ne);
+      }
+      return;
+    }
+
+    // ---- heavy bucket: two halves of 2^15 bins with 32-bit counters ---------
+    uint64_t hbase = base;  // where the current half's run starts
+    for (uint32_t half = 0; half < 2; ++half) {
+      const uint32_t hb0 = half << 15;
+      if (hb0 >= cnt) break;
+      const uint32_t hcnt = cnt - hb0 < (1u << 15) ? cnt - hb0 : (1u << 15);
+      __syncthreads();
+      for (uint32_t i = tid; i < SM::WPW; i += NT) S.s[i] = 0;
+      if (tid == 0) S.n = 0;
+      __syncthreads();
+      bucket_gather<NT, LOG2W, AGG, GM_HALF>(S, staging, seg, bstride, T, b, half);
+      __syncthreads();
+      for (uint32_t i = tid; i < hcnt; i += NT) H[hb + hb0 + i] = S.s[pw(i)];
+      if constexpr (FULL) {
+        hbase += project_piece<NT, (1u << 15) / NT, false>(S, status, nitems, items, item_cap, CL2, hbase,
+                                                           hb + hb0, hcnt, klast, 0);
+      }
+    }
+  }
+}
+
+template <int AGG, bool HALIGNED, bool FULL>
+__global__ __launch_bounds__(PART_NT) void k_bucket(const uint16_t* __restrict__ staging,
+                                                    const uint16_t* __restrict__ seg, uint32_t bstride,
+                                                    uint32_t T, uint32_t B, uint64_t U, uint32_t* __restrict__ H,
+                                                    Ctl* ctl, FillItem* __restrict__ items, uint32_t item_cap,
+                                                    int CL2) {
+  __shared__ __align__(16) BinSmem<PART_NT, PART_LOG2W> S;
+  // XCD-aware bucket order: blocks are dispatched round-robin over 8 XCDs
+  uint32_t b = blockIdx.x;
+  if ((B & 7u) == 0) b = (blockIdx.x & 7u) * (B >> 3) + (blockIdx.x >> 3);
+  bucket_body<PART_NT, PART_LOG2W, AGG, HALIGNED, FULL>(S, staging, seg, bstride, T, U, H, &ctl->status,
+                                                        &ctl->nitems, items, item_cap, CL2, b);
+}
+
+// ---------------------------------------------------------------------------
+// Row sum + projection of a small universe (U <= 2^16) in one workgroup
+// ---------------------------------------------------------------------------
+// Sums nrows partial rows (row r at rows + r*row_stride) into H (skipped when
+// H_out is null: rows already is H) and, FULL, appends the fill items of the
+// whole output, piece by piece of P = min(W, 2^15) bins.
+template <int NT, int LOG2W, bool FULL>
+__device__ __forceinline__ void rows_body(BinSmem<NT, LOG2W>& S, const uint32_t* __restrict__ rows, uint32_t nrows,
+                                          uint64_t row_stride, uint32_t* __restrict__ H_out, uint32_t U,
+                                          uint32_t* status, uint32_t* nitems, FillItem* __restrict__ items,
+                                          uint32_t item_cap, int CL2) {
+  constexpr uint32_t P = LOG2W >= 15 ? (1u << 15) : (1u << LOG2W);
+  const uint32_t tid = threadIdx.x;
+  uint64_t pbase = 0;
+  for (uint32_t p0 = 0; p0 < U; p0 += P) {
+    const uint32_t pcnt = U - p0 < P ? U - p0 : P;
+    __syncthreads();  // S.s of the previous piece is no longer read
+    for (uint32_t i = tid; i < P; i += NT) {
+      uint32_t a = 0;
+      if (i < pcnt) {
+        const uint32_t* r = rows + p0 + i;
+#pragma unroll 4
+        for (uint32_t j = 0; j < nrows; ++j) a += r[(uint64_t)j * row_stride];
+        if (H_out) H_out[p0 + i] = a;
+      }
+      S.s[pw(i)] = a;
+    }
+    __syncthreads();
+    if constexpr (FULL) {
+      const uint32_t klast = p0 + pcnt - 1;
+      pbase += project_piece<NT, P / NT, false>(S, status, nitems, items, item_cap, CL2, pbase, p0, pcnt, klast, 0);
     }
   }
 }

@@ -252,113 +252,130 @@ __global__ __launch_bounds__(NT) void k_scan(const uint32_t* __restrict__ rows, 
   }
 }
 
-// Persistent fill over the items.  NT threads, C = 2^CL2 = 32*NT local
-// positions (one 32-bit flag word per thread).  Local position i is output
-// position a0 + i with a0 = p0 rounded down to a multiple of 4; an item always
-// fits in [0, C) of that frame.
-template <int NT, int CL2, bool OALIGNED>
-__global__ __launch_bounds__(NT) void k_fill(const uint32_t* __restrict__ H, uint32_t* __restrict__ out,
-                                             const Ctl* ctl, const FillItem* __restrict__ items,
-                                             uint32_t item_cap) {
-  constexpr uint32_t C = 1u << CL2;
-  static_assert(C == 32 * NT, "one 32-bit flag word per thread");
+// Fill of one item by NT threads.  C = 2^CL2 local positions, one 32-bit flag
+// word per 32 positions (NFW = C/32 <= NT words, held by threads tid < NFW).
+// Local position i is output position a0 + i with a0 = p0 rounded down to a
+// multiple of 4; an item always fits in [0, C) of that frame.
+template <int NT, int CL2>
+struct FillSmem {
+  static constexpr uint32_t C = 1u << CL2;
+  static constexpr uint32_t NFW = C / 32;
   // val[0, C): the key marked at each run start; val[C + s]: the key carried
   // into segment s (the last mark before it)
-  __shared__ __align__(16) uint32_t val[C + NT];
-  __shared__ uint32_t flag[NT];
-  __shared__ uint64_t scan_tmp[NT / WAVE + 1];
-  __shared__ int32_t last_idx[NT / WAVE];
+  __align__(16) uint32_t val[C + NFW];
+  uint32_t flag[NFW];
+  uint64_t scan_tmp[NT / WAVE + 1];
+  int32_t last_idx[NT / WAVE];
+};
+
+template <int NT, int CL2, bool OALIGNED>
+__device__ __forceinline__ void fill_item(FillSmem<NT, CL2>& S, const uint32_t* __restrict__ H,
+                                          uint32_t* __restrict__ out, const FillItem& I) {
+  constexpr uint32_t C = 1u << CL2;
+  constexpr uint32_t NFW = C / 32;
+  static_assert(NFW <= NT && NT % 8 == 0, "one flag word per thread at most");
   const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / WAVE;
   // output quads q = tid + k*NT all sit at the same offset b0 = 4 (q mod 8)
   // inside their 32-position segment: the masks of positions <= b0 + e are fixed
   const uint32_t b0 = (tid & 7u) * 4u;
   const uint32_t mk0 = 0xFFFFFFFFu >> (31u - b0), mk1 = 0xFFFFFFFFu >> (30u - b0);
   const uint32_t mk2 = 0xFFFFFFFFu >> (29u - b0), mk3 = 0xFFFFFFFFu >> (28u - b0);
+
+  const uint64_t p0 = I.p0, p1 = I.p1;
+  const uint64_t a0 = p0 & ~3ull;
+  const uint32_t lb = (uint32_t)(p0 - a0), le = (uint32_t)(p1 - a0);  // local [lb, le) within [0, C)
+  if (tid < NFW) S.flag[tid] = 0;
+  __syncthreads();
+  // walk the item's bins, marking run starts inside [p0, p1)
+  uint64_t kb = I.k;
+  uint64_t run = I.o;  // start position of bin kb's run (<= p0)
+  while (run < p1 && kb <= I.klast) {  // uniform: run and kb are block-wide values
+    const uint64_t k0 = kb + 4ull * tid;
+    uint32_t h[4];
+    uint64_t tsum = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      h[j] = k0 + j <= I.klast ? H[k0 + j] : 0u;
+      tsum += h[j];
+    }
+    uint64_t tot;
+    uint64_t ok = run + block_exclusive_sum<NT>(tsum, S.scan_tmp, &tot);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (h[j] > 0 && ok < p1) {
+        const uint32_t pos = ok <= p0 ? lb : (uint32_t)(ok - a0);
+        S.val[pos] = (uint32_t)(k0 + j);
+        atomicOr(&S.flag[pos >> 5], 1u << (pos & 31));
+      }
+      ok += h[j];
+    }
+    run += tot;
+    kb += 4ull * NT;
+  }
+  __syncthreads();
+  // carry the last mark forward.  Segment s = local positions [32s, 32s+32)
+  // with flag word flag[s]; val[C + s] = key of the last mark before segment s.
+  // Segment 0 always holds the item's first mark (at lb <= 3).
+  const uint32_t f = tid < NFW ? S.flag[tid] : 0u;
+  int32_t inc = f ? (int32_t)tid : -1;
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    const int32_t y = __shfl_up(inc, d, WAVE);
+    if ((int)lane >= d && y > inc) inc = y;
+  }
+  if (lane == WAVE - 1) S.last_idx[w] = inc;
+  int32_t ex_idx = __shfl_up(inc, 1, WAVE);
+  if (lane == 0) ex_idx = -1;
+  __syncthreads();
+  for (uint32_t q = 0; q < w; ++q) ex_idx = S.last_idx[q] > ex_idx ? S.last_idx[q] : ex_idx;
+  if (tid < NFW) {
+    uint32_t cin = 0;
+    if (ex_idx >= 0) cin = S.val[ex_idx * 32 + (31 - __clz(S.flag[ex_idx]))];
+    S.val[C + tid] = cin;
+  }
+  __syncthreads();
+  // every output quad resolves its keys from its segment's flag word: the
+  // key at position p is the last mark at or before p in the segment, else
+  // the segment's carried key
+  const uint32_t nq = (le + 3) >> 2;
+  for (uint32_t q = tid; q < nq; q += NT) {
+    const uint32_t sg = q >> 3;
+    const uint32_t fw = S.flag[sg];
+    uint32_t r0, r1, r2, r3;
+    if (fw == 0) {
+      r0 = r1 = r2 = r3 = S.val[C + sg];
+    } else {
+      const uint32_t base = sg * 32u + 31u;
+      const uint32_t m0 = fw & mk0, m1 = fw & mk1, m2 = fw & mk2, m3 = fw & mk3;
+      r0 = S.val[m0 ? base - __clz(m0) : C + sg];
+      r1 = S.val[m1 ? base - __clz(m1) : C + sg];
+      r2 = S.val[m2 ? base - __clz(m2) : C + sg];
+      r3 = S.val[m3 ? base - __clz(m3) : C + sg];
+    }
+    const uint32_t i0 = q << 2;
+    if (OALIGNED && i0 >= lb && i0 + 4 <= le) {
+      *reinterpret_cast<uint4*>(out + a0 + i0) = make_uint4(r0, r1, r2, r3);
+    } else {
+      if (i0 >= lb && i0 < le) out[a0 + i0] = r0;
+      if (i0 + 1 >= lb && i0 + 1 < le) out[a0 + i0 + 1] = r1;
+      if (i0 + 2 >= lb && i0 + 2 < le) out[a0 + i0 + 2] = r2;
+      if (i0 + 3 >= lb && i0 + 3 < le) out[a0 + i0 + 3] = r3;
+    }
+  }
+  __syncthreads();
+}
+
+// Persistent fill over the items appended to ctl->nitems.
+template <int NT, int CL2, bool OALIGNED>
+__global__ __launch_bounds__(NT) void k_fill(const uint32_t* __restrict__ H, uint32_t* __restrict__ out,
+                                             const Ctl* ctl, const FillItem* __restrict__ items,
+                                             uint32_t item_cap) {
+  __shared__ FillSmem<NT, CL2> S;
   // a failed invariant (reported as ST_INTERNAL) leaves items unwritten: fill nothing
   const uint32_t nitems = (ctl->status & ST_INTERNAL) ? 0u : (ctl->nitems < item_cap ? ctl->nitems : item_cap);
-
   for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
     const FillItem I = items[it];
-    const uint64_t p0 = I.p0, p1 = I.p1;
-    const uint64_t a0 = p0 & ~3ull;
-    const uint32_t lb = (uint32_t)(p0 - a0), le = (uint32_t)(p1 - a0);  // local [lb, le) within [0, C)
-    flag[tid] = 0;
-    __syncthreads();
-    // walk the item's bins, marking run starts inside [p0, p1)
-    uint64_t kb = I.k;
-    uint64_t run = I.o;  // start position of bin kb's run (<= p0)
-    while (run < p1 && kb <= I.klast) {  // uniform: run and kb are block-wide values
-      const uint64_t k0 = kb + 4ull * tid;
-      uint32_t h[4];
-      uint64_t tsum = 0;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        h[j] = k0 + j <= I.klast ? H[k0 + j] : 0u;
-        tsum += h[j];
-      }
-      uint64_t tot;
-      uint64_t ok = run + block_exclusive_sum<NT>(tsum, scan_tmp, &tot);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (h[j] > 0 && ok < p1) {
-          const uint32_t pos = ok <= p0 ? lb : (uint32_t)(ok - a0);
-          val[pos] = (uint32_t)(k0 + j);
-          atomicOr(&flag[pos >> 5], 1u << (pos & 31));
-        }
-        ok += h[j];
-      }
-      run += tot;
-      kb += 4ull * NT;
-    }
-    __syncthreads();
-    // carry the last mark forward.  Segment s = local positions [32s, 32s+32)
-    // with flag word flag[s]; val[C + s] = key of the last mark before segment s.
-    // Segment 0 always holds the item's first mark (at lb <= 3).
-    const uint32_t f = flag[tid];
-    int32_t inc = f ? (int32_t)tid : -1;
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-      const int32_t y = __shfl_up(inc, d, WAVE);
-      if ((int)lane >= d && y > inc) inc = y;
-    }
-    if (lane == WAVE - 1) last_idx[w] = inc;
-    int32_t ex_idx = __shfl_up(inc, 1, WAVE);
-    if (lane == 0) ex_idx = -1;
-    __syncthreads();
-    for (uint32_t q = 0; q < w; ++q) ex_idx = last_idx[q] > ex_idx ? last_idx[q] : ex_idx;
-    uint32_t cin = 0;
-    if (ex_idx >= 0) cin = val[ex_idx * 32 + (31 - __clz(flag[ex_idx]))];
-    val[C + tid] = cin;
-    __syncthreads();
-    // every output quad resolves its keys from its segment's flag word: the
-    // key at position p is the last mark at or before p in the segment, else
-    // the segment's carried key
-    const uint32_t nq = (le + 3) >> 2;
-    for (uint32_t q = tid; q < nq; q += NT) {
-      const uint32_t sg = q >> 3;
-      const uint32_t fw = flag[sg];
-      uint32_t r0, r1, r2, r3;
-      if (fw == 0) {
-        r0 = r1 = r2 = r3 = val[C + sg];
-      } else {
-        const uint32_t base = sg * 32u + 31u;
-        const uint32_t m0 = fw & mk0, m1 = fw & mk1, m2 = fw & mk2, m3 = fw & mk3;
-        r0 = val[m0 ? base - __clz(m0) : C + sg];
-        r1 = val[m1 ? base - __clz(m1) : C + sg];
-        r2 = val[m2 ? base - __clz(m2) : C + sg];
-        r3 = val[m3 ? base - __clz(m3) : C + sg];
-      }
-      const uint32_t i0 = q << 2;
-      if (OALIGNED && i0 >= lb && i0 + 4 <= le) {
-        *reinterpret_cast<uint4*>(out + a0 + i0) = make_uint4(r0, r1, r2, r3);
-      } else {
-        if (i0 >= lb && i0 < le) out[a0 + i0] = r0;
-        if (i0 + 1 >= lb && i0 + 1 < le) out[a0 + i0 + 1] = r1;
-        if (i0 + 2 >= lb && i0 + 2 < le) out[a0 + i0 + 2] = r2;
-        if (i0 + 3 >= lb && i0 + 3 < le) out[a0 + i0 + 3] = r3;
-      }
-    }
-    __syncthreads();
+    fill_item<NT, CL2, OALIGNED>(S, H, out, I);
   }
 }
 

@@ -73,6 +73,42 @@ def test_batched_argument_checks():
     assert ds._lib.dialsort_batched_workspace_bytes(d, 1) > 0
 
 
+def test_batch_host_checks():
+    d = (ds.dialsort_desc * 2)()
+    d[0] = ds.dialsort_desc(FAKE, 4, 8, FAKE + 4096, FAKE + 8192)
+    d[1] = ds.dialsort_desc(FAKE, 4, 1 << 32, FAKE + 4096 * 4, FAKE + 8192 * 4)
+    # the second array is outside the fused form (U > 1024 * 2^16)
+    assert ds._lib.dialsort_batched_workspace_bytes(d, 2) > 0
+    plan = ds.dialsort_batch_plan()
+    cfg = ds.batch_config(1024, 16, 1 << 20)
+    assert ds._lib.dialsort_batch_prepare(d, 2, ctypes.byref(cfg), FAKE, 1 << 40, None,
+                                          ctypes.byref(plan)) == ds.DIALSORT_EINVAL
+    # bad configurations
+    for bad in [ds.batch_config(256, 16, 1 << 20), ds.batch_config(1024, 13, 1 << 20),
+                ds.batch_config(1024, 17, 1 << 20), ds.batch_config(1024, 16, 3 << 18),
+                ds.batch_config(1024, 16, 1 << 23)]:
+        assert ds._lib.dialsort_batch_prepare(d, 1, ctypes.byref(bad), FAKE, 1 << 40, None,
+                                              ctypes.byref(plan)) == ds.DIALSORT_EINVAL
+    # misaligned keys are outside the fused form
+    d[0] = ds.dialsort_desc(FAKE + 4, 4, 8, FAKE + 4096, FAKE + 8192)
+    assert ds._lib.dialsort_batch_prepare(d, 1, ctypes.byref(cfg), FAKE, 1 << 40, None,
+                                          ctypes.byref(plan)) == ds.DIALSORT_EINVAL
+    # null plan / launch of an empty plan
+    assert ds._lib.dialsort_batch_prepare(d, 1, ctypes.byref(cfg), FAKE, 1 << 40, None, None) == ds.DIALSORT_EINVAL
+    assert ds._lib.dialsort_batch_launch(ctypes.byref(ds.dialsort_batch_plan()), None) == ds.DIALSORT_EINVAL
+
+
+def test_batched_workspace_covers_every_config():
+    d = (ds.dialsort_desc * 3)()
+    d[0] = ds.dialsort_desc(FAKE, 1 << 22, 1 << 20, FAKE, FAKE)
+    d[1] = ds.dialsort_desc(FAKE, 1 << 20, 1 << 16, FAKE, FAKE)
+    d[2] = ds.dialsort_desc(FAKE, 0, 1 << 10, FAKE, FAKE)
+    b = ds._lib.dialsort_batched_workspace_bytes(d, 3)
+    # at least the staging of the partitioned array (2 B per key) and the
+    # partial rows of the LDS array at the smallest chunk (4 copies of U)
+    assert b >= 2 * (1 << 22) + 4 * 4 * (1 << 16)
+
+
 def test_strerror():
     for s in range(6):
         assert ds.dialsort_strerror(s)

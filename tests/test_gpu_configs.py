@@ -73,3 +73,11 @@ def test_skewed_2pow28(ds):
     keys = w.hot_zipf(1 << 28, U, w.BASE_SEED + 2, "cuda")
     H_ref = check_sort(ds, keys, U, "skewed")
     assert H_ref.max() >= (1 << 27)
+
+
+def test_many_heavy_buckets(ds):
+    """U = 2^20 (16 buckets of 2^16 bins) with 70e6 uniform keys: every bucket
+    holds more than 2^22 keys, so each is counted and projected in two halves --
+    32 spans of fill items, which must all fit the item list."""
+    keys = w.uniform(70_000_000, 1 << 20, w.BASE_SEED + 9, "cuda")
+    check_sort(ds, keys, 1 << 20, "heavy buckets")
