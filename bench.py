@@ -182,6 +182,137 @@ def run_sort_workload(ds, hip, keys, U, K, W, mode="sort"):
     return res
 
 
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    i = min(len(xs) - 1, max(0, int(round(q / 100.0 * (len(xs) - 1)))))
+    return xs[i]
+
+
+def verify_batch(arrays):
+    ok = True
+    for (k, U, H, o) in arrays:
+        ok = ok and verify_sort(k, U, H, o)
+        if not ok:
+            break
+    return ok
+
+
+def run_batch_workload(ds, hip, count, K, W):
+    """The uneven batch: `count` independent arrays (n log-uniform in
+    [2^10, 2^22], U = 2^e with e uniform on 10..20, half uniform and half
+    Zipf(1.1)), sorted (a) by one autotuned fused persistent launch, captured
+    in a HIP graph and replayed, and (b) by the plain form, one launch sequence
+    per array (dialsort_sort_each).  Per-array latency is the time from the
+    submission of the batch to the completion of that array."""
+    import torch
+
+    import workloads as w
+
+    dev = torch.device("cuda:0")
+    specs = w.batch_spec(count=count)
+    arrays = []
+    for s in specs:
+        k = s.keys("cuda")
+        arrays.append((k, s.U, torch.empty(s.U, dtype=torch.int32, device=dev),
+                       torch.empty(s.n, dtype=torch.int32, device=dev)))
+    torch.cuda.synchronize()
+    nkeys = sum(s.n for s in specs)
+    algo = sum(8 * s.n + 8 * s.U for s in specs)
+    descs = ds.make_descs(arrays)
+    ws = ds.workspace(ds.dialsort_batched_workspace_bytes(descs, count), dev)
+    log(f"batch: {count} arrays, {nkeys} keys, workspace {ws.numel() / 2**30:.2f} GiB; autotuning")
+    t0 = time.perf_counter()
+    st, cfg = ds.dialsort_batch_autotune(descs, count, ws)
+    ds.check(st)
+    tune_s = time.perf_counter() - t0
+    st, plan = ds.dialsort_batch_prepare(descs, count, cfg, ws)
+    ds.check(st)
+    # fused: graph of the launch, replayed
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            ds.check(ds.dialsort_batch_launch(plan, stream=side))
+    torch.cuda.current_stream().wait_stream(side)
+    for _ in range(W):
+        g.replay()
+    torch.cuda.synchronize()
+    ev = hip.make(2 * K)
+    stream = torch.cuda.current_stream()
+    lib = hip.lib
+    lib.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    times = []
+    for i in range(K):
+        lib.hipEventRecord(ev[2 * i], ctypes.c_void_p(stream.cuda_stream))
+        g.replay()
+        lib.hipEventRecord(ev[2 * i + 1], ctypes.c_void_p(stream.cuda_stream))
+    torch.cuda.synchronize()
+    times = [hip.ms(ev[2 * i], ev[2 * i + 1]) for i in range(K)]
+    hip.free(ev)
+    st = ds.dialsort_status_sync(ws)
+    if st != ds.DIALSORT_OK:
+        raise RuntimeError(f"device status {st}")
+    st, arr_ms, launch_ms, unit_ms = ds.dialsort_batch_times(plan, count, units=True)
+    ds.check(st)
+    fused_ms = statistics.median(times)
+    lead = max(0.0, times[-1] - launch_ms)  # submission to the first unit
+    lat = [t + lead for t in arr_ms]
+    fused = {"ms": fused_ms, "best_ms": min(times), "keys_per_s": nkeys / (fused_ms * 1e-3),
+             "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99), "max_ms": max(lat),
+             "launch_ms_device": launch_ms,
+             "path_roofline": {"algo_bytes": algo, "achieved_GBps": algo / (fused_ms * 1e-3) / 1e9,
+                               "frac": algo / (fused_ms * 1e-3) / HBM_PEAK},
+             "config": {"block": cfg.block, "log2_width": cfg.log2_width, "chunk_keys": cfg.chunk_keys},
+             "units": plan.units, "grid": plan.grid, "autotune_s": tune_s,
+             "unit_wg_ms": {k: [round(v[0], 3), round(v[1], 3)] for k, v in unit_ms.items()}}
+    fused["verified"] = verify_batch(arrays)
+    log(f"batch fused: {fused_ms:.3f} ms, p50 {fused['p50_ms']:.3f} p99 {fused['p99_ms']:.3f} "
+        f"verified={fused['verified']} cfg={fused['config']}")
+    del g
+    # plain: one launch sequence per array, launch events for per-array completion
+    for (k, U, H, o) in arrays:
+        H.fill_(-1)
+        o.fill_(-1)
+    ncap = 6 * count + 8
+    evs = hip.make(ncap)
+    cnt = ctypes.c_uint32(0)
+    Kl = max(2, K // 2)
+    loop_ms, loop_lat = [], None
+    for it in range(1 + Kl):
+        ds.check(ds.dialsort_set_launch_events(evs, ncap, cnt))
+        ds.check(ds.dialsort_sort_each(descs, count, ws))
+        nl = cnt.value
+        names = [ds.dialsort_launch_name(i) for i in range(nl)]
+        ds.check(ds.dialsort_set_launch_events(None, 0, None))
+        torch.cuda.synchronize()
+        if it == 0:
+            continue  # warm-up
+        total = hip.ms(evs[0], evs[nl])
+        loop_ms.append(total)
+        ends = [i + 1 for i, nm in enumerate(names) if nm and "k_or_status" in nm]
+        loop_lat = [hip.ms(evs[0], evs[e]) for e in ends]
+    hip.free(evs)
+    st = ds.dialsort_status_sync(ws)
+    if st != ds.DIALSORT_OK:
+        raise RuntimeError(f"device status {st}")
+    lm = statistics.median(loop_ms)
+    plain = {"ms": lm, "keys_per_s": nkeys / (lm * 1e-3), "p50_ms": percentile(loop_lat, 50),
+             "p99_ms": percentile(loop_lat, 99), "launches": nl,
+             "path_roofline": {"algo_bytes": algo, "frac": algo / (lm * 1e-3) / HBM_PEAK}}
+    plain["verified"] = verify_batch(arrays)
+    log(f"batch per-array: {lm:.3f} ms, p50 {plain['p50_ms']:.3f} p99 {plain['p99_ms']:.3f} "
+        f"verified={plain['verified']}")
+    res = {"workload": f"{count} uneven arrays: n log-uniform in [2^10, 2^22], U = 2^e, e uniform on 10..20, "
+                       "half uniform, half Zipf(1.1)", "arrays": count, "keys": nkeys,
+           "fused_graph": fused, "per_array_launches": plain, "speedup": lm / fused_ms}
+    del arrays, ws
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(keys_dev, U, budget_s=12.0, max_runs=5):
     """The oracle as it stands, on this host, on the same keys (sequential C)."""
     import oracle
@@ -207,8 +338,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workloads", default="large,hist,plain,skewed")
+    ap.add_argument("--workloads", default="large,hist,plain,skewed,batch")
+    ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run a plain 256 MiB device copy (reference for profiler byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures the single-GPU hot path: this build runs on one GPU only "
@@ -225,6 +359,13 @@ def main():
     hip = HipEvents()
     K, W = args.steps, args.warmup
     todo = set(args.workloads.split(","))
+    if args.calib_copy:
+        a = torch.ones(64 << 20, dtype=torch.int32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     extra = {}
 
     n, U = 10**8, 1 << 24
@@ -274,6 +415,9 @@ def main():
         extra["skew_over_uniform"] = extra["skewed"]["keys_per_s"] / r["keys_per_s"]
         del k3u
         torch.cuda.empty_cache()
+
+    if "batch" in todo:
+        extra["batched"] = run_batch_workload(ds, hip, args.batch_count, max(K // 4, 3), 2)
 
     line = {
         "metric": METRIC,

@@ -188,11 +188,15 @@ dialsort_status dialsort_batch_default_config(const dialsort_desc *descs, uint32
 
 /* After a launch of `plan` has been enqueued: waits for `stream` and stores,
  * for the first `count` arrays, the time in ms from the start of the launch's
- * first work unit to the end of the array's last one (array_ms[i]), and in
+ * first work unit to the end of the array's last one (array_ms[i]), in
  * *launch_ms (if not NULL) the time to the end of the last unit of the whole
- * launch.  Read from the device wall clock. */
+ * launch, and in unit_ms[0..9] (if not NULL), for the unit types ingestion
+ * (LDS), ingestion (partition), row sum + scan, bucket, fill, the
+ * workgroup-milliseconds spent working (unit_ms[2t]) and waiting for other
+ * units (unit_ms[2t+1]).  Read from the device wall clock. */
 dialsort_status dialsort_batch_times(const dialsort_batch_plan *plan, hipStream_t stream,
-                                     double *array_ms, uint32_t count, double *launch_ms);
+                                     double *array_ms, uint32_t count, double *launch_ms,
+                                     double *unit_ms);
 
 /* Waits for `stream` and returns the device-detected status of the last call
  * that used ws (DIALSORT_OK, DIALSORT_ERANGE or DIALSORT_EOVERFLOW). */
@@ -212,7 +216,7 @@ dialsort_status dialsort_result_total(const void *ws, hipStream_t stream, uint64
 dialsort_status dialsort_set_launch_events(hipEvent_t *events, uint32_t cap, uint32_t *count);
 
 /* Kernel name of launch i of the last call on this host thread (NULL when i is
- * out of range).  Static storage. */
+ * out of range or not below max(cap, 64) of the hook).  Static storage. */
 const char *dialsort_launch_name(uint32_t i);
 
 /* Text for a status code (static storage). */

@@ -69,7 +69,8 @@ def _load() -> ctypes.CDLL:
         "dialsort_batch_default_config": (st, [ctypes.POINTER(dialsort_desc), ctypes.c_uint32,
                                                ctypes.POINTER(dialsort_batch_config)]),
         "dialsort_batch_times": (st, [ctypes.POINTER(dialsort_batch_plan), p, ctypes.POINTER(ctypes.c_double),
-                                      ctypes.c_uint32, ctypes.POINTER(ctypes.c_double)]),
+                                      ctypes.c_uint32, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double)]),
         "dialsort_status_sync": (st, [p, p]),
         "dialsort_result_total": (st, [p, p, ctypes.POINTER(u64)]),
         "dialsort_strerror": (ctypes.c_char_p, [st]),
@@ -198,12 +199,19 @@ def dialsort_batch_default_config(descs, count: int) -> Tuple[int, dialsort_batc
     return st, cfg
 
 
-def dialsort_batch_times(plan: dialsort_batch_plan, count: int, stream=None):
+UNIT_TYPES = ("hist", "partition", "rows", "bucket", "fill")
+
+
+def dialsort_batch_times(plan: dialsort_batch_plan, count: int, stream=None, units: bool = False):
     """(status, per-array completion times in ms, whole-launch time in ms) of the
-    last launch of `plan`."""
+    last launch of `plan`; with units=True a fourth element maps every unit type
+    to its (busy, waiting) workgroup-milliseconds."""
     arr = (ctypes.c_double * max(count, 1))()
     tot = ctypes.c_double(0.0)
-    st = _lib.dialsort_batch_times(ctypes.byref(plan), _stream(stream), arr, count, ctypes.byref(tot))
+    um = (ctypes.c_double * 10)()
+    st = _lib.dialsort_batch_times(ctypes.byref(plan), _stream(stream), arr, count, ctypes.byref(tot), um)
+    if units:
+        return st, list(arr[:count]), tot.value, {t: (um[2 * i], um[2 * i + 1]) for i, t in enumerate(UNIT_TYPES)}
     return st, list(arr[:count]), tot.value
 
 

@@ -21,7 +21,7 @@ using namespace dsh;
 namespace {
 
 constexpr uint32_t UNIT_KEYS = 1u << 18;  // target keys per A or B unit
-constexpr uint32_t FILL_PER = 8;          // item slots per fill unit
+constexpr uint32_t FILL_PER = 32;         // item slots per fill unit (shared by its waves)
 constexpr uint64_t BT_PACKED_CHUNK_MAX = 1ull << 22;
 
 struct Cfg {
@@ -97,17 +97,18 @@ void plan_batch(const dialsort_desc* d, uint32_t count, const Cfg& cfg, char* ba
       A.na = (uint32_t)cdiv(n, A.per);
       A.row_stride = A.na == 1 ? 0 : align_up(U, 64);
       A.nb = 1;
-      // one item per chunk of C positions plus, per piece of the universe, one
-      // more where a piece boundary splits a chunk
-      A.item_cap = (uint32_t)(cdiv(n, C) + 2 * cdiv(U, piece) + 2);
+      // one item per chunk of C positions plus one per projection tile and per
+      // piece of the universe, where a span boundary splits a chunk
+      A.item_cap = (uint32_t)(cdiv(n, C) + cdiv(U, PT_BINS) + 2 * cdiv(U, piece) + 2);
     } else {
       A.kind = BA_PART;
       A.B = (uint32_t)cdiv(U, W);
       A.na = (uint32_t)cdiv(n, PART_TK);
       A.bstride = (uint32_t)align_up(A.B + 1, 8);
       A.nb = A.B;
-      // every bucket is one span (two for a heavy bucket counted in halves)
-      A.item_cap = (uint32_t)(cdiv(n, C) + 2ull * A.B + 2);
+      // every projection tile is one span; every bucket one piece (two for a
+      // heavy bucket counted in halves)
+      A.item_cap = (uint32_t)(cdiv(n, C) + cdiv(U, PT_BINS) + 2ull * A.B + 2);
     }
     A.nf = A.item_cap ? (uint32_t)cdiv(A.item_cap, FILL_PER) : 0;
   }
@@ -416,7 +417,7 @@ dialsort_status dialsort_batch_autotune(const dialsort_desc* descs, uint32_t cou
 }
 
 dialsort_status dialsort_batch_times(const dialsort_batch_plan* plan, hipStream_t stream, double* array_ms,
-                                     uint32_t count, double* launch_ms) {
+                                     uint32_t count, double* launch_ms, double* unit_ms) {
   if (!plan || !plan->ws || (count && !array_ms) || count > plan->count) return DIALSORT_EINVAL;
   char* base = ws_base(plan->ws);
   const size_t off_states = align_up(ALIGN + (size_t)plan->count * sizeof(BArray), ALIGN);
@@ -432,6 +433,8 @@ dialsort_status dialsort_batch_times(const dialsort_batch_plan* plan, hipStream_
   for (uint32_t i = 0; i < count; ++i)
     array_ms[i] = st[i].t_done >= ctl.total ? (double)(st[i].t_done - ctl.total) * tick_ms : 0.0;
   if (launch_ms) *launch_ms = ctl.limit >= ctl.total ? (double)(ctl.limit - ctl.total) * tick_ms : 0.0;
+  if (unit_ms)
+    for (int i = 0; i < 10; ++i) unit_ms[i] = (double)ctl.prof[i] * tick_ms;
   return DIALSORT_OK;
 }
 

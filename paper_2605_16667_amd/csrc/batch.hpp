@@ -36,7 +36,7 @@
 namespace ds {
 
 constexpr uint32_t BT_BMAX = 1024;  // buckets per array on the fused path
-constexpr int BT_CL2 = 14;          // fill item span: 16384 positions
+constexpr int BT_CL2 = 11;          // fill item span: 2048 positions (one wave)
 
 enum BatchKind : uint32_t { BA_EMPTY = 0, BA_LDS = 1, BA_PART = 2 };
 enum UnitType : uint32_t { UT_HIST = 0, UT_PART = 1, UT_ROWS = 2, UT_BUCKET = 3, UT_FILL = 4 };
@@ -82,28 +82,44 @@ struct BUnit {
 
 // Launch-wide control, in the first 256 bytes of the batch workspace (Ctl).
 // Ctl::tile_ticket is the unit ticket; Ctl::total receives the launch's start
-// time (wall clock) and Ctl::limit the time its last unit finished.
+// time (wall clock) and Ctl::limit the time its last unit finished;
+// Ctl::prof[2 t] / [2 t + 1] sum, over the units of type t, the clock ticks
+// their workgroups spent working / waiting for other units.
 
 template <int NT, int LOG2W>
 union BatchSmem {
   BinSmem<NT, LOG2W> bin;
   PartSmem<NT, BT_BMAX> part;
-  FillSmem<NT, BT_CL2> fill;
+  WaveFillSmem<BT_CL2> fill[NT / WAVE];
 };
 
-__device__ __forceinline__ void unit_wait(const uint32_t* counter, uint32_t need) {
+// Wait until *counter >= need.  Thread 0 polls with relaxed agent-scope loads
+// (they read the coherent value without invalidating any cache), then one
+// acquire fence makes everything published before the counter's increments
+// visible to the whole workgroup (it invalidates this CU's L1 and this XCD's
+// L2, which every wave of the workgroup reads through).  Returns the clock
+// ticks spent waiting (thread 0).
+__device__ __forceinline__ uint64_t unit_wait(const uint32_t* counter, uint32_t need) {
+  uint64_t waited = 0;
   if (threadIdx.x == 0) {
-    while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need)
-      __builtin_amdgcn_s_sleep(4);
+    if (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+      const uint64_t t0 = wall_clock64();
+      while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need)
+        __builtin_amdgcn_s_sleep(8);
+      waited = wall_clock64() - t0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
-  __threadfence();
+  return waited;
 }
 
-// Publish the unit's stores and add `add` to counter; returns the counter's
-// old value in thread 0 (0 elsewhere).
+// Publish the unit's stores and add `add` to counter: every wave waits until
+// its own stores are acknowledged, then (after the barrier) thread 0 adds with
+// release semantics at agent scope, which writes this XCD's L2 back first.
+// Returns the counter's old value in thread 0 (0 elsewhere).
 __device__ __forceinline__ uint32_t unit_signal(uint32_t* counter, uint32_t add) {
-  __threadfence();
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   uint32_t old = 0;
   if (threadIdx.x == 0) old = __hip_atomic_fetch_add(counter, add, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -152,23 +168,24 @@ __device__ __forceinline__ void unit_part(BatchSmem<NT, LOG2W>& S, const BArray*
 }
 
 template <int NT, int LOG2W>
-__device__ __forceinline__ void unit_rows(BatchSmem<NT, LOG2W>& S, const BArray* __restrict__ Ap, BState* st,
+__device__ __forceinline__ uint64_t unit_rows(BatchSmem<NT, LOG2W>& S, const BArray* __restrict__ Ap, BState* st,
                                        uint32_t* status, Ctl* ctl) {
   const BArray& A = *Ap;
-  unit_wait(&st->a_done, A.na);
+  const uint64_t waited = unit_wait(&st->a_done, A.na);
   // several chunks: sum their rows into H; one chunk wrote H itself; no keys: H := 0
   uint32_t* H_out = A.na != 1 ? A.H : nullptr;
   rows_body<NT, LOG2W, true>(S.bin, A.rows, A.na, A.row_stride, H_out, (uint32_t)A.U, status, &st->nitems, A.items,
                              A.item_cap, BT_CL2);
   const uint32_t old = unit_signal(&st->b_done, 1);
   if (threadIdx.x == 0 && A.nf == 0 && old + 1 == A.nb) mark_done(st, ctl);
+  return waited;
 }
 
 template <int NT, int LOG2W>
-__device__ __forceinline__ void unit_bucket(BatchSmem<NT, LOG2W>& S, const BArray* __restrict__ Ap, BState* st,
+__device__ __forceinline__ uint64_t unit_bucket(BatchSmem<NT, LOG2W>& S, const BArray* __restrict__ Ap, BState* st,
                                          uint32_t first, uint32_t count, uint32_t* status, Ctl* ctl) {
   const BArray& A = *Ap;
-  unit_wait(&st->a_done, A.na);
+  const uint64_t waited = unit_wait(&st->a_done, A.na);
   for (uint32_t b = first; b < first + count; ++b) {
     bucket_body<NT, LOG2W, 3, true, true>(S.bin, A.staging, A.seg, A.bstride, A.na, A.U, A.H, status, &st->nitems,
                                           A.items, A.item_cap, BT_CL2, b);
@@ -176,32 +193,37 @@ __device__ __forceinline__ void unit_bucket(BatchSmem<NT, LOG2W>& S, const BArra
   }
   const uint32_t old = unit_signal(&st->b_done, count);
   if (threadIdx.x == 0 && A.nf == 0 && old + count == A.nb) mark_done(st, ctl);
+  return waited;
 }
 
 template <int NT, int LOG2W>
-__device__ __forceinline__ void unit_fill(BatchSmem<NT, LOG2W>& S, const BArray* __restrict__ Ap, BState* st,
+__device__ __forceinline__ uint64_t unit_fill(BatchSmem<NT, LOG2W>& S, const BArray* __restrict__ Ap, BState* st,
                                        uint32_t first, uint32_t stride, uint32_t* status, Ctl* ctl) {
   const BArray& A = *Ap;
-  unit_wait(&st->b_done, A.nb);
+  const uint64_t waited = unit_wait(&st->b_done, A.nb);
   const uint32_t ni = st->nitems < A.item_cap ? st->nitems : A.item_cap;
   // a failed invariant (ST_INTERNAL) may leave items unwritten: fill nothing
   const bool failed = (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ST_INTERNAL) != 0;
   if (!failed) {
-    for (uint32_t j = first; j < ni; j += stride) {
+    // wave w takes slots first + stride * (w + NW m)
+    constexpr uint32_t NW = NT / WAVE;
+    const uint32_t w = threadIdx.x / WAVE;
+    for (uint64_t j = first + (uint64_t)stride * w; j < ni; j += (uint64_t)stride * NW) {
       const FillItem I = A.items[j];
       // an item always lies inside its array; anything else is a broken
       // invariant, reported instead of written
       const bool valid = I.k <= I.klast && I.klast < A.U && I.o <= I.p0 && I.p0 < I.p1 && I.p1 <= A.n &&
                          I.p1 - (I.p0 & ~3ull) <= (1ull << BT_CL2);
       if (!valid) {
-        if (threadIdx.x == 0) atomicOr(status, ST_INTERNAL);
+        if (lane_id() == 0) atomicOr(status, ST_INTERNAL);
         continue;
       }
-      fill_item<NT, BT_CL2, true>(S.fill, A.H, A.out, I);
+      wave_fill_item<BT_CL2, true>(S.fill[w], A.H, A.out, I);
     }
   }
   const uint32_t old = unit_signal(&st->c_done, 1);
   if (threadIdx.x == 0 && old + 1 == A.nf) mark_done(st, ctl);
+  return waited;
 }
 
 template <int NT, int LOG2W>
@@ -224,15 +246,22 @@ __global__ __launch_bounds__(NT) void k_batch(const BArray* __restrict__ arrays,
     const BUnit u = units[t];
     const BArray* A = arrays + u.array;
     BState* st = states + u.array;
+    const uint64_t t0 = wall_clock64();
+    uint64_t waited = 0;
     switch (u.type) {
       case UT_HIST: unit_hist<NT, LOG2W>(S, A, st, u.first, u.count, status); break;
       case UT_PART: unit_part<NT, LOG2W>(S, A, st, u.first, u.count, status); break;
-      case UT_ROWS: unit_rows<NT, LOG2W>(S, A, st, status, ctl); break;
-      case UT_BUCKET: unit_bucket<NT, LOG2W>(S, A, st, u.first, u.count, status, ctl); break;
-      case UT_FILL: unit_fill<NT, LOG2W>(S, A, st, u.first, u.count, status, ctl); break;
+      case UT_ROWS: waited = unit_rows<NT, LOG2W>(S, A, st, status, ctl); break;
+      case UT_BUCKET: waited = unit_bucket<NT, LOG2W>(S, A, st, u.first, u.count, status, ctl); break;
+      case UT_FILL: waited = unit_fill<NT, LOG2W>(S, A, st, u.first, u.count, status, ctl); break;
       default:
         if (tid == 0) atomicOr(status, ST_INTERNAL);
         break;
+    }
+    if (tid == 0 && u.type <= UT_FILL) {
+      const uint64_t busy = wall_clock64() - t0 - waited;
+      __hip_atomic_fetch_add(&ctl->prof[2 * u.type], busy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&ctl->prof[2 * u.type + 1], waited, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }

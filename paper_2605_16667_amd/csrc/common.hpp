@@ -20,7 +20,9 @@ struct Ctl {
   uint64_t total;        // sum(H), saturated at SAT_MAX
   uint64_t limit;        // number of output positions that are written
   uint32_t nitems;       // fill items appended by the scan
-  uint32_t pad[55];
+  uint32_t pad0;
+  uint64_t prof[16];     // batched launch: per unit type, workgroup clock ticks busy / waiting
+  uint32_t pad[22];
 };
 static_assert(sizeof(Ctl) == 256, "control block is 256 bytes");
 

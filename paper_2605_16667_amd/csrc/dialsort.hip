@@ -27,13 +27,13 @@ using namespace dsh;
 
 namespace dsh {
 thread_local int g_last_hip_error = 0;
-thread_local LaunchLog g_log;
+thread_local LaunchLog g_log{nullptr, 0, nullptr, 0, std::vector<const char*>(64, nullptr)};
 }  // namespace dsh
 
 namespace {
 
 constexpr int FILL_NT = 256;
-constexpr int FILL_CL2 = 13;  // chunk of 8192 positions
+constexpr int FILL_CL2 = 11;  // fill items of at most 2048 positions (one wave each)
 constexpr int SCAN_NT = 256;
 
 enum Kind { K_EMPTY, K_LDS32S, K_LDS32, K_LDS16, K_PART, K_GLOBAL, K_NONE };
@@ -109,9 +109,11 @@ Layout plan(uint64_t n, uint64_t U, int mode) {
   if (L.scan) {
     L.off_tile = off; off = align_up(off + L.scan_tiles * 8, ALIGN);
     // one item per chunk of output positions, plus one per span boundary that
-    // splits a chunk: spans are the scan tiles, or the buckets of the
-    // partitioned path (two spans for a bucket counted in two halves)
-    L.item_cap = (L.kind == K_PART ? 2ull * L.B : L.scan_tiles) + cdiv(L.limit, 1ull << FILL_CL2) + 2;
+    // splits a chunk: spans are the scan tiles, or on the partitioned path the
+    // projection tiles of PT_BINS bins and the buckets (two pieces for a bucket
+    // counted in two halves)
+    L.item_cap = (L.kind == K_PART ? 2ull * L.B + cdiv(U, PT_BINS) : L.scan_tiles) +
+                 cdiv(L.limit, 1ull << FILL_CL2) + 2;
     L.off_items = off; off = align_up(off + L.item_cap * sizeof(FillItem), ALIGN);
   }
   if (L.rows_in_ws) {
@@ -226,7 +228,8 @@ dialsort_status launch_fill(const uint32_t* H, uint32_t* out, char* base, const 
   Ctl* ctl = (Ctl*)base;
   const FillItem* items = (const FillItem*)(base + L.off_items);
   if (L.limit == 0) return DIALSORT_OK;
-  const uint32_t grid = (uint32_t)std::min<uint64_t>(L.item_cap, 256 * 8);
+  // one resident round of workgroups (4 per CU at 256 threads), or fewer
+  const uint32_t grid = (uint32_t)std::min<uint64_t>(cdiv(L.item_cap, FILL_NT / WAVE), 256 * 4);
   const uint32_t icap = (uint32_t)std::min<uint64_t>(L.item_cap, 0xFFFFFFF0ull);
   if (aligned16(out))
     DS_LAUNCH((k_fill<FILL_NT, FILL_CL2, true>), dim3(grid), dim3(FILL_NT), s, H, out, ctl, items, icap);
@@ -357,11 +360,12 @@ dialsort_status dialsort_set_launch_events(hipEvent_t* events, uint32_t cap, uin
   g_log.ev = events;
   g_log.cap = events ? cap : 0;
   g_log.count = events ? count : nullptr;
+  if (g_log.names.size() < std::max<uint32_t>(g_log.cap, 64)) g_log.names.resize(std::max<uint32_t>(g_log.cap, 64));
   return DIALSORT_OK;
 }
 
 const char* dialsort_launch_name(uint32_t i) {
-  return i < g_log.n && i < 64 ? g_log.names[i] : nullptr;
+  return i < g_log.n && i < g_log.names.size() ? g_log.names[i] : nullptr;
 }
 
 dialsort_status dialsort_status_sync(const void* ws, hipStream_t stream) {

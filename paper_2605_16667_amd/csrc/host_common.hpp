@@ -8,6 +8,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/dialsort.h"
 
 namespace dsh {
@@ -27,13 +29,13 @@ struct LaunchLog {
   uint32_t cap = 0;
   uint32_t* count = nullptr;
   uint32_t n = 0;
-  const char* names[64];
+  std::vector<const char*> names;  // kernel of launch i (the first max(cap, 64) launches)
 };
 extern thread_local LaunchLog g_log;
 
 inline void log_launch(const char* name, hipStream_t s) {
   if (g_log.ev && g_log.n + 1 < g_log.cap) (void)hipEventRecord(g_log.ev[g_log.n], s);
-  if (g_log.n < 64) g_log.names[g_log.n] = name;
+  if (g_log.n < g_log.names.size()) g_log.names[g_log.n] = name;
   ++g_log.n;
 }
 

@@ -168,7 +168,7 @@ __global__ __launch_bounds__(P1_NT) void k_partition(const uint32_t* __restrict_
 // ---------------------------------------------------------------------------
 
 constexpr int BK_SQ = 4;            // 16-byte quads (8 keys each) per lane per gather step
-constexpr uint32_t BK_LRCAP = 512;  // long-run list entries
+constexpr uint32_t BK_LRCAP = 256;  // long-run list entries
 constexpr uint64_t BK_PACKMAX = 1ull << 22;  // keys per bucket on the packed path
 
 // LDS state of a bucket (or of a row sum): counters of one bucket of W = 2^LOG2W
@@ -184,8 +184,8 @@ struct BinSmem {
   uint32_t evflag[PACKED ? 65536 / 32 : 1];
   uint32_t ev[PACKED ? LDS16_EVCAP : 1];
   uint32_t nev;
-  uint32_t lr_k[BK_LRCAP], lr_n[BK_LRCAP];
-  uint64_t lr_o[BK_LRCAP], lr_c[BK_LRCAP];
+  uint32_t lr_k[BK_LRCAP], lr_n[BK_LRCAP], lr_l[BK_LRCAP], lr_i[BK_LRCAP];
+  uint64_t lr_o[BK_LRCAP], lr_c[BK_LRCAP], lr_e[BK_LRCAP];
   uint64_t red[NT / WAVE + 1];
   uint32_t n, item0;
 };
@@ -196,10 +196,12 @@ enum GatherMode { GM_PACKED, GM_HALF, GM_DIRECT };
 // into the packed 16-bit fields (W = 2^16).  GM_HALF: 32-bit counters for the
 // keys whose relative value lies in half `half` (x >> 15 == half, W = 2^16).
 // GM_DIRECT: 32-bit counters for all keys (W <= 2^15).
-// Each lane owns whole segments (tiles tid, tid + NT, ...): it loads its segment
-// as aligned 16-byte quads of 8 keys, BK_SQ quads per step, and prefetches the
-// bounds of its next segment while it works on the current one, so the
-// segment-table loads never sit on the critical path.
+// Lanes own whole segments: with T >= NT tiles, lane tid takes tiles tid,
+// tid + NT, ...; with fewer tiles, lps = NT / T (rounded down to a power of
+// two) lanes share each tile's segment, sub-lane s taking its quads s, s + lps,
+// ....  Each lane loads its quads as aligned 16-byte quads of 8 keys, BK_SQ
+// quads per step, and prefetches the bounds of its next segment while it works
+// on the current one, so the segment-table loads never sit on the critical path.
 template <int NT, int LOG2W, int AGG, GatherMode GM>
 __device__ __forceinline__ void bucket_gather(BinSmem<NT, LOG2W>& S, const uint16_t* __restrict__ staging,
                                               const uint16_t* __restrict__ seg, uint32_t bstride, uint32_t T,
@@ -211,9 +213,14 @@ __device__ __forceinline__ void bucket_gather(BinSmem<NT, LOG2W>& S, const uint1
   WaveAgg st;
   const uint32_t tid = threadIdx.x;
   const uint4* sq = reinterpret_cast<const uint4*>(staging);
-  // cursor: tile t, segment [s16, e16) as tile-local key indices (< 2^13), next
+  uint32_t lps = 1;  // lanes per segment (uniform)
+  while (lps < (uint32_t)NT && (uint64_t)T * lps * 2 <= (uint64_t)NT) lps *= 2;
+  const uint32_t sub = tid & (lps - 1);
+  const uint32_t tstep = NT / lps;
+  const uint32_t qstep = 8u * lps;  // key index distance between a lane's quads
+  // cursor: tile t, segment [s16, e16) as tile-local key indices (<= 2^13), next
   // quad at tile-local key index ql (a multiple of 8); 32-bit arithmetic only
-  uint32_t t = tid;
+  uint32_t t = tid / lps;
   uint32_t ns = 0, ne = 0;  // prefetched bounds of tile t
   if (t < T) { const uint16_t* row = seg + (uint64_t)t * bstride; ns = row[b]; ne = row[b + 1]; }
   uint32_t s16 = 0, e16 = 0, ql = 0;
@@ -221,13 +228,13 @@ __device__ __forceinline__ void bucket_gather(BinSmem<NT, LOG2W>& S, const uint1
     // a segment never leaves its tile's slice of staging
     e16 = ne < (uint32_t)PART_TK ? ne : (uint32_t)PART_TK;
     s16 = ns < e16 ? ns : e16;
-    ql = s16 & ~7u;
-    const uint32_t tn = t + NT;
+    ql = (s16 & ~7u) + 8u * sub;
+    const uint32_t tn = t + tstep;
     if (tn < T) { const uint16_t* row = seg + (uint64_t)tn * bstride; ns = row[b]; ne = row[b + 1]; }
   };
   auto advance = [&]() {
     while (t < T && ql >= e16) {
-      t += NT;
+      t += tstep;
       if (t < T) open();
     }
   };
@@ -236,7 +243,7 @@ __device__ __forceinline__ void bucket_gather(BinSmem<NT, LOG2W>& S, const uint1
 #pragma unroll
     for (int j = 0; j < BK_SQ; ++j) {
       d[j] = make_uint4(0, 0, 0, 0);
-      if (has && ql + 8u * j < e16) d[j] = sq[q0 + j];
+      if (has && ql + qstep * j < e16) d[j] = sq[q0 + (uint64_t)lps * j];
     }
   };
   if (t < T) open();
@@ -248,7 +255,7 @@ __device__ __forceinline__ void bucket_gather(BinSmem<NT, LOG2W>& S, const uint1
   for (;;) {
     if (!__any(has)) break;
     // issue the next step's loads before working on this one
-    ql += 8u * BK_SQ;
+    ql += qstep * BK_SQ;
     advance();
     const bool hasn = t < T;
     uint4 dn[BK_SQ];
@@ -256,7 +263,7 @@ __device__ __forceinline__ void bucket_gather(BinSmem<NT, LOG2W>& S, const uint1
 #pragma unroll
     for (int j = 0; j < BK_SQ; ++j) {
       // valid keys of this quad: tile-local indices [cs, ce) within [q, q + 8)
-      const int32_t q = (int32_t)(cq + 8u * j);
+      const int32_t q = (int32_t)(cq + qstep * j);
       const int32_t lob = max((int32_t)cs - q, 0), hib = min((int32_t)ce - q, 8);
       uint32_t qm = hib > lob ? ((1u << hib) - 1u) & ~((1u << lob) - 1u) : 0u;
       qm = has ? qm : 0u;
@@ -347,8 +354,10 @@ __device__ __forceinline__ uint64_t block_sum(SM& S, uint64_t x) {
 
 // Append fill items for this thread's bins: the thread owns NB consecutive bins
 // starting at relative bin j0, whose counts come from count(j) and sum to len;
-// o0 is the absolute position where its stretch starts.  The span of the bucket part being
-// emitted is [sp0, sp1); item0 is the index of its first item.
+// o0 is the absolute position where its stretch starts.  The thread's bins lie
+// in a span of output positions [sp0, sp1) (the run of a group of bins ending
+// at bin klast) whose items start at index item0; threads may belong to
+// different spans.
 template <int NT, uint32_t NB, typename SM, typename CountF>
 __device__ __forceinline__ void emit_items(SM& S, FillItem* __restrict__ items, uint32_t item0, int CL2,
                                            uint64_t sp0, uint64_t sp1, uint64_t hb, uint32_t j0, uint32_t nb_valid,
@@ -417,21 +426,23 @@ __device__ __forceinline__ void emit_items(SM& S, FillItem* __restrict__ items, 
       if (pending) {
         const uint32_t slot = atomicAdd(&S.n, 1u);
         if (slot < BK_LRCAP) {
+          // the entry carries its own span: spans differ between threads
           S.lr_o[slot] = o; S.lr_c[slot] = lo; S.lr_n[slot] = (uint32_t)cntc; S.lr_k[slot] = (uint32_t)(hb + i);
+          S.lr_i[slot] = item0 + (uint32_t)(lo - cb); S.lr_e[slot] = sp1; S.lr_l[slot] = klast;
           pending = false;
         }
       }
       __syncthreads();
       const uint32_t nl = S.n < BK_LRCAP ? S.n : BK_LRCAP;
       for (uint32_t e2 = 0; e2 < nl; ++e2) {
-        const uint64_t oo = S.lr_o[e2], cc = S.lr_c[e2], nn = S.lr_n[e2];
-        const uint32_t kk = S.lr_k[e2];
+        const uint64_t oo = S.lr_o[e2], cc = S.lr_c[e2], nn = S.lr_n[e2], ee = S.lr_e[e2];
+        const uint32_t kk = S.lr_k[e2], ii = S.lr_i[e2], ll = S.lr_l[e2];
         for (uint64_t x = tid; x < nn; x += NT) {
           const uint64_t c = cc + x;
           FillItem it;
-          it.p0 = c << CL2; it.p1 = ((c + 1) << CL2) < sp1 ? ((c + 1) << CL2) : sp1;
-          it.o = oo; it.k = kk; it.klast = klast;
-          items[item0 + (c - cb)] = it;
+          it.p0 = c << CL2; it.p1 = ((c + 1) << CL2) < ee ? ((c + 1) << CL2) : ee;
+          it.o = oo; it.k = kk; it.klast = ll;
+          items[ii + (uint32_t)x] = it;
         }
       }
       __syncthreads();
@@ -459,17 +470,24 @@ __device__ __forceinline__ uint32_t reserve_items(SM& S, uint32_t* status, uint3
   return S.item0;
 }
 
+// Bins per projection tile: fill items never walk more bins than this.
+constexpr uint32_t PT_BINS = 1024;
+
 // Project the counts held in S: the piece covers relative bins [0, pcnt) of
 // absolute first bin hb, counts at S.s[pw(i)] (uint32) or from the packed
 // fields (PACKED; ne = logged events), and its run starts at output position
 // base.  Each thread owns NB consecutive bins; a block scan of their sums tells
-// it where its stretch starts and it appends the fill items that start there.
-// Returns the piece's total.
+// it where its stretch starts.  Groups of PT_BINS bins (G = PT_BINS / NB
+// threads, inside one wave) form tiles, each with its own span of output
+// positions, so that no fill item walks more than PT_BINS bins; a second block
+// scan numbers the tiles' items.  Returns the piece's total.
 template <int NT, uint32_t NB, bool PACKED, typename SM>
 __device__ __forceinline__ uint64_t project_piece(SM& S, uint32_t* status, uint32_t* nitems, FillItem* items,
                                                   uint32_t item_cap, int CL2, uint64_t base, uint64_t hb,
                                                   uint32_t pcnt, uint32_t klast, uint32_t ne) {
-  const uint32_t tid = threadIdx.x;
+  constexpr uint32_t G = PT_BINS / NB < (uint32_t)WAVE ? (PT_BINS / NB > 0 ? PT_BINS / NB : 1) : (uint32_t)WAVE;
+  static_assert((G & (G - 1)) == 0, "tiles are a power of two of threads");
+  const uint32_t tid = threadIdx.x, lane = lane_id();
   const uint32_t j0 = tid * NB;
   uint32_t sum = 0;
   if constexpr (PACKED) {
@@ -498,14 +516,41 @@ __device__ __forceinline__ uint64_t project_piece(SM& S, uint32_t* status, uint3
   uint64_t tot;
   const uint64_t pre = block_exclusive_sum<NT>((uint64_t)sum, S.red, &tot);
   if (tot == 0) return 0;
-  const uint32_t item0 = reserve_items(S, status, nitems, base, base + tot, item_cap, CL2);
+  // the thread's tile: threads [lead, lead + G) of its wave
+  const uint32_t lead = lane & ~(G - 1);
+  const uint64_t ts = base + (uint64_t)__shfl((long long)pre, (int)lead, WAVE);
+  uint64_t tsum = sum;
+#pragma unroll
+  for (uint32_t d = 1; d < G; d <<= 1) tsum += (uint64_t)__shfl_xor((long long)tsum, (int)d, WAVE);
+  const uint64_t te = ts + tsum;
+  const uint64_t C = 1ull << CL2;
+  const uint64_t tnit = te > ts ? ((te + C - 1) >> CL2) - (ts >> CL2) : 0;
+  uint64_t all_items;
+  const uint64_t toff = block_exclusive_sum<NT>((uint64_t)(lane == lead ? tnit : 0ull), S.red, &all_items);
+  const uint64_t tile_off = (uint64_t)__shfl((long long)toff, (int)lead, WAVE);
+  const uint32_t tfirst = (tid - (lane - lead)) * NB;  // first relative bin of the tile
+  const uint32_t tklast = (uint32_t)(hb + (tfirst + G * NB < pcnt ? tfirst + G * NB : pcnt) - 1);
+  (void)klast;
+  // reserve all the piece's items at once (thread 0) and broadcast the first
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t i0 = 0;
+    if (all_items) {
+      i0 = atomicAdd(nitems, (uint32_t)all_items);
+      if ((uint64_t)i0 + all_items > item_cap) { atomicOr(status, ST_INTERNAL); i0 = 0xFFFFFFFFu; }
+    }
+    S.item0 = i0;
+  }
+  __syncthreads();
+  const uint32_t item0 = S.item0;
   if (item0 == 0xFFFFFFFFu) return tot;
+  const uint32_t my0 = item0 + (uint32_t)tile_off;
   if constexpr (PACKED) {
     auto count = [&](uint32_t i) -> uint32_t { return packed_count(S, i, ne); };
-    emit_items<NT, NB>(S, items, item0, CL2, base, base + tot, hb, j0, pcnt, base + pre, sum, klast, count);
+    emit_items<NT, NB>(S, items, my0, CL2, ts, te, hb, j0, pcnt, base + pre, sum, tklast, count);
   } else {
     auto count = [&](uint32_t i) -> uint32_t { return S.s[pw(i)]; };
-    emit_items<NT, NB>(S, items, item0, CL2, base, base + tot, hb, j0, pcnt, base + pre, sum, klast, count);
+    emit_items<NT, NB>(S, items, my0, CL2, ts, te, hb, j0, pcnt, base + pre, sum, tklast, count);
   }
   return tot;
 }

@@ -16,10 +16,10 @@
 //   C positions and at most one tile of bins, whatever the skew (a hot key of
 //   10^8 copies becomes 10^8 / C items) and however sparse H is.
 //
-// k_fill: persistent workgroups take items.  An item walks its bins, marks the
-//   position where each run begins, and fills its positions by carrying every
-//   marked key forward to the next mark; interior stores are 16-byte coalesced
-//   stores.  Zero bins emit nothing (the presence test of Sec. 2, Table
+// k_fill: persistent waves take items, each wave on its own.  An item walks
+//   its bins, marks the position where each run begins, and fills its
+//   positions by carrying every marked key forward to the next mark; interior
+//   stores are 16-byte coalesced stores.  Zero bins emit nothing (the presence test of Sec. 2, Table
 //   "tab:comparison", is not an order comparison).
 #pragma once
 
@@ -252,45 +252,44 @@ __global__ __launch_bounds__(NT) void k_scan(const uint32_t* __restrict__ rows, 
   }
 }
 
-// Fill of one item by NT threads.  C = 2^CL2 local positions, one 32-bit flag
-// word per 32 positions (NFW = C/32 <= NT words, held by threads tid < NFW).
-// Local position i is output position a0 + i with a0 = p0 rounded down to a
-// multiple of 4; an item always fits in [0, C) of that frame.
-template <int NT, int CL2>
-struct FillSmem {
+// Fill of one item by ONE wavefront, with no workgroup barrier: every wave of
+// a workgroup takes its own items.  C = 2^CL2 local positions per item (C/32
+// <= 64 flag words, one per lane).  Local position i is output position a0 + i
+// with a0 = p0 rounded down to a multiple of 4; an item always fits in [0, C)
+// of that frame.  The wave's LDS: val[0, C) holds the key marked at each run
+// start, val[C + s] the key carried into 32-position segment s (the last mark
+// before it), flag[s] the marks of segment s.  LDS operations of one wave take
+// effect in program order, so no fence is needed between the phases.
+template <int CL2>
+struct WaveFillSmem {
   static constexpr uint32_t C = 1u << CL2;
   static constexpr uint32_t NFW = C / 32;
-  // val[0, C): the key marked at each run start; val[C + s]: the key carried
-  // into segment s (the last mark before it)
   __align__(16) uint32_t val[C + NFW];
   uint32_t flag[NFW];
-  uint64_t scan_tmp[NT / WAVE + 1];
-  int32_t last_idx[NT / WAVE];
 };
 
-template <int NT, int CL2, bool OALIGNED>
-__device__ __forceinline__ void fill_item(FillSmem<NT, CL2>& S, const uint32_t* __restrict__ H,
-                                          uint32_t* __restrict__ out, const FillItem& I) {
+template <int CL2, bool OALIGNED>
+__device__ __forceinline__ void wave_fill_item(WaveFillSmem<CL2>& S, const uint32_t* __restrict__ H,
+                                               uint32_t* __restrict__ out, const FillItem& I) {
   constexpr uint32_t C = 1u << CL2;
   constexpr uint32_t NFW = C / 32;
-  static_assert(NFW <= NT && NT % 8 == 0, "one flag word per thread at most");
-  const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / WAVE;
-  // output quads q = tid + k*NT all sit at the same offset b0 = 4 (q mod 8)
+  static_assert(NFW <= (uint32_t)WAVE, "one flag word per lane at most");
+  const uint32_t lane = lane_id();
+  // output quads q = lane + 64 r all sit at the same offset b0 = 4 (q mod 8)
   // inside their 32-position segment: the masks of positions <= b0 + e are fixed
-  const uint32_t b0 = (tid & 7u) * 4u;
+  const uint32_t b0 = (lane & 7u) * 4u;
   const uint32_t mk0 = 0xFFFFFFFFu >> (31u - b0), mk1 = 0xFFFFFFFFu >> (30u - b0);
   const uint32_t mk2 = 0xFFFFFFFFu >> (29u - b0), mk3 = 0xFFFFFFFFu >> (28u - b0);
 
   const uint64_t p0 = I.p0, p1 = I.p1;
   const uint64_t a0 = p0 & ~3ull;
   const uint32_t lb = (uint32_t)(p0 - a0), le = (uint32_t)(p1 - a0);  // local [lb, le) within [0, C)
-  if (tid < NFW) S.flag[tid] = 0;
-  __syncthreads();
-  // walk the item's bins, marking run starts inside [p0, p1)
+  if (lane < NFW) S.flag[lane] = 0;
+  // walk the item's bins, 4 per lane per round, marking run starts in [p0, p1)
   uint64_t kb = I.k;
   uint64_t run = I.o;  // start position of bin kb's run (<= p0)
-  while (run < p1 && kb <= I.klast) {  // uniform: run and kb are block-wide values
-    const uint64_t k0 = kb + 4ull * tid;
+  while (run < p1 && kb <= I.klast) {  // wave-uniform
+    const uint64_t k0 = kb + 4ull * lane;
     uint32_t h[4];
     uint64_t tsum = 0;
 #pragma unroll
@@ -298,8 +297,9 @@ __device__ __forceinline__ void fill_item(FillSmem<NT, CL2>& S, const uint32_t* 
       h[j] = k0 + j <= I.klast ? H[k0 + j] : 0u;
       tsum += h[j];
     }
-    uint64_t tot;
-    uint64_t ok = run + block_exclusive_sum<NT>(tsum, S.scan_tmp, &tot);
+    const uint64_t inc = wave_inclusive_sum(tsum);
+    const uint64_t tot = __shfl(inc, WAVE - 1, WAVE);
+    uint64_t ok = run + inc - tsum;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       if (h[j] > 0 && ok < p1) {
@@ -310,35 +310,29 @@ __device__ __forceinline__ void fill_item(FillSmem<NT, CL2>& S, const uint32_t* 
       ok += h[j];
     }
     run += tot;
-    kb += 4ull * NT;
+    kb += 4ull * WAVE;
   }
-  __syncthreads();
-  // carry the last mark forward.  Segment s = local positions [32s, 32s+32)
-  // with flag word flag[s]; val[C + s] = key of the last mark before segment s.
-  // Segment 0 always holds the item's first mark (at lb <= 3).
-  const uint32_t f = tid < NFW ? S.flag[tid] : 0u;
-  int32_t inc = f ? (int32_t)tid : -1;
+  // carry the last mark forward: lane s owns segment s; segment 0 always holds
+  // the item's first mark (at lb <= 3)
+  const uint32_t f = lane < NFW ? S.flag[lane] : 0u;
+  int32_t inc = f ? (int32_t)lane : -1;
 #pragma unroll
   for (int d = 1; d < WAVE; d <<= 1) {
     const int32_t y = __shfl_up(inc, d, WAVE);
     if ((int)lane >= d && y > inc) inc = y;
   }
-  if (lane == WAVE - 1) S.last_idx[w] = inc;
   int32_t ex_idx = __shfl_up(inc, 1, WAVE);
   if (lane == 0) ex_idx = -1;
-  __syncthreads();
-  for (uint32_t q = 0; q < w; ++q) ex_idx = S.last_idx[q] > ex_idx ? S.last_idx[q] : ex_idx;
-  if (tid < NFW) {
+  if (lane < NFW) {
     uint32_t cin = 0;
     if (ex_idx >= 0) cin = S.val[ex_idx * 32 + (31 - __clz(S.flag[ex_idx]))];
-    S.val[C + tid] = cin;
+    S.val[C + lane] = cin;
   }
-  __syncthreads();
-  // every output quad resolves its keys from its segment's flag word: the
-  // key at position p is the last mark at or before p in the segment, else
-  // the segment's carried key
+  // every output quad resolves its keys from its segment's flag word: the key
+  // at position p is the last mark at or before p in the segment, else the
+  // segment's carried key
   const uint32_t nq = (le + 3) >> 2;
-  for (uint32_t q = tid; q < nq; q += NT) {
+  for (uint32_t q = lane; q < nq; q += WAVE) {
     const uint32_t sg = q >> 3;
     const uint32_t fw = S.flag[sg];
     uint32_t r0, r1, r2, r3;
@@ -362,20 +356,22 @@ __device__ __forceinline__ void fill_item(FillSmem<NT, CL2>& S, const uint32_t* 
       if (i0 + 3 >= lb && i0 + 3 < le) out[a0 + i0 + 3] = r3;
     }
   }
-  __syncthreads();
 }
 
-// Persistent fill over the items appended to ctl->nitems.
+// Persistent fill over the items appended to ctl->nitems: every wave of every
+// workgroup takes items on its own.
 template <int NT, int CL2, bool OALIGNED>
 __global__ __launch_bounds__(NT) void k_fill(const uint32_t* __restrict__ H, uint32_t* __restrict__ out,
                                              const Ctl* ctl, const FillItem* __restrict__ items,
                                              uint32_t item_cap) {
-  __shared__ FillSmem<NT, CL2> S;
+  constexpr uint32_t NW = NT / WAVE;
+  __shared__ WaveFillSmem<CL2> S[NW];
+  const uint32_t w = threadIdx.x / WAVE;
   // a failed invariant (reported as ST_INTERNAL) leaves items unwritten: fill nothing
   const uint32_t nitems = (ctl->status & ST_INTERNAL) ? 0u : (ctl->nitems < item_cap ? ctl->nitems : item_cap);
-  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+  for (uint32_t it = blockIdx.x * NW + w; it < nitems; it += gridDim.x * NW) {
     const FillItem I = items[it];
-    fill_item<NT, CL2, OALIGNED>(S, H, out, I);
+    wave_fill_item<CL2, OALIGNED>(S[w], H, out, I);
   }
 }
 
