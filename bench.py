@@ -35,6 +35,7 @@ if ROOT not in sys.path:
 
 METRIC = "sorted keys/s at n=100M,U=2^24 (% HBM roofline); batched p50/p99 latency"
 HBM_PEAK = 8.0e12  # MI355X HBM3E, bytes/s
+SERVE_SLOTS = 4    # batches (or lone requests) the server keeps on the device at once
 
 
 def log(msg):
@@ -313,6 +314,118 @@ def run_batch_workload(ds, hip, count, K, W):
     return res
 
 
+def run_serve_workload(ds, hip, num, loads, batch_cfg, arena_gib=8):
+    """The served stream: `num` requests with Poisson arrivals, n log-uniform
+    in [2^12, 2^24], U uniform over {2^12, 2^16, 2^20, 2^24}, uniform or
+    Zipf(1.2) keys (p = 1/2), all keys already in device memory.  For every
+    load L the arrival rate is L / (mean serial service time).  Baseline: serial
+    plain sorts, first in first out, one dialsort_sort at a time; served: the
+    continuous-batching server.  Latency = arrival to completion."""
+    import torch
+
+    import workloads as w
+
+    dev = torch.device("cuda:0")
+    probe = w.request_stream(num, 1.0)
+    keys = [r.spec.keys("cuda") for r in probe]
+    torch.cuda.synchronize()
+    nkeys = sum(r.spec.n for r in probe)
+    nmax = max(r.spec.n for r in probe)
+    Umax = max(r.spec.U for r in probe)
+    H = torch.empty(Umax, dtype=torch.int32, device=dev)
+    out = torch.empty(nmax, dtype=torch.int32, device=dev)
+    ws = ds.workspace(max(ds.dialsort_workspace_bytes(r.spec.n, r.spec.U, ds.DIALSORT_MODE_SORT) for r in probe), dev)
+    # serial service times (each sort alone, warm)
+    for i in range(min(8, num)):
+        ds.check(ds.dialsort_sort(keys[i], probe[i].spec.U, H, out, ws))
+    torch.cuda.synchronize()
+    svc = []
+    for k, r in zip(keys, probe):
+        t = time.perf_counter()
+        ds.check(ds.dialsort_sort(k, r.spec.U, H, out, ws))
+        torch.cuda.synchronize()
+        svc.append(time.perf_counter() - t)
+    mean_svc = statistics.mean(svc)
+    arena = torch.empty(arena_gib << 30, dtype=torch.uint8, device=dev)
+    res = {"workload": f"{num} requests, Poisson arrivals at L x (1 / mean serial service time), "
+                       "n log-uniform in [2^12, 2^24], U in {2^12, 2^16, 2^20, 2^24}, uniform or Zipf(1.2)",
+           "requests": num, "keys": nkeys, "mean_serial_service_ms": mean_svc * 1e3,
+           "server_config": {"block": batch_cfg.block, "log2_width": batch_cfg.log2_width,
+                             "chunk_keys": batch_cfg.chunk_keys, "max_inflight": SERVE_SLOTS, "max_batch": 256,
+                             "arena_gib": arena_gib},
+           "loads": {}}
+    for load in loads:
+        rate = load / mean_svc
+        reqs = w.request_stream(num, rate)
+        arrivals = [r.arrival for r in reqs]
+        log(f"serve L={load}: {num} requests, {nkeys} keys, mean serial service {mean_svc * 1e3:.3f} ms, "
+            f"rate {rate:.1f}/s")
+        # serial FIFO replay
+        lat = []
+        t0 = time.perf_counter()
+        for k, r, a in zip(keys, reqs, arrivals):
+            while time.perf_counter() - t0 < a:
+                pass
+            ds.check(ds.dialsort_sort(k, r.spec.U, H, out, ws))
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - t0 - a) * 1e3)
+        span = time.perf_counter() - t0
+        st = ds.dialsort_status_sync(ws)
+        if st != ds.DIALSORT_OK:
+            raise RuntimeError(f"device status {st}")
+        serial = {"keys_per_s": nkeys / span, "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+                  "mean_ms": statistics.mean(lat), "span_s": span}
+        # served replay
+        st, srv = ds.dialsort_server_create(arena, ds.server_config(batch_cfg, SERVE_SLOTS, 256))
+        ds.check(st)
+        ids, outstanding, infos = [], [], {}
+
+        def retire_front():
+            while outstanding:
+                st_, info = ds.dialsort_server_info(srv, outstanding[0])
+                ds.check(st_)
+                if info.state != ds.DIALSORT_REQ_DONE:
+                    break
+                if info.status != ds.DIALSORT_OK:
+                    raise RuntimeError(f"request status {info.status}")
+                infos[outstanding[0]] = (info.submit_ms, info.launch_ms, info.done_ms)
+                ds.check(ds.dialsort_server_release(srv, outstanding[0]))
+                outstanding.pop(0)
+
+        try:
+            t0 = time.perf_counter()
+            for k, r, a in zip(keys, reqs, arrivals):
+                while time.perf_counter() - t0 < a:
+                    ds.check(ds.dialsort_server_poll(srv)[0])
+                    retire_front()
+                st, rid = ds.dialsort_server_submit(srv, k, r.spec.U)
+                ds.check(st)
+                ids.append(rid)
+                outstanding.append(rid)
+                ds.check(ds.dialsort_server_poll(srv)[0])
+            while outstanding:
+                ds.check(ds.dialsort_server_poll(srv)[0])
+                retire_front()
+                if outstanding:
+                    ds.check(ds.dialsort_server_drain(srv))
+        finally:
+            ds.check(ds.dialsort_server_destroy(srv))
+        slat = [infos[i][2] - infos[i][0] for i in ids]
+        launches = sorted(set(round(infos[i][1], 6) for i in ids))
+        first_sub = min(infos[i][0] for i in ids)
+        last_done = max(infos[i][2] for i in ids)
+        served = {"keys_per_s": nkeys / ((last_done - first_sub) * 1e-3), "p50_ms": percentile(slat, 50),
+                  "p99_ms": percentile(slat, 99), "mean_ms": statistics.mean(slat), "launches": len(launches),
+                  "mean_requests_per_launch": num / max(len(launches), 1)}
+        log(f"serve L={load}: serial p50 {serial['p50_ms']:.3f} p99 {serial['p99_ms']:.3f} ms "
+            f"{serial['keys_per_s'] / 1e9:.1f} Gkeys/s; served p50 {served['p50_ms']:.3f} p99 {served['p99_ms']:.3f} ms "
+            f"{served['keys_per_s'] / 1e9:.1f} Gkeys/s, {len(launches)} launches")
+        res["loads"][str(load)] = {"rate_per_s": rate, "serial_plain": serial, "served": served}
+    del H, out, ws, arena, keys
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(keys_dev, U, budget_s=12.0, max_runs=5):
     """The oracle as it stands, on this host, on the same keys (sequential C)."""
     import oracle
@@ -338,7 +451,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workloads", default="large,hist,plain,skewed,batch")
+    ap.add_argument("--workloads", default="large,hist,plain,skewed,batch,serve")
+    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--serve-loads", default="0.7,1.5,3.0",
+                    help="arrival rates, as multiples of 1 / (mean serial service time)")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
@@ -416,8 +532,16 @@ def main():
         del k3u
         torch.cuda.empty_cache()
 
+    batch_cfg = None
     if "batch" in todo:
         extra["batched"] = run_batch_workload(ds, hip, args.batch_count, max(K // 4, 3), 2)
+        c = extra["batched"]["fused_graph"]["config"]
+        batch_cfg = ds.batch_config(c["block"], c["log2_width"], c["chunk_keys"])
+    if "serve" in todo:
+        if batch_cfg is None:
+            batch_cfg = ds.batch_config(1024, 16, 1 << 20)
+        loads = [float(x) for x in args.serve_loads.split(",")]
+        extra["served"] = run_serve_workload(ds, hip, args.serve_requests, loads, batch_cfg)
 
     line = {
         "metric": METRIC,

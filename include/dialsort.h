@@ -198,6 +198,85 @@ dialsort_status dialsort_batch_times(const dialsort_batch_plan *plan, hipStream_
                                      double *array_ms, uint32_t count, double *launch_ms,
                                      double *unit_ms);
 
+/* ---- Serving: continuous batching of sort requests ----------------------------
+ *
+ * A server runs sort requests of mixed n and U that arrive over time.  It owns
+ * a device arena given by the caller and admits requests first-in first-out
+ * by their HBM footprint: a request's H (U counters) and output (n keys) are
+ * reserved in the arena at admission and stay resident there until the caller
+ * releases the request, so later work can read the canonical histogram
+ * (Sec. 3.3) without moving it.  Each poll retires finished batches, admits
+ * what fits, and launches every admitted request (up to max_batch) as one
+ * fused batched launch on a free stream; up to max_inflight batches run on the
+ * device at once, on separate streams, so work that arrives while others run
+ * overlaps with them.  A request's H and output equal dialsort_sort's for the
+ * same keys, whatever else is in its batch.  Keys are read from the caller's
+ * device buffer (16-byte aligned) and must stay unchanged until the request is
+ * done.  A server is used from one host thread at a time (calls are
+ * serialised by a lock).  Serving is not part of the paper; it runs the
+ * method of Sec. 3.3 for many clients. */
+
+typedef struct dialsort_server dialsort_server;
+
+typedef struct dialsort_server_config {
+    dialsort_batch_config batch;  /* configuration of every fused launch */
+    uint32_t max_inflight;        /* batches on the device at once: 1..8 (one stream each) */
+    uint32_t max_batch;           /* requests per batch, >= 1 */
+} dialsort_server_config;
+
+#define DIALSORT_REQ_QUEUED 0   /* waiting for arena space */
+#define DIALSORT_REQ_ADMITTED 1 /* H and output reserved, not launched yet */
+#define DIALSORT_REQ_RUNNING 2  /* in a batch on the device */
+#define DIALSORT_REQ_DONE 3     /* H and output written (see status) */
+
+typedef struct dialsort_request_info {
+    uint32_t state;          /* DIALSORT_REQ_* */
+    dialsort_status status;  /* once done: OK, or ERANGE if a key is >= U */
+    uint32_t *H;             /* once admitted: the request's U counters in the arena */
+    uint32_t *out;           /* once admitted: its n output keys in the arena */
+    uint64_t n, U;
+    double submit_ms;        /* times in ms since dialsort_server_create: submission, */
+    double launch_ms;        /* launch of its batch (host clock) and end of its batch */
+    double done_ms;          /* on the device (event clock) */
+} dialsort_request_info;
+
+/* Arena bytes a request of this size holds from admission to release. */
+size_t dialsort_server_footprint(uint64_t n, uint64_t U);
+
+/* Creates a server on the current device.  arena: device memory owned by the
+ * caller, kept allocated until dialsort_server_destroy returns.  Creates
+ * max_inflight streams and events; pinned host staging is allocated on first
+ * use and grown when a batch's tables need more. */
+dialsort_status dialsort_server_create(void *arena, size_t arena_bytes, const dialsort_server_config *config,
+                                       dialsort_server **server);
+
+/* Waits for every batch on the device, then frees the server. */
+dialsort_status dialsort_server_destroy(dialsort_server *server);
+
+/* Queues a request; nothing is enqueued on the device before the next poll.
+ * EINVAL: bad arguments, or U above what the fused launch of the configuration
+ * takes; EOVERFLOW: n > 2^32 - 1; EWORKSPACE: the request cannot fit in the
+ * arena even alone. */
+dialsort_status dialsort_server_submit(dialsort_server *server, const uint32_t *keys, uint64_t n, uint64_t U,
+                                       uint64_t *id);
+
+/* One non-blocking step: retire, admit, launch.  *pending (if not NULL)
+ * receives the number of submitted requests not done yet. */
+dialsort_status dialsort_server_poll(dialsort_server *server, uint32_t *pending);
+
+/* Polls until every submitted request is done, waiting on the device in
+ * between.  EWORKSPACE if nothing is running and nothing can start because the
+ * arena is held by done requests that were not released. */
+dialsort_status dialsort_server_drain(dialsort_server *server);
+
+/* State, status, buffers and times of a request (EINVAL for an unknown or
+ * released id). */
+dialsort_status dialsort_server_info(dialsort_server *server, uint64_t id, dialsort_request_info *info);
+
+/* Returns a done request's H and output to the arena (EINVAL if the request is
+ * unknown or not done). */
+dialsort_status dialsort_server_release(dialsort_server *server, uint64_t id);
+
 /* Waits for `stream` and returns the device-detected status of the last call
  * that used ws (DIALSORT_OK, DIALSORT_ERANGE or DIALSORT_EOVERFLOW). */
 dialsort_status dialsort_status_sync(const void *ws, hipStream_t stream);

@@ -47,6 +47,19 @@ class dialsort_batch_plan(ctypes.Structure):
                 ("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t)]
 
 
+class dialsort_server_config(ctypes.Structure):
+    _fields_ = [("batch", dialsort_batch_config), ("max_inflight", ctypes.c_uint32), ("max_batch", ctypes.c_uint32)]
+
+
+class dialsort_request_info(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_uint32), ("status", ctypes.c_int), ("H", ctypes.c_void_p), ("out", ctypes.c_void_p),
+                ("n", ctypes.c_uint64), ("U", ctypes.c_uint64), ("submit_ms", ctypes.c_double),
+                ("launch_ms", ctypes.c_double), ("done_ms", ctypes.c_double)]
+
+
+DIALSORT_REQ_QUEUED, DIALSORT_REQ_ADMITTED, DIALSORT_REQ_RUNNING, DIALSORT_REQ_DONE = range(4)
+
+
 def _load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2605_16667_amd.build.build()")
@@ -71,6 +84,14 @@ def _load() -> ctypes.CDLL:
         "dialsort_batch_times": (st, [ctypes.POINTER(dialsort_batch_plan), p, ctypes.POINTER(ctypes.c_double),
                                       ctypes.c_uint32, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_double)]),
+        "dialsort_server_footprint": (sz, [u64, u64]),
+        "dialsort_server_create": (st, [p, sz, ctypes.POINTER(dialsort_server_config), ctypes.POINTER(p)]),
+        "dialsort_server_destroy": (st, [p]),
+        "dialsort_server_submit": (st, [p, p, u64, u64, ctypes.POINTER(u64)]),
+        "dialsort_server_poll": (st, [p, ctypes.POINTER(ctypes.c_uint32)]),
+        "dialsort_server_drain": (st, [p]),
+        "dialsort_server_info": (st, [p, u64, ctypes.POINTER(dialsort_request_info)]),
+        "dialsort_server_release": (st, [p, u64]),
         "dialsort_status_sync": (st, [p, p]),
         "dialsort_result_total": (st, [p, p, ctypes.POINTER(u64)]),
         "dialsort_strerror": (ctypes.c_char_p, [st]),
@@ -88,7 +109,9 @@ _lib = _load()
 EXPORTED = ("dialsort_workspace_bytes", "dialsort_histogram", "dialsort_reconstruct", "dialsort_sort",
             "dialsort_batched_workspace_bytes", "dialsort_sort_batched", "dialsort_sort_each",
             "dialsort_batch_prepare", "dialsort_batch_launch", "dialsort_batch_autotune",
-            "dialsort_batch_default_config", "dialsort_batch_times", "dialsort_status_sync",
+            "dialsort_batch_default_config", "dialsort_batch_times", "dialsort_server_footprint",
+            "dialsort_server_create", "dialsort_server_destroy", "dialsort_server_submit", "dialsort_server_poll",
+            "dialsort_server_drain", "dialsort_server_info", "dialsort_server_release", "dialsort_status_sync",
             "dialsort_result_total", "dialsort_strerror", "dialsort_last_hip_error",
             "dialsort_set_launch_events", "dialsort_launch_name")
 
@@ -213,6 +236,62 @@ def dialsort_batch_times(plan: dialsort_batch_plan, count: int, stream=None, uni
     if units:
         return st, list(arr[:count]), tot.value, {t: (um[2 * i], um[2 * i + 1]) for i, t in enumerate(UNIT_TYPES)}
     return st, list(arr[:count]), tot.value
+
+
+def dialsort_server_footprint(n: int, U: int) -> int:
+    return _lib.dialsort_server_footprint(n, U)
+
+
+def server_config(batch: dialsort_batch_config, max_inflight: int = 2, max_batch: int = 256) -> dialsort_server_config:
+    return dialsort_server_config(batch, max_inflight, max_batch)
+
+
+def dialsort_server_create(arena: torch.Tensor, config: dialsort_server_config) -> Tuple[int, Optional[int]]:
+    h = ctypes.c_void_p()
+    st = _lib.dialsort_server_create(_ptr(arena), arena.numel() * arena.element_size(), ctypes.byref(config),
+                                     ctypes.byref(h))
+    return st, h.value
+
+
+def dialsort_server_destroy(server: int) -> int:
+    return _lib.dialsort_server_destroy(server)
+
+
+def dialsort_server_submit(server: int, keys: torch.Tensor, U: int) -> Tuple[int, int]:
+    rid = ctypes.c_uint64(0)
+    st = _lib.dialsort_server_submit(server, _ptr(keys), keys.numel(), U, ctypes.byref(rid))
+    return st, rid.value
+
+
+def dialsort_server_poll(server: int) -> Tuple[int, int]:
+    pending = ctypes.c_uint32(0)
+    st = _lib.dialsort_server_poll(server, ctypes.byref(pending))
+    return st, pending.value
+
+
+def dialsort_server_drain(server: int) -> int:
+    return _lib.dialsort_server_drain(server)
+
+
+def dialsort_server_info(server: int, rid: int) -> Tuple[int, dialsort_request_info]:
+    info = dialsort_request_info()
+    st = _lib.dialsort_server_info(server, rid, ctypes.byref(info))
+    return st, info
+
+
+def dialsort_server_release(server: int, rid: int) -> int:
+    return _lib.dialsort_server_release(server, rid)
+
+
+def arena_view(arena: torch.Tensor, ptr: int, count: int) -> torch.Tensor:
+    """The int32 view of `count` uint32 values at device address ptr inside the
+    byte tensor `arena` (a request's H or output in a server arena)."""
+    off = int(ptr) - arena.data_ptr()
+    if count == 0:
+        return arena[:0].view(torch.int32)
+    if off < 0 or off % 4 or off + 4 * count > arena.numel():
+        raise ValueError("address outside the arena")
+    return arena[off:off + 4 * count].view(torch.int32)
 
 
 def dialsort_status_sync(ws: torch.Tensor, stream=None) -> int:

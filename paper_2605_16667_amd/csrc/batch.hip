@@ -13,21 +13,17 @@
 
 #include "../../include/dialsort.h"
 #include "batch.hpp"
+#include "batch_host.hpp"
 #include "host_common.hpp"
 
 using namespace ds;
 using namespace dsh;
 
-namespace {
+namespace dsb {
 
 constexpr uint32_t UNIT_KEYS = 1u << 18;  // target keys per A or B unit
 constexpr uint32_t FILL_PER = 32;         // item slots per fill unit (shared by its waves)
 constexpr uint64_t BT_PACKED_CHUNK_MAX = 1ull << 22;
-
-struct Cfg {
-  uint32_t nt = 1024, log2w = 16;
-  uint64_t chunk = 1ull << 20;
-};
 
 bool cfg_valid(const dialsort_batch_config& c) {
   const bool nt = c.block == 512 || c.block == 1024;
@@ -61,12 +57,6 @@ bool fused_ok(const dialsort_desc& d, const Cfg& c) {
   if (d.n && (!aligned16(d.keys) || !aligned16(d.out))) return false;
   return true;
 }
-
-struct Planned {
-  std::vector<BArray> arr;
-  std::vector<BUnit> units;
-  size_t off_arrays = 0, off_states = 0, off_units = 0, bytes = 0;
-};
 
 // Lay out the batch in a workspace based at `base` (null: sizes only):
 // [Ctl][arrays][states][units][per-array rows / staging / segments / items].
@@ -224,13 +214,28 @@ int occupancy_t() {
 }
 
 // Resident workgroups per CU of the fused kernel, per configuration.
-int occupancy(const Cfg& c) {
+int occupancy_query(const Cfg& c) {
   if (c.nt == 512 && c.log2w == 14) return occupancy_t<512, 14>();
   if (c.nt == 512 && c.log2w == 15) return occupancy_t<512, 15>();
   if (c.nt == 512 && c.log2w == 16) return occupancy_t<512, 16>();
   if (c.nt == 1024 && c.log2w == 14) return occupancy_t<1024, 14>();
   if (c.nt == 1024 && c.log2w == 15) return occupancy_t<1024, 15>();
   return occupancy_t<1024, 16>();
+}
+
+std::mutex g_occ_mu;
+std::map<std::pair<int, uint32_t>, int> g_occ;
+
+int occupancy(const Cfg& c) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const uint32_t key = c.nt * 32u + c.log2w;
+  std::lock_guard<std::mutex> lk(g_occ_mu);
+  auto it = g_occ.find({dev, key});
+  if (it != g_occ.end()) return it->second;
+  const int v = occupancy_query(c);
+  g_occ[{dev, key}] = v;
+  return v;
 }
 
 // Autotune cache: per device, batch shape -> best configuration.
@@ -262,25 +267,16 @@ Cfg default_cfg(const dialsort_desc* d, uint32_t count) {
   return Cfg{};
 }
 
-dialsort_status prepare(const dialsort_desc* d, uint32_t count, const Cfg& cfg, void* ws, size_t ws_bytes,
-                        hipStream_t s, dialsort_batch_plan* plan) {
-  if (count && !d) return DIALSORT_EINVAL;
-  for (uint32_t i = 0; i < count; ++i) {
-    DS_TRY(check_desc(d[i]));
-    if (!fused_ok(d[i], cfg)) return DIALSORT_EINVAL;
-  }
-  if (!ws) return DIALSORT_EWORKSPACE;
-  char* base = ws_base(ws);
-  Planned P;
-  plan_batch(d, count, cfg, base, P);
-  if (ws_bytes < P.bytes) return DIALSORT_EWORKSPACE;
-  if (P.units.size() >= 0xFFFFFFF0ull) return DIALSORT_EINVAL;
-  // tables: arrays, states (cleared again by every launch), units
-  std::vector<char> host(P.off_units + P.units.size() * sizeof(BUnit) - P.off_arrays, 0);
-  std::memcpy(host.data(), P.arr.data(), P.arr.size() * sizeof(BArray));
-  std::memcpy(host.data() + (P.off_units - P.off_arrays), P.units.data(), P.units.size() * sizeof(BUnit));
-  DS_HIP(hipMemcpyAsync(base + P.off_arrays, host.data(), host.size(), hipMemcpyHostToDevice, s));
-  DS_HIP(hipStreamSynchronize(s));
+size_t table_bytes(const Planned& P) { return P.off_units + P.units.size() * sizeof(BUnit) - P.off_arrays; }
+
+void write_tables(const Planned& P, char* host) {
+  std::memset(host, 0, table_bytes(P));
+  std::memcpy(host, P.arr.data(), P.arr.size() * sizeof(BArray));
+  std::memcpy(host + (P.off_units - P.off_arrays), P.units.data(), P.units.size() * sizeof(BUnit));
+}
+
+dialsort_status make_plan(const Planned& P, uint32_t count, const Cfg& cfg, void* ws, size_t ws_bytes,
+                          dialsort_batch_plan* plan) {
   int dev = 0, cus = 0;
   DS_HIP(hipGetDevice(&dev));
   DS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -296,6 +292,27 @@ dialsort_status prepare(const dialsort_desc* d, uint32_t count, const Cfg& cfg, 
   return DIALSORT_OK;
 }
 
+dialsort_status prepare(const dialsort_desc* d, uint32_t count, const Cfg& cfg, void* ws, size_t ws_bytes,
+                        hipStream_t s, dialsort_batch_plan* plan) {
+  if (count && !d) return DIALSORT_EINVAL;
+  for (uint32_t i = 0; i < count; ++i) {
+    DS_TRY(check_desc(d[i]));
+    if (!fused_ok(d[i], cfg)) return DIALSORT_EINVAL;
+  }
+  if (!ws) return DIALSORT_EWORKSPACE;
+  char* base = ws_base(ws);
+  Planned P;
+  plan_batch(d, count, cfg, base, P);
+  if (ws_bytes < P.bytes) return DIALSORT_EWORKSPACE;
+  if (P.units.size() >= 0xFFFFFFF0ull) return DIALSORT_EINVAL;
+  // tables: arrays, states (cleared again by every launch), units
+  std::vector<char> host(table_bytes(P));
+  write_tables(P, host.data());
+  DS_HIP(hipMemcpyAsync(base + P.off_arrays, host.data(), host.size(), hipMemcpyHostToDevice, s));
+  DS_HIP(hipStreamSynchronize(s));
+  return make_plan(P, count, cfg, ws, ws_bytes, plan);
+}
+
 size_t fused_workspace_bytes(const dialsort_desc* d, uint32_t count) {
   size_t mx = 0;
   for (const Cfg& c : candidates()) {
@@ -309,7 +326,9 @@ size_t fused_workspace_bytes(const dialsort_desc* d, uint32_t count) {
   return mx;
 }
 
-}  // namespace
+}  // namespace dsb
+
+using namespace dsb;
 
 extern "C" {
 

@@ -69,7 +69,8 @@ struct BState {
   uint32_t nitems;   // fill items appended
   uint32_t c_done;   // C units finished
   uint64_t t_done;   // wall clock when the array's last unit finished
-  uint64_t pad;
+  uint32_t status;   // the array's own status bits (ST_*)
+  uint32_t pad;
 };
 static_assert(sizeof(BState) == 32, "state is 32 bytes");
 
@@ -126,11 +127,16 @@ __device__ __forceinline__ uint32_t unit_signal(uint32_t* counter, uint32_t add)
   return old;
 }
 
-// The array is complete when its last unit finishes: stamp the time.
+// The array is complete when its last unit finishes: stamp the time and fold
+// its status into the batch's.
 __device__ __forceinline__ void mark_done(BState* st, Ctl* ctl) {
   const uint64_t now = wall_clock64();
   st->t_done = now;
   __hip_atomic_fetch_max(&ctl->limit, now, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // every other unit of the array has signalled: see their status bits
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  const uint32_t bits = __hip_atomic_load(&st->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (bits) atomicOr(&ctl->status, bits);
 }
 
 // Unit bodies.
@@ -232,7 +238,6 @@ __global__ __launch_bounds__(NT) void k_batch(const BArray* __restrict__ arrays,
   __shared__ BatchSmem<NT, LOG2W> S;
   __shared__ uint32_t s_ticket;
   const uint32_t tid = threadIdx.x;
-  uint32_t* status = &ctl->status;
   for (;;) {
     __syncthreads();
     if (tid == 0) {
@@ -246,6 +251,7 @@ __global__ __launch_bounds__(NT) void k_batch(const BArray* __restrict__ arrays,
     const BUnit u = units[t];
     const BArray* A = arrays + u.array;
     BState* st = states + u.array;
+    uint32_t* status = &st->status;
     const uint64_t t0 = wall_clock64();
     uint64_t waited = 0;
     switch (u.type) {
@@ -255,7 +261,7 @@ __global__ __launch_bounds__(NT) void k_batch(const BArray* __restrict__ arrays,
       case UT_BUCKET: waited = unit_bucket<NT, LOG2W>(S, A, st, u.first, u.count, status, ctl); break;
       case UT_FILL: waited = unit_fill<NT, LOG2W>(S, A, st, u.first, u.count, status, ctl); break;
       default:
-        if (tid == 0) atomicOr(status, ST_INTERNAL);
+        if (tid == 0) atomicOr(&ctl->status, ST_INTERNAL);
         break;
     }
     if (tid == 0 && u.type <= UT_FILL) {
@@ -267,7 +273,7 @@ __global__ __launch_bounds__(NT) void k_batch(const BArray* __restrict__ arrays,
 }
 
 // Clears the launch control block and the per-array states.
-__global__ void k_batch_init(Ctl* ctl, BState* states, uint32_t count) {
+static __global__ void k_batch_init(Ctl* ctl, BState* states, uint32_t count) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < sizeof(Ctl) / 4) reinterpret_cast<uint32_t*>(ctl)[i] = 0;
   const uint32_t nw = count * (uint32_t)(sizeof(BState) / 4);

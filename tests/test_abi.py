@@ -109,6 +109,24 @@ def test_batched_workspace_covers_every_config():
     assert b >= 2 * (1 << 22) + 4 * 4 * (1 << 16)
 
 
+def test_server_host_checks():
+    bad = ds.server_config(ds.batch_config(1024, 16, 1 << 20), 0, 8)  # max_inflight 0
+    h = ctypes.c_void_p()
+    assert ds._lib.dialsort_server_create(FAKE, 1 << 30, ctypes.byref(bad), ctypes.byref(h)) == ds.DIALSORT_EINVAL
+    bad = ds.server_config(ds.batch_config(1024, 16, 1 << 20), 9, 8)
+    assert ds._lib.dialsort_server_create(FAKE, 1 << 30, ctypes.byref(bad), ctypes.byref(h)) == ds.DIALSORT_EINVAL
+    bad = ds.server_config(ds.batch_config(100, 16, 1 << 20), 2, 8)
+    assert ds._lib.dialsort_server_create(FAKE, 1 << 30, ctypes.byref(bad), ctypes.byref(h)) == ds.DIALSORT_EINVAL
+    assert ds._lib.dialsort_server_create(None, 1 << 30, ctypes.byref(bad), ctypes.byref(h)) == ds.DIALSORT_EINVAL
+    rid = ctypes.c_uint64()
+    assert ds._lib.dialsort_server_submit(None, FAKE, 4, 8, ctypes.byref(rid)) == ds.DIALSORT_EINVAL
+    assert ds._lib.dialsort_server_poll(None, None) == ds.DIALSORT_EINVAL
+    assert ds._lib.dialsort_server_destroy(None) == ds.DIALSORT_EINVAL
+    # footprint: H and output, each rounded up to 256 bytes
+    assert ds.dialsort_server_footprint(1000, 1 << 16) == (1 << 18) + 4096
+    assert ds.dialsort_server_footprint(0, 1) == 512
+
+
 def test_strerror():
     for s in range(6):
         assert ds.dialsort_strerror(s)

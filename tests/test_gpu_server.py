@@ -1,0 +1,207 @@
+"""GPU tests of the serving engine: every request's H and output equal the
+oracle's and equal the result of the same request served alone, whatever else
+shares its batch; admission by arena footprint; per-request errors; release
+and drain rules."""
+
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def ds(cuda):
+    import paper_2605_16667_amd as m
+
+    return m
+
+
+def make_server(ds, arena_bytes, max_inflight=2, max_batch=64, cfg=(1024, 16, 1 << 20)):
+    arena = torch.empty(arena_bytes, dtype=torch.uint8, device=DEV)
+    st, srv = ds.dialsort_server_create(arena, ds.server_config(ds.batch_config(*cfg), max_inflight, max_batch))
+    ds.check(st)
+    return arena, srv
+
+
+def result(ds, arena, srv, rid):
+    st, info = ds.dialsort_server_info(srv, rid)
+    ds.check(st)
+    assert info.state == ds.DIALSORT_REQ_DONE
+    H = ds.arena_view(arena, info.H, info.U).clone()
+    out = ds.arena_view(arena, info.out, info.n).clone()
+    return info, H, out
+
+
+def small_stream(count, seed_shift=0):
+    """Requests of the served workload's recipe, at sizes the oracle checks fast."""
+    reqs = w.request_stream(count, 1000.0, seed=w.BASE_SEED + 4 + seed_shift, n_lo=1 << 10, n_hi=1 << 18)
+    out = []
+    for r in reqs:
+        kh = w.as_u32(r.spec.keys())
+        out.append((kh, r.spec.U))
+    return out
+
+
+def test_alone_equals_in_mix(ds):
+    rng = np.random.default_rng(11)
+    kR = w.as_u32(w.zipf(300001, 1 << 20, 1.2, w.BASE_SEED + 77))
+    keysR = torch.from_numpy(kR.view(np.int32)).to(DEV)
+    st_ref, H_ref, out_ref = oracle.sort(kR, 1 << 20)
+    assert st_ref == oracle.OK
+    arena, srv = make_server(ds, 1 << 30)
+    try:
+        say("request alone")
+        st, rid = ds.dialsort_server_submit(srv, keysR, 1 << 20)
+        ds.check(st)
+        ds.check(ds.dialsort_server_drain(srv))
+        info, H_alone, out_alone = result(ds, arena, srv, rid)
+        assert info.status == ds.DIALSORT_OK
+        ds.check(ds.dialsort_server_release(srv, rid))
+        assert np.array_equal(w.as_u32(H_alone), H_ref) and np.array_equal(w.as_u32(out_alone), out_ref)
+
+        say("the same request in a mix of 40, submitted while batches run")
+        mix = small_stream(40)
+        dev_keys = [torch.from_numpy(k.view(np.int32)).to(DEV) for k, _ in mix]
+        ids = []
+        pos_R = 17
+        for i, (k, U) in enumerate(mix):
+            if i == pos_R:
+                st, ridR = ds.dialsort_server_submit(srv, keysR, 1 << 20)
+                ds.check(st)
+            st, rid = ds.dialsort_server_submit(srv, dev_keys[i], U)
+            ds.check(st)
+            ids.append(rid)
+            if i % 3 == 0:
+                ds.check(ds.dialsort_server_poll(srv)[0])
+        ds.check(ds.dialsort_server_drain(srv))
+        info, H_mix, out_mix = result(ds, arena, srv, ridR)
+        assert info.status == ds.DIALSORT_OK
+        assert torch.equal(H_mix, H_alone) and torch.equal(out_mix, out_alone)
+        launches = set()
+        for (k, U), rid in zip(mix, ids):
+            info, H, out = result(ds, arena, srv, rid)
+            assert info.status == ds.DIALSORT_OK
+            launches.add(round(info.launch_ms, 6))
+            st, Hr, outr = oracle.sort(k, U)
+            assert np.array_equal(w.as_u32(H), Hr)
+            assert np.array_equal(w.as_u32(out), outr)
+            assert info.submit_ms <= info.launch_ms + 1e-6 and info.done_ms > 0
+            ds.check(ds.dialsort_server_release(srv, rid))
+        ds.check(ds.dialsort_server_release(srv, ridR))
+        assert len(launches) >= 2  # requests were batched as they arrived, not all at once
+    finally:
+        ds.check(ds.dialsort_server_destroy(srv))
+
+
+def test_admission_under_small_arena(ds):
+    reqs = small_stream(24, seed_shift=1)
+    need = max(ds.dialsort_server_footprint(k.size, U) for k, U in reqs)
+    arena_bytes = 6 * need + (64 << 20)
+    say(f"24 requests through an arena of {arena_bytes >> 20} MiB")
+    arena, srv = make_server(ds, arena_bytes, max_inflight=2, max_batch=8)
+    try:
+        dev_keys = [torch.from_numpy(k.view(np.int32)).to(DEV) for k, _ in reqs]
+        ids = []
+        for kd, (k, U) in zip(dev_keys, reqs):
+            st, rid = ds.dialsort_server_submit(srv, kd, U)
+            ds.check(st)
+            ids.append(rid)
+        done = set()
+        batches = set()
+        spins = 0
+        while len(done) < len(ids):
+            st, pending = ds.dialsort_server_poll(srv)
+            ds.check(st)
+            for (k, U), rid in zip(reqs, ids):
+                if rid in done:
+                    continue
+                st, info = ds.dialsort_server_info(srv, rid)
+                if info.state == ds.DIALSORT_REQ_DONE:
+                    _i, H, out = result(ds, arena, srv, rid)
+                    assert info.status == ds.DIALSORT_OK
+                    batches.add(round(info.launch_ms, 6))
+                    s2, Hr, outr = oracle.sort(k, U)
+                    assert np.array_equal(w.as_u32(H), Hr) and np.array_equal(w.as_u32(out), outr)
+                    ds.check(ds.dialsort_server_release(srv, rid))
+                    done.add(rid)
+            spins += 1
+            assert spins < 200000
+        assert len(batches) >= 3  # the arena forced several admission rounds
+    finally:
+        ds.check(ds.dialsort_server_destroy(srv))
+
+
+def test_bad_request_does_not_spoil_its_batch(ds):
+    rng = np.random.default_rng(12)
+    good = [rng.integers(0, 5000, 20000).astype(np.uint32) for _ in range(3)]
+    bad = rng.integers(0, 1 << 18, 30000).astype(np.uint32)
+    bad[777] = 1 << 18
+    arena, srv = make_server(ds, 1 << 28)
+    try:
+        say("one request with a key >= U among four")
+        ks = [torch.from_numpy(k.view(np.int32)).to(DEV) for k in good + [bad]]
+        Us = [5000, 5000, 5000, 1 << 18]
+        ids = []
+        for k, U in zip(ks, Us):
+            st, rid = ds.dialsort_server_submit(srv, k, U)
+            ds.check(st)
+            ids.append(rid)
+        ds.check(ds.dialsort_server_drain(srv))
+        for i, rid in enumerate(ids):
+            info, H, out = result(ds, arena, srv, rid)
+            if i < 3:
+                assert info.status == ds.DIALSORT_OK
+                s2, Hr, outr = oracle.sort(good[i], 5000)
+                assert np.array_equal(w.as_u32(H), Hr) and np.array_equal(w.as_u32(out), outr)
+            else:
+                assert info.status == ds.DIALSORT_ERANGE
+    finally:
+        ds.check(ds.dialsort_server_destroy(srv))
+
+
+def test_release_rules_and_held_arena(ds):
+    rng = np.random.default_rng(13)
+    k = torch.from_numpy(rng.integers(0, 1 << 16, 1 << 20).astype(np.uint32).view(np.int32)).to(DEV)
+    need = ds.dialsort_server_footprint(1 << 20, 1 << 16)
+    # room for two requests' H and output; the spare MiB holds a fused launch's
+    # workspace (a lone request falls back to it when dialsort_sort's does not fit)
+    arena, srv = make_server(ds, 2 * need + (1 << 20), max_batch=1)
+    try:
+        say("errors, and a drain blocked by results that were not released")
+        st, _ = ds.dialsort_server_submit(srv, k[1:], 1 << 16)  # misaligned keys
+        assert st == ds.DIALSORT_EINVAL
+        big = torch.empty(1 << 28, dtype=torch.int32, device=DEV)
+        st, _ = ds.dialsort_server_submit(srv, big, 1 << 16)  # can never fit
+        assert st == ds.DIALSORT_EWORKSPACE
+        del big
+        ids = []
+        for _ in range(3):
+            st, rid = ds.dialsort_server_submit(srv, k, 1 << 16)
+            ds.check(st)
+            ids.append(rid)
+        assert ds.dialsort_server_release(srv, ids[2]) == ds.DIALSORT_EINVAL  # not done
+        assert ds.dialsort_server_drain(srv) == ds.DIALSORT_EWORKSPACE  # two results hold the arena
+        st, info = ds.dialsort_server_info(srv, ids[2])
+        assert info.state == ds.DIALSORT_REQ_QUEUED
+        ds.check(ds.dialsort_server_release(srv, ids[0]))
+        ds.check(ds.dialsort_server_drain(srv))
+        kh = w.as_u32(k)
+        s2, Hr, outr = oracle.sort(kh, 1 << 16)
+        for rid in ids[1:]:
+            info, H, out = result(ds, arena, srv, rid)
+            assert np.array_equal(w.as_u32(H), Hr) and np.array_equal(w.as_u32(out), outr)
+        assert ds.dialsort_server_info(srv, ids[0])[0] == ds.DIALSORT_EINVAL  # released
+    finally:
+        ds.check(ds.dialsort_server_destroy(srv))
