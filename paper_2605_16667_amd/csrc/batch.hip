@@ -93,7 +93,7 @@ void plan_batch(const dialsort_desc* d, uint32_t count, const Cfg& cfg, char* ba
     } else {
       A.kind = BA_PART;
       A.B = (uint32_t)cdiv(U, W);
-      A.na = (uint32_t)cdiv(n, PART_TK);
+      A.na = (uint32_t)cdiv(n, BT_TK);
       A.bstride = (uint32_t)align_up(A.B + 1, 8);
       A.nb = A.B;
       // every projection tile is one span; every bucket one piece (two for a
@@ -117,7 +117,7 @@ void plan_batch(const dialsort_desc* d, uint32_t count, const Cfg& cfg, char* ba
       const uint32_t g = (uint32_t)std::max<uint64_t>(1, UNIT_KEYS / A.per);
       for (uint32_t c = 0; c < A.na; c += g) add(i, UT_HIST, c, std::min(g, A.na - c));
     } else if (A.kind == BA_PART) {
-      const uint32_t g = UNIT_KEYS / PART_TK;
+      const uint32_t g = UNIT_KEYS / BT_TK;
       for (uint32_t t = 0; t < A.na; t += g) add(i, UT_PART, t, std::min(g, A.na - t));
     }
   }
@@ -156,7 +156,7 @@ void plan_batch(const dialsort_desc* d, uint32_t count, const Cfg& cfg, char* ba
       }
     } else if (A.kind == BA_PART) {
       A.staging = (uint16_t*)at(off);
-      off = align_up(off + ((size_t)A.na * PART_TK + 16) * 2, ALIGN);  // whole tiles
+      off = align_up(off + ((size_t)A.na * BT_TK + 16) * 2, ALIGN);  // whole tiles
       A.seg = (uint16_t*)at(off);
       off = align_up(off + (size_t)A.na * A.bstride * 2, ALIGN);
     }

@@ -5,7 +5,7 @@
 //   A  ingestion   -- LDS path (U <= W): chunks of `per` keys, each counted into a
 //                     private LDS histogram and written as one partial row (or as
 //                     H itself when the array has a single chunk);
-//                     partitioned path (U > W): groups of 8192-key tiles
+//                     partitioned path (U > W): groups of BT_TK-key tiles
 //                     (partition_tile, bucket = x >> LOG2W);
 //   B  counting    -- LDS path: one unit sums the rows into H and scans it;
 //                     partitioned path: groups of buckets (bucket_body), each
@@ -37,6 +37,7 @@ namespace ds {
 
 constexpr uint32_t BT_BMAX = 1024;  // buckets per array on the fused path
 constexpr int BT_CL2 = 11;          // fill item span: 2048 positions (one wave)
+constexpr int BT_TK = 8192;         // keys per partition tile
 
 enum BatchKind : uint32_t { BA_EMPTY = 0, BA_LDS = 1, BA_PART = 2 };
 enum UnitType : uint32_t { UT_HIST = 0, UT_PART = 1, UT_ROWS = 2, UT_BUCKET = 3, UT_FILL = 4 };
@@ -90,7 +91,7 @@ struct BUnit {
 template <int NT, int LOG2W>
 union BatchSmem {
   BinSmem<NT, LOG2W> bin;
-  PartSmem<NT, BT_BMAX> part;
+  PartSmem<NT, BT_BMAX, BT_TK> part;
   WaveFillSmem<BT_CL2> fill[NT / WAVE];
 };
 
@@ -153,9 +154,9 @@ __device__ __forceinline__ void unit_hist(BatchSmem<NT, LOG2W>& S, const BArray*
     if constexpr (LOG2W == 16) packed = A.U > 32768u;  // two 16-bit counters per word
     if (packed) {
       if constexpr (LOG2W == 16)
-        hist_slab<NT, true, true, 3, true, 4>(S.bin, A.keys, beg, end, umax, (uint32_t)A.U, row, status);
+        hist_slab<NT, true, 3, true, 4>(S.bin, A.keys, beg, end, umax, (uint32_t)A.U, row, status);
     } else {
-      hist_slab<NT, false, true, 3, true, 4>(S.bin, A.keys, beg, end, umax, (uint32_t)A.U, row, status);
+      hist_slab<NT, false, 3, true, 4>(S.bin, A.keys, beg, end, umax, (uint32_t)A.U, row, status);
     }
     __syncthreads();
   }
@@ -168,7 +169,7 @@ __device__ __forceinline__ void unit_part(BatchSmem<NT, LOG2W>& S, const BArray*
   const BArray& A = *Ap;
   const uint32_t umax = (uint32_t)(A.U - 1);
   for (uint32_t c = first; c < first + count; ++c)
-    partition_tile<NT, BT_BMAX, 3, true, LOG2W>(S.part, A.keys, A.n, umax, A.B, A.staging, A.seg, A.bstride, status,
+    partition_tile<NT, BT_BMAX, 3, true, LOG2W, BT_TK>(S.part, A.keys, A.n, umax, A.B, A.staging, A.seg, A.bstride, status,
                                                 c);
   unit_signal(&st->a_done, count);
 }
@@ -193,7 +194,7 @@ __device__ __forceinline__ uint64_t unit_bucket(BatchSmem<NT, LOG2W>& S, const B
   const BArray& A = *Ap;
   const uint64_t waited = unit_wait(&st->a_done, A.na);
   for (uint32_t b = first; b < first + count; ++b) {
-    bucket_body<NT, LOG2W, 3, true, true>(S.bin, A.staging, A.seg, A.bstride, A.na, A.U, A.H, status, &st->nitems,
+    bucket_body<NT, LOG2W, 3, true, true, BT_TK>(S.bin, A.staging, A.seg, A.bstride, A.na, A.U, A.H, status, &st->nitems,
                                           A.items, A.item_cap, BT_CL2, b);
     __syncthreads();
   }
@@ -221,7 +222,7 @@ __device__ __forceinline__ uint64_t unit_fill(BatchSmem<NT, LOG2W>& S, const BAr
       const bool valid = I.k <= I.klast && I.klast < A.U && I.o <= I.p0 && I.p0 < I.p1 && I.p1 <= A.n &&
                          I.p1 - (I.p0 & ~3ull) <= (1ull << BT_CL2);
       if (!valid) {
-        if (lane_id() == 0) atomicOr(status, ST_INTERNAL);
+        if (lane_id() == 0) atomicOr(status, ST_INT_ITEM);
         continue;
       }
       wave_fill_item<BT_CL2, true>(S.fill[w], A.H, A.out, I);
@@ -261,7 +262,7 @@ __global__ __launch_bounds__(NT) void k_batch(const BArray* __restrict__ arrays,
       case UT_BUCKET: waited = unit_bucket<NT, LOG2W>(S, A, st, u.first, u.count, status, ctl); break;
       case UT_FILL: waited = unit_fill<NT, LOG2W>(S, A, st, u.first, u.count, status, ctl); break;
       default:
-        if (tid == 0) atomicOr(&ctl->status, ST_INTERNAL);
+        if (tid == 0) atomicOr(&ctl->status, ST_INT_UNIT);
         break;
     }
     if (tid == 0 && u.type <= UT_FILL) {

@@ -28,7 +28,11 @@ static_assert(sizeof(Ctl) == 256, "control block is 256 bytes");
 
 constexpr uint32_t ST_RANGE = 1u;
 constexpr uint32_t ST_OVERFLOW = 2u;
-constexpr uint32_t ST_INTERNAL = 0x80000000u;  // a library invariant failed
+constexpr uint32_t ST_INTERNAL = 0x80000000u;  // a library invariant failed; with it, one cause bit:
+constexpr uint32_t ST_INT_ITEMS = ST_INTERNAL | 0x40000000u;  // fill-item list full
+constexpr uint32_t ST_INT_ITEM = ST_INTERNAL | 0x20000000u;   // a fill item outside its array
+constexpr uint32_t ST_INT_EVLOG = ST_INTERNAL | 0x10000000u;  // packed-counter event log full
+constexpr uint32_t ST_INT_UNIT = ST_INTERNAL | 0x08000000u;   // unknown work unit
 constexpr uint64_t SAT_MAX = (uint64_t(1) << 62) - 1;
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }

@@ -82,8 +82,8 @@ __device__ __noinline__ void lds16_crossing(uint32_t* words, uint32_t word, uint
   }
 }
 
-// LDS state of one ingestion slab: CAP counter words (PAD: one spare word per
-// 32, see pw()), plus the crossing log of the packed layout.
+// LDS state of one ingestion slab: CAP counter words, plus the crossing log of
+// the packed layout.
 template <int CAP, bool PACKED>
 struct HistSmem {
   uint32_t s[CAP];
@@ -92,22 +92,16 @@ struct HistSmem {
   uint32_t nev;
 };
 
-// padded word index: one spare word per 32 keeps per-thread runs of 32
-// consecutive words on distinct banks
-__device__ __forceinline__ uint32_t pw(uint32_t w) { return w + (w >> 5); }
-
 // Count keys [beg, end) into S (NT threads) and write the U exact counts to row.
-// The word of bin x is x (uint32 counters) or x >> 1 (packed), at pw() of it
-// when PAD.  A key > umax sets ST_RANGE in *status.
-template <int NT, bool PACKED, bool PAD, int AGG, bool ALIGNED, int UNR, typename SM>
+// The word of bin x is x (uint32 counters) or x >> 1 (packed).  A key > umax
+// sets ST_RANGE in *status.
+template <int NT, bool PACKED, int AGG, bool ALIGNED, int UNR, typename SM>
 __device__ __forceinline__ void hist_slab(SM& S, const uint32_t* __restrict__ keys, uint64_t beg, uint64_t end,
                                           uint32_t umax, uint32_t U, uint32_t* __restrict__ row,
                                           uint32_t* status) {
-  auto wi = [](uint32_t w) { return PAD ? pw(w) : w; };
   const uint32_t nwords = PACKED ? (U + 1) / 2 : U;
-  const uint32_t zwords = PAD ? pw(nwords - 1) + 1 : nwords;
   const uint32_t tid = threadIdx.x;
-  for (uint32_t i = tid; i < zwords; i += NT) S.s[i] = 0;
+  for (uint32_t i = tid; i < nwords; i += NT) S.s[i] = 0;
   if constexpr (PACKED) {
     for (uint32_t i = tid; i < 65536 / 32; i += NT) S.evflag[i] = 0;
     if (tid == 0) S.nev = 0;
@@ -136,9 +130,9 @@ __device__ __forceinline__ void hist_slab(SM& S, const uint32_t* __restrict__ ke
         cc[u][i] = c;
         old[u][i] = 0;
         if constexpr (!PACKED) {
-          if (c) atomicAdd(&S.s[wi(v[u][i])], c);
+          if (c) atomicAdd(&S.s[v[u][i]], c);
         } else {
-          if (c) old[u][i] = atomicAdd(&S.s[wi(v[u][i] >> 1)], c << ((v[u][i] & 1u) << 4));
+          if (c) old[u][i] = atomicAdd(&S.s[v[u][i] >> 1], c << ((v[u][i] & 1u) << 4));
         }
       }
     }
@@ -159,7 +153,7 @@ __device__ __forceinline__ void hist_slab(SM& S, const uint32_t* __restrict__ ke
           for (int i = 0; i < 4; ++i) {
             const uint32_t c = cc[u][i], k = v[u][i];
             const uint32_t field = __builtin_amdgcn_ubfe(old[u][i], (k & 1u) << 4, 16);
-            if (c && field + c >= 0x10000u) lds16_crossing(S.s, wi(k >> 1), k, c, old[u][i], S.evflag, S.ev, &S.nev);
+            if (c && field + c >= 0x10000u) lds16_crossing(S.s, k >> 1, k, c, old[u][i], S.evflag, S.ev, &S.nev);
           }
         }
       }
@@ -168,12 +162,12 @@ __device__ __forceinline__ void hist_slab(SM& S, const uint32_t* __restrict__ ke
   if (__syncthreads_or(bad) && tid == 0) atomicOr(status, ST_RANGE);
 
   if constexpr (!PACKED) {
-    for (uint32_t i = tid; i < U; i += NT) row[i] = S.s[wi(i)];
+    for (uint32_t i = tid; i < U; i += NT) row[i] = S.s[i];
   } else {
     const uint32_t ne = S.nev < LDS16_EVCAP ? S.nev : LDS16_EVCAP;
-    if (tid == 0 && S.nev > LDS16_EVCAP) atomicOr(status, ST_INTERNAL);  // cannot happen within the key bound
+    if (tid == 0 && S.nev > LDS16_EVCAP) atomicOr(status, ST_INT_EVLOG);  // cannot happen within the key bound
     for (uint32_t w = tid; w < nwords; w += NT) {
-      const uint32_t word = S.s[wi(w)];
+      const uint32_t word = S.s[w];
       uint64_t cnt[2] = {word & 0xFFFFu, word >> 16};
       if ((S.evflag[(2 * w) >> 5] >> ((2 * w) & 31)) & 3u) {
 #pragma unroll
@@ -202,7 +196,7 @@ __global__ __launch_bounds__(NT) void k_hist_lds(const uint32_t* __restrict__ ke
   __shared__ HistSmem<CAP, PACKED> S;
   const uint64_t beg = (uint64_t)blockIdx.x * per;
   const uint64_t end = beg + per < n ? beg + per : n;
-  hist_slab<NT, PACKED, false, AGG, ALIGNED, UNR>(S, keys, beg, end, umax, U, rows + (uint64_t)blockIdx.x * row_stride,
+  hist_slab<NT, PACKED, AGG, ALIGNED, UNR>(S, keys, beg, end, umax, U, rows + (uint64_t)blockIdx.x * row_stride,
                                                   &ctl->status);
 }
 

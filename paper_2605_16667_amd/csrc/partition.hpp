@@ -43,34 +43,34 @@ constexpr int PART_LOG2W = 16;   // bucket width of the single-array path
 constexpr uint32_t PART_W = 1u << PART_LOG2W;
 constexpr int PART_TK = 8192;    // keys per pass-1 tile (segment starts fit in uint16)
 constexpr int PART_NT = 1024;    // pass-2 workgroup
-constexpr int P1_NT = 512;       // pass-1 workgroup
+constexpr int P1_NT = 512;       // pass-1 workgroup (two per CU)
 constexpr uint32_t PART_BMAX = 8192;
 constexpr uint64_t PART_UMAX = (uint64_t)PART_W * PART_BMAX;  // 2^29
 
 // ---------------------------------------------------------------------------
 // Pass 1
 // ---------------------------------------------------------------------------
-template <int NT, int BMAXT>
+template <int NT, int BMAXT, int TK>
 struct PartSmem {
   uint32_t cnt[BMAXT + 1];
-  __align__(16) uint16_t stage[PART_TK];
+  __align__(16) uint16_t stage[TK];
   uint32_t scan_tmp[NT / WAVE + 1];
 };
 
-// Tile `tile` of TK keys (NT threads).  seg: T rows of `bstride` uint16
+// Tile `tile` of TK keys (NT threads; TK <= 65536 so segment starts fit in uint16).  seg: T rows of `bstride` uint16
 // (bstride >= B + 1, multiple of 8).  Invalid keys are parked as 0xFFFFFFFF
 // (U <= 2^29 here, so no valid key has that value).  Bucket of x: x >> LOG2W.
-template <int NT, int BMAXT, int AGG, bool ALIGNED, int LOG2W>
-__device__ __forceinline__ void partition_tile(PartSmem<NT, BMAXT>& S, const uint32_t* __restrict__ keys, uint64_t n,
+template <int NT, int BMAXT, int AGG, bool ALIGNED, int LOG2W, int TK>
+__device__ __forceinline__ void partition_tile(PartSmem<NT, BMAXT, TK>& S, const uint32_t* __restrict__ keys, uint64_t n,
                                                uint32_t umax, uint32_t B, uint16_t* __restrict__ staging,
                                                uint16_t* __restrict__ seg, uint32_t bstride, uint32_t* status,
                                                uint32_t tile) {
-  constexpr int GPT = PART_TK / 4 / NT;  // key groups of 4 per thread
+  constexpr int GPT = TK / 4 / NT;  // key groups of 4 per thread
   static_assert(GPT >= 1, "a tile gives every thread at least one group");
   constexpr uint32_t WM = (1u << LOG2W) - 1;
   const uint32_t tid = threadIdx.x;
-  const uint64_t tb = (uint64_t)tile * PART_TK;
-  const uint64_t te = tb + PART_TK < n ? tb + PART_TK : n;
+  const uint64_t tb = (uint64_t)tile * TK;
+  const uint64_t te = tb + TK < n ? tb + TK : n;
 
   for (uint32_t i = tid; i <= B; i += NT) S.cnt[i] = 0;
 
@@ -121,26 +121,30 @@ __device__ __forceinline__ void partition_tile(PartSmem<NT, BMAXT>& S, const uin
   }
   __syncthreads();
 
-  // place the relative keys at cursors taken from the bucket starts: all
-  // cursor atomics first, then the stores
+  // place the relative keys at cursors taken from the bucket starts, RG groups
+  // of 4 keys at a time: that round's cursor atomics first, then its stores
+  constexpr int RG = GPT < 4 ? GPT : 4;
   WaveAgg st2;
-  RankTicket tk[GPT][4];
 #pragma unroll
-  for (int u = 0; u < GPT; ++u) {
+  for (int u0 = 0; u0 < GPT; u0 += RG) {
+    RankTicket tk[RG][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const uint32_t x = v[u][i];
-      const bool ok = x != 0xFFFFFFFFu;
-      tk[u][i] = wave_rank_issue<AGG>(S.cnt, ok ? (x >> LOG2W) : 0u, ok, st2);
+    for (int u = 0; u < RG; ++u) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t x = v[u0 + u][i];
+        const bool ok = x != 0xFFFFFFFFu;
+        tk[u][i] = wave_rank_issue<AGG>(S.cnt, ok ? (x >> LOG2W) : 0u, ok, st2);
+      }
     }
-  }
 #pragma unroll
-  for (int u = 0; u < GPT; ++u) {
+    for (int u = 0; u < RG; ++u) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const uint32_t x = v[u][i];
-      const uint32_t pos = wave_rank_finish(tk[u][i]);
-      if (x != 0xFFFFFFFFu) S.stage[pos] = (uint16_t)(x & WM);
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t x = v[u0 + u][i];
+        const uint32_t pos = wave_rank_finish(tk[u][i]);
+        if (x != 0xFFFFFFFFu) S.stage[pos] = (uint16_t)(x & WM);
+      }
     }
   }
   __syncthreads();
@@ -158,8 +162,8 @@ __global__ __launch_bounds__(P1_NT) void k_partition(const uint32_t* __restrict_
                                                      uint32_t umax, uint32_t B,
                                                      uint16_t* __restrict__ staging,
                                                      uint16_t* __restrict__ seg, uint32_t bstride, Ctl* ctl) {
-  __shared__ PartSmem<P1_NT, BMAXT> S;
-  partition_tile<P1_NT, BMAXT, AGG, ALIGNED, PART_LOG2W>(S, keys, n, umax, B, staging, seg, bstride, &ctl->status,
+  __shared__ PartSmem<P1_NT, BMAXT, PART_TK> S;
+  partition_tile<P1_NT, BMAXT, AGG, ALIGNED, PART_LOG2W, PART_TK>(S, keys, n, umax, B, staging, seg, bstride, &ctl->status,
                                                          blockIdx.x);
 }
 
@@ -169,18 +173,16 @@ __global__ __launch_bounds__(P1_NT) void k_partition(const uint32_t* __restrict_
 
 constexpr int BK_SQ = 4;            // 16-byte quads (8 keys each) per lane per gather step
 constexpr uint32_t BK_LRCAP = 256;  // long-run list entries
-constexpr uint64_t BK_PACKMAX = 1ull << 22;  // keys per bucket on the packed path
 
 // LDS state of a bucket (or of a row sum): counters of one bucket of W = 2^LOG2W
-// bins -- packed 16-bit pairs when LOG2W == 16, else one uint32 per bin -- at
-// padded word indices, the crossing log of the packed layout, the long-run list
+// bins -- packed 16-bit pairs when LOG2W == 16, else one uint32 per bin -- the
+// crossing log used by the packed LDS ingestion (hist_slab), the long-run list
 // of the item emitter and block-reduction space.
 template <int NT, int LOG2W>
 struct BinSmem {
   static constexpr bool PACKED = LOG2W == 16;
   static constexpr uint32_t WORDS = PACKED ? (1u << 15) : (1u << LOG2W);
-  static constexpr uint32_t WPW = WORDS + WORDS / 32;
-  uint32_t s[WPW];
+  uint32_t s[WORDS];
   uint32_t evflag[PACKED ? 65536 / 32 : 1];
   uint32_t ev[PACKED ? LDS16_EVCAP : 1];
   uint32_t nev;
@@ -193,23 +195,22 @@ struct BinSmem {
 enum GatherMode { GM_PACKED, GM_HALF, GM_DIRECT };
 
 // Gather the segments of bucket b and count their relative keys.  GM_PACKED:
-// into the packed 16-bit fields (W = 2^16).  GM_HALF: 32-bit counters for the
-// keys whose relative value lies in half `half` (x >> 15 == half, W = 2^16).
-// GM_DIRECT: 32-bit counters for all keys (W <= 2^15).
+// into the packed 16-bit fields (W = 2^16), with no check for a field passing
+// 0xFFFF -- the caller detects any wrap afterwards from the sum of the fields.
+// GM_HALF: 32-bit counters for the keys whose relative value lies in half
+// `half` (x >> 15 == half, W = 2^16).  GM_DIRECT: 32-bit counters for all keys
+// (W <= 2^15).
 // Lanes own whole segments: with T >= NT tiles, lane tid takes tiles tid,
 // tid + NT, ...; with fewer tiles, lps = NT / T (rounded down to a power of
 // two) lanes share each tile's segment, sub-lane s taking its quads s, s + lps,
 // ....  Each lane loads its quads as aligned 16-byte quads of 8 keys, BK_SQ
-// quads per step, and prefetches the bounds of its next segment while it works
-// on the current one, so the segment-table loads never sit on the critical path.
-template <int NT, int LOG2W, int AGG, GatherMode GM>
+// quads per step, two steps ahead of the counting (segments are short, so the
+// loads of one tile must overlap the counting of earlier ones), and fetches the
+// bounds of its segments two tiles ahead of the loads that need them.
+template <int NT, int LOG2W, int AGG, GatherMode GM, int TK>
 __device__ __forceinline__ void bucket_gather(BinSmem<NT, LOG2W>& S, const uint16_t* __restrict__ staging,
                                               const uint16_t* __restrict__ seg, uint32_t bstride, uint32_t T,
                                               uint32_t b, uint32_t half) {
-  Lds16Log L;
-  L.evflag = S.evflag;
-  L.ev = S.ev;
-  L.nev = &S.nev;
   WaveAgg st;
   const uint32_t tid = threadIdx.x;
   const uint4* sq = reinterpret_cast<const uint4*>(staging);
@@ -218,19 +219,26 @@ __device__ __forceinline__ void bucket_gather(BinSmem<NT, LOG2W>& S, const uint1
   const uint32_t sub = tid & (lps - 1);
   const uint32_t tstep = NT / lps;
   const uint32_t qstep = 8u * lps;  // key index distance between a lane's quads
-  // cursor: tile t, segment [s16, e16) as tile-local key indices (<= 2^13), next
-  // quad at tile-local key index ql (a multiple of 8); 32-bit arithmetic only
+  // cursor: tile t, segment [s16, e16) as tile-local key indices (<= TK), next
+  // quad at tile-local key index ql (a multiple of 8); 32-bit arithmetic only.
+  // Loads run two steps ahead of the counting, and segment bounds two tiles
+  // ahead of the loads that need them.
   uint32_t t = tid / lps;
-  uint32_t ns = 0, ne = 0;  // prefetched bounds of tile t
-  if (t < T) { const uint16_t* row = seg + (uint64_t)t * bstride; ns = row[b]; ne = row[b + 1]; }
+  uint32_t ns1 = 0, ne1 = 0, ns2 = 0, ne2 = 0;  // bounds of tiles t and t + tstep
+  auto fetch = [&](uint32_t tt, uint32_t& lo, uint32_t& hi) {
+    if (tt < T) { const uint16_t* row = seg + (uint64_t)tt * bstride; lo = row[b]; hi = row[b + 1]; }
+  };
+  fetch(t, ns1, ne1);
+  fetch(t + tstep, ns2, ne2);
   uint32_t s16 = 0, e16 = 0, ql = 0;
-  auto open = [&]() {
+  auto open = [&]() {  // open tile t; its bounds are in ns1/ne1
     // a segment never leaves its tile's slice of staging
-    e16 = ne < (uint32_t)PART_TK ? ne : (uint32_t)PART_TK;
-    s16 = ns < e16 ? ns : e16;
+    e16 = ne1 < (uint32_t)TK ? ne1 : (uint32_t)TK;
+    s16 = ns1 < e16 ? ns1 : e16;
     ql = (s16 & ~7u) + 8u * sub;
-    const uint32_t tn = t + tstep;
-    if (tn < T) { const uint16_t* row = seg + (uint64_t)tn * bstride; ns = row[b]; ne = row[b + 1]; }
+    ns1 = ns2;
+    ne1 = ne2;
+    fetch(t + 2 * tstep, ns2, ne2);
   };
   auto advance = [&]() {
     while (t < T && ql >= e16) {
@@ -239,7 +247,7 @@ __device__ __forceinline__ void bucket_gather(BinSmem<NT, LOG2W>& S, const uint1
     }
   };
   auto load = [&](uint4* d, bool has) {
-    const uint64_t q0 = (((uint64_t)t * PART_TK) + ql) >> 3;
+    const uint64_t q0 = (((uint64_t)t * TK) + ql) >> 3;
 #pragma unroll
     for (int j = 0; j < BK_SQ; ++j) {
       d[j] = make_uint4(0, 0, 0, 0);
@@ -248,18 +256,26 @@ __device__ __forceinline__ void bucket_gather(BinSmem<NT, LOG2W>& S, const uint1
   };
   if (t < T) open();
   advance();
+  // stage 0 (counted this step) and stage 1 (in flight), each with its segment
   bool has = t < T;
   uint4 d[BK_SQ];
   load(d, has);
-  uint32_t cs = s16, ce = e16, cq = ql;  // the segment of the step in flight
+  uint32_t cs = s16, ce = e16, cq = ql;
+  ql += qstep * BK_SQ;
+  advance();
+  bool has1 = t < T;
+  uint4 d1[BK_SQ];
+  load(d1, has1);
+  uint32_t cs1 = s16, ce1 = e16, cq1 = ql;
   for (;;) {
+    // the cursor only moves forward: no data in stage 0 means none later
     if (!__any(has)) break;
-    // issue the next step's loads before working on this one
+    // issue the loads two steps ahead before counting this step
     ql += qstep * BK_SQ;
     advance();
-    const bool hasn = t < T;
-    uint4 dn[BK_SQ];
-    load(dn, hasn);
+    const bool has2 = t < T;
+    uint4 d2[BK_SQ];
+    load(d2, has2);
 #pragma unroll
     for (int j = 0; j < BK_SQ; ++j) {
       // valid keys of this quad: tile-local indices [cs, ce) within [q, q + 8)
@@ -268,7 +284,6 @@ __device__ __forceinline__ void bucket_gather(BinSmem<NT, LOG2W>& S, const uint1
       uint32_t qm = hib > lob ? ((1u << hib) - 1u) & ~((1u << lob) - 1u) : 0u;
       qm = has ? qm : 0u;
       const uint32_t wds[4] = {d[j].x, d[j].y, d[j].z, d[j].w};
-      uint32_t kk[8], cc[8], old[8];
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const uint32_t x = (e & 1) ? (wds[e >> 1] >> 16) : (wds[e >> 1] & 0xFFFFu);
@@ -276,70 +291,45 @@ __device__ __forceinline__ void bucket_gather(BinSmem<NT, LOG2W>& S, const uint1
         if (GM == GM_HALF) ok = ok && (x >> 15) == half;
         WaveGroups g;
         const uint32_t n = wave_merge_count<AGG>(x, ok, st, g);
-        kk[e] = x;
-        cc[e] = n;
-        old[e] = 0;
-        if (GM == GM_PACKED) {
-          const uint32_t sh = (x & 1u) << 4;
-          if (n) old[e] = atomicAdd(&S.s[pw(x >> 1)], n << sh);
-        } else if (GM == GM_HALF) {
-          if (n) atomicAdd(&S.s[pw(x & 0x7FFFu)], n);
-        } else {
-          if (n) atomicAdd(&S.s[pw(x)], n);
-        }
-      }
-      if (GM == GM_PACKED) {
-        // a field crossed a multiple of 65536 iff its old value plus the add
-        // exceeds 0xFFFF; check the quad at once, handle crossings rarely
-        uint32_t anyx = 0;
-#pragma unroll
-        for (int e = 0; e < 8; ++e)
-          anyx |= __builtin_amdgcn_ubfe(old[e], (kk[e] & 1u) << 4, 16) + cc[e];
-        if (anyx > 0xFFFFu) {
-#pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const uint32_t n = cc[e], x = kk[e];
-            const uint32_t field = __builtin_amdgcn_ubfe(old[e], (x & 1u) << 4, 16);
-            if (n && field + n >= 0x10000u) {
-              // the same crossing accounting as the LDS16 ingestion path, on
-              // the padded word of bin x
-              if ((x & 1u) == 0) {
-                L.log(x, false);
-                if ((old[e] >> 16) == 0xFFFFu) L.log(x + 1, false);
-                const uint32_t old2 = atomicAdd(&S.s[pw(x >> 1)], 0xFFFF0000u);
-                if ((old2 >> 16) == 0u) L.log(x + 1, true);
-              } else {
-                L.log(x, false);
-              }
-            }
+        // lanes without a count issue nothing: as no-ops they would all hit
+        // one word (zero-filled quads, merged group members) and serialise
+        if (n) {
+          if (GM == GM_PACKED) {
+            atomicAdd(&S.s[x >> 1], n << ((x & 1u) << 4));
+          } else if (GM == GM_HALF) {
+            atomicAdd(&S.s[x & 0x7FFFu], n);
+          } else {
+            atomicAdd(&S.s[x], n);
           }
         }
       }
     }
 #pragma unroll
-    for (int j = 0; j < BK_SQ; ++j) d[j] = dn[j];
-    has = hasn;
-    cs = s16;
-    ce = e16;
-    cq = ql;
-  }
-}
-
-// Exact count of relative bin k on the packed path.
-template <typename SM>
-__device__ __forceinline__ uint32_t packed_count(const SM& S, uint32_t k, uint32_t ne) {
-  const uint32_t word = S.s[pw(k >> 1)];
-  uint32_t c = (word >> ((k & 1u) << 4)) & 0xFFFFu;
-  if (S.evflag[k >> 5] & (1u << (k & 31))) {
-    for (uint32_t e = 0; e < ne; ++e) {
-      const uint32_t x = S.ev[e];
-      if ((x & 0x7FFFFFFFu) == k) c += (x & 0x80000000u) ? (uint32_t)-65536 : 65536u;
+    for (int j = 0; j < BK_SQ; ++j) {
+      d[j] = d1[j];
+      d1[j] = d2[j];
     }
+    has = has1;
+    cs = cs1;
+    ce = ce1;
+    cq = cq1;
+    has1 = has2;
+    cs1 = s16;
+    ce1 = e16;
+    cq1 = ql;
   }
-  return c;
 }
 
-// Block sum over NT threads (result in every thread).
+// Count of relative bin k on the packed path (no field wrapped).
+template <typename SM>
+__device__ __forceinline__ uint32_t packed_count(const SM& S, uint32_t k) {
+  return (S.s[k >> 1] >> ((k & 1u) << 4)) & 0xFFFFu;
+}
+
+// Block sum over NT threads (result in every thread).  Ends with a barrier, so
+// that S.red may be written by the next block operation at once: without it a
+// fast wave could overwrite S.red while slower waves still read it, and the
+// waves would then see different sums.
 template <int NT, typename SM>
 __device__ __forceinline__ uint64_t block_sum(SM& S, uint64_t x) {
   const uint32_t lane = lane_id(), w = threadIdx.x / WAVE;
@@ -349,7 +339,11 @@ __device__ __forceinline__ uint64_t block_sum(SM& S, uint64_t x) {
   __syncthreads();
   uint64_t a = 0;
   for (uint32_t i = 0; i < NT / WAVE; ++i) a += S.red[i];
-  return a;
+  __syncthreads();
+  // the same in every lane: keep it in scalar registers
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  return ((uint64_t)hi << 32) | lo;
 }
 
 // Append fill items for this thread's bins: the thread owns NB consecutive bins
@@ -462,7 +456,7 @@ __device__ __forceinline__ uint32_t reserve_items(SM& S, uint32_t* status, uint3
     uint32_t i0 = 0;
     if (nit) {
       i0 = atomicAdd(nitems, (uint32_t)nit);
-      if ((uint64_t)i0 + nit > item_cap) { atomicOr(status, ST_INTERNAL); i0 = 0xFFFFFFFFu; }
+      if ((uint64_t)i0 + nit > item_cap) { atomicOr(status, ST_INT_ITEMS); i0 = 0xFFFFFFFFu; }
     }
     S.item0 = i0;
   }
@@ -474,44 +468,35 @@ __device__ __forceinline__ uint32_t reserve_items(SM& S, uint32_t* status, uint3
 constexpr uint32_t PT_BINS = 1024;
 
 // Project the counts held in S: the piece covers relative bins [0, pcnt) of
-// absolute first bin hb, counts at S.s[pw(i)] (uint32) or from the packed
-// fields (PACKED; ne = logged events), and its run starts at output position
-// base.  Each thread owns NB consecutive bins; a block scan of their sums tells
-// it where its stretch starts.  Groups of PT_BINS bins (G = PT_BINS / NB
-// threads, inside one wave) form tiles, each with its own span of output
-// positions, so that no fill item walks more than PT_BINS bins; a second block
-// scan numbers the tiles' items.  Returns the piece's total.
+// absolute first bin hb, counts in S.s (uint32, or packed 16-bit fields when
+// PACKED), and its run starts at output position base.  Each thread owns NB
+// consecutive bins; a block scan of their sums tells it where its stretch
+// starts.  Groups of PT_BINS bins (G = PT_BINS / NB threads, inside one wave)
+// form tiles, each with its own span of output positions, so that no fill item
+// walks more than PT_BINS bins; a second block scan numbers the tiles' items.
+// Returns the piece's total.
 template <int NT, uint32_t NB, bool PACKED, typename SM>
 __device__ __forceinline__ uint64_t project_piece(SM& S, uint32_t* status, uint32_t* nitems, FillItem* items,
                                                   uint32_t item_cap, int CL2, uint64_t base, uint64_t hb,
-                                                  uint32_t pcnt, uint32_t klast, uint32_t ne) {
+                                                  uint32_t pcnt, uint32_t klast) {
   constexpr uint32_t G = PT_BINS / NB < (uint32_t)WAVE ? (PT_BINS / NB > 0 ? PT_BINS / NB : 1) : (uint32_t)WAVE;
   static_assert((G & (G - 1)) == 0, "tiles are a power of two of threads");
   const uint32_t tid = threadIdx.x, lane = lane_id();
   const uint32_t j0 = tid * NB;
+  // the thread's NB bins, read in an order rotated by lane so that the lanes of
+  // a wave hit different banks; bins at or beyond pcnt are never counted
+  // (their keys are out of range), so their counters are zero
   uint32_t sum = 0;
   if constexpr (PACKED) {
-    // whole words when none of the thread's bins logged a crossing; bins at or
-    // beyond pcnt are never counted (keys there are out of range), so their
-    // fields are zero
-    uint32_t fl = 0;
-#pragma unroll
-    for (uint32_t f = 0; f < NB / 32; ++f) fl |= S.evflag[(j0 >> 5) + f];
-    if (fl == 0u) {
+    constexpr uint32_t NW = NB / 2;
 #pragma unroll 8
-      for (uint32_t w = 0; w < NB / 2; ++w) {
-        const uint32_t word = S.s[pw((j0 >> 1) + w)];
-        sum += (word & 0xFFFFu) + (word >> 16);
-      }
-    } else {
-      for (uint32_t j = 0; j < NB; ++j) {
-        const uint32_t i = j0 + j;
-        sum += i < pcnt ? packed_count(S, i, ne) : 0u;
-      }
+    for (uint32_t w = 0; w < NW; ++w) {
+      const uint32_t word = S.s[(j0 >> 1) + ((w + lane) & (NW - 1))];
+      sum += (word & 0xFFFFu) + (word >> 16);
     }
   } else {
 #pragma unroll 8
-    for (uint32_t j = 0; j < NB; ++j) sum += j0 + j < pcnt ? S.s[pw(j0 + j)] : 0u;
+    for (uint32_t j = 0; j < NB; ++j) sum += S.s[j0 + ((j + lane) & (NB - 1))];
   }
   uint64_t tot;
   const uint64_t pre = block_exclusive_sum<NT>((uint64_t)sum, S.red, &tot);
@@ -537,7 +522,7 @@ __device__ __forceinline__ uint64_t project_piece(SM& S, uint32_t* status, uint3
     uint32_t i0 = 0;
     if (all_items) {
       i0 = atomicAdd(nitems, (uint32_t)all_items);
-      if ((uint64_t)i0 + all_items > item_cap) { atomicOr(status, ST_INTERNAL); i0 = 0xFFFFFFFFu; }
+      if ((uint64_t)i0 + all_items > item_cap) { atomicOr(status, ST_INT_ITEMS); i0 = 0xFFFFFFFFu; }
     }
     S.item0 = i0;
   }
@@ -546,10 +531,10 @@ __device__ __forceinline__ uint64_t project_piece(SM& S, uint32_t* status, uint3
   if (item0 == 0xFFFFFFFFu) return tot;
   const uint32_t my0 = item0 + (uint32_t)tile_off;
   if constexpr (PACKED) {
-    auto count = [&](uint32_t i) -> uint32_t { return packed_count(S, i, ne); };
+    auto count = [&](uint32_t i) -> uint32_t { return packed_count(S, i); };
     emit_items<NT, NB>(S, items, my0, CL2, ts, te, hb, j0, pcnt, base + pre, sum, tklast, count);
   } else {
-    auto count = [&](uint32_t i) -> uint32_t { return S.s[pw(i)]; };
+    auto count = [&](uint32_t i) -> uint32_t { return S.s[i]; };
     emit_items<NT, NB>(S, items, my0, CL2, ts, te, hb, j0, pcnt, base + pre, sum, tklast, count);
   }
   return tot;
@@ -559,8 +544,12 @@ __device__ __forceinline__ uint64_t project_piece(SM& S, uint32_t* status, uint3
 // Pass 2
 // ---------------------------------------------------------------------------
 // Bucket b of W = 2^LOG2W bins (T tiles): H receives bins [b*W, min((b+1)*W, U)).
-// FULL also appends the fill items of the bucket's sorted run.
-template <int NT, int LOG2W, int AGG, bool HALIGNED, bool FULL>
+// FULL also appends the fill items of the bucket's sorted run.  With W = 2^16
+// the bucket is counted into packed 16-bit fields; a field that passed 0xFFFF
+// shows up as a sum of all fields below the number of keys gathered (a wrap of
+// a low field costs 65535, of a high field 65536), and the bucket is then
+// counted again, exactly, in two halves of 2^15 bins with 32-bit counters.
+template <int NT, int LOG2W, int AGG, bool HALIGNED, bool FULL, int TK>
 __device__ __forceinline__ void bucket_body(BinSmem<NT, LOG2W>& S, const uint16_t* __restrict__ staging,
                                             const uint16_t* __restrict__ seg, uint32_t bstride, uint32_t T,
                                             uint64_t U, uint32_t* __restrict__ H, uint32_t* status,
@@ -573,8 +562,11 @@ __device__ __forceinline__ void bucket_body(BinSmem<NT, LOG2W>& S, const uint16_
   const uint32_t cnt = (uint32_t)(U - hb < W ? U - hb : W);
   const uint32_t klast = (uint32_t)(hb + cnt - 1);
 
-  // where the bucket's run starts (keys of earlier buckets) and its length
+  // where the bucket's run starts (keys of earlier buckets) and its length; the
+  // pass also brings the segment bounds into the caches for the gather, whose
+  // lanes visit the same tiles
   uint64_t mb = 0, mt = 0;
+#pragma unroll 4
   for (uint32_t tt = tid; tt < T; tt += NT) {
     const uint16_t* row = seg + (uint64_t)tt * bstride;
     const uint32_t lo = row[b], hi = row[b + 1];
@@ -583,68 +575,56 @@ __device__ __forceinline__ void bucket_body(BinSmem<NT, LOG2W>& S, const uint16_
   }
   const uint64_t base = block_sum<NT>(S, mb);
   const uint64_t total = block_sum<NT>(S, mt);
+  for (uint32_t i = tid; i < SM::WORDS; i += NT) S.s[i] = 0;
+  __syncthreads();
+  bucket_gather<NT, LOG2W, AGG, SM::PACKED ? GM_PACKED : GM_DIRECT, TK>(S, staging, seg, bstride, T, b, 0);
+  __syncthreads();
 
   if constexpr (!SM::PACKED) {
-    // ---- W <= 2^15: one gather into 32-bit counters -------------------------
-    for (uint32_t i = tid; i < SM::WPW; i += NT) S.s[i] = 0;
-    __syncthreads();
-    bucket_gather<NT, LOG2W, AGG, GM_DIRECT>(S, staging, seg, bstride, T, b, 0);
-    __syncthreads();
-    for (uint32_t i = tid; i < cnt; i += NT) H[hb + i] = S.s[pw(i)];
+    // ---- W <= 2^15: 32-bit counters ----------------------------------------
+    for (uint32_t i = tid; i < cnt; i += NT) H[hb + i] = S.s[i];
     if constexpr (FULL) {
-      if (total) project_piece<NT, W / NT, false>(S, status, nitems, items, item_cap, CL2, base, hb, cnt, klast, 0);
+      if (total) project_piece<NT, W / NT, false>(S, status, nitems, items, item_cap, CL2, base, hb, cnt, klast);
     }
     return;
   } else {
-    if (total <= BK_PACKMAX) {
-      // ---- packed path: one gather, 16-bit fields + crossing events --------
-      for (uint32_t i = tid; i < SM::WPW; i += NT) S.s[i] = 0;
-      for (uint32_t i = tid; i < W / 32; i += NT) S.evflag[i] = 0;
-      if (tid == 0) { S.nev = 0; S.n = 0; }
-      __syncthreads();
-      bucket_gather<NT, LOG2W, AGG, GM_PACKED>(S, staging, seg, bstride, T, b, 0);
-      __syncthreads();
-      const uint32_t ne = S.nev < LDS16_EVCAP ? S.nev : LDS16_EVCAP;
-      if (tid == 0 && S.nev > LDS16_EVCAP) atomicOr(status, ST_INTERNAL);  // cannot happen within BK_PACKMAX
-      // H: two bins per packed word; bins with logged crossings (flag bit set)
-      // take the slow exact count
-      for (uint32_t wv = tid; wv < (cnt + 1) / 2; wv += NT) {
-        const uint32_t k = 2 * wv;
-        const uint32_t word = S.s[pw(wv)];
-        uint32_t c0 = word & 0xFFFFu, c1 = word >> 16;
-        if ((S.evflag[k >> 5] >> (k & 31)) & 3u) {
-          c0 = packed_count(S, k, ne);
-          c1 = packed_count(S, k + 1, ne);
-        }
-        if (HALIGNED && k + 1 < cnt) {
-          *reinterpret_cast<uint2*>(H + hb + k) = make_uint2(c0, c1);
-        } else {
-          H[hb + k] = c0;
-          if (k + 1 < cnt) H[hb + k + 1] = c1;
-        }
+    // ---- packed fields: H from whole words, and the sum of the fields ------
+    uint64_t fsum = 0;
+    for (uint32_t wv = tid; wv < (cnt + 1) / 2; wv += NT) {
+      const uint32_t k = 2 * wv;
+      const uint32_t word = S.s[wv];
+      const uint32_t c0 = word & 0xFFFFu, c1 = word >> 16;
+      fsum += c0 + c1;
+      if (HALIGNED && k + 1 < cnt) {
+        *reinterpret_cast<uint2*>(H + hb + k) = make_uint2(c0, c1);
+      } else {
+        H[hb + k] = c0;
+        if (k + 1 < cnt) H[hb + k + 1] = c1;
       }
+    }
+    if (block_sum<NT>(S, fsum) == total) {
       if constexpr (FULL) {
-        if (total) project_piece<NT, W / NT, true>(S, status, nitems, items, item_cap, CL2, base, hb, cnt, klast, ne);
+        if (total) project_piece<NT, W / NT, true>(S, status, nitems, items, item_cap, CL2, base, hb, cnt, klast);
       }
       return;
     }
 
-    // ---- heavy bucket: two halves of 2^15 bins with 32-bit counters ---------
+    // ---- a field wrapped: two halves of 2^15 bins with 32-bit counters -----
     uint64_t hbase = base;  // where the current half's run starts
     for (uint32_t half = 0; half < 2; ++half) {
       const uint32_t hb0 = half << 15;
       if (hb0 >= cnt) break;
       const uint32_t hcnt = cnt - hb0 < (1u << 15) ? cnt - hb0 : (1u << 15);
       __syncthreads();
-      for (uint32_t i = tid; i < SM::WPW; i += NT) S.s[i] = 0;
+      for (uint32_t i = tid; i < SM::WORDS; i += NT) S.s[i] = 0;
       if (tid == 0) S.n = 0;
       __syncthreads();
-      bucket_gather<NT, LOG2W, AGG, GM_HALF>(S, staging, seg, bstride, T, b, half);
+      bucket_gather<NT, LOG2W, AGG, GM_HALF, TK>(S, staging, seg, bstride, T, b, half);
       __syncthreads();
-      for (uint32_t i = tid; i < hcnt; i += NT) H[hb + hb0 + i] = S.s[pw(i)];
+      for (uint32_t i = tid; i < hcnt; i += NT) H[hb + hb0 + i] = S.s[i];
       if constexpr (FULL) {
         hbase += project_piece<NT, (1u << 15) / NT, false>(S, status, nitems, items, item_cap, CL2, hbase,
-                                                           hb + hb0, hcnt, klast, 0);
+                                                           hb + hb0, hcnt, klast);
       }
     }
   }
@@ -660,7 +640,7 @@ __global__ __launch_bounds__(PART_NT) void k_bucket(const uint16_t* __restrict__
   // XCD-aware bucket order: blocks are dispatched round-robin over 8 XCDs
   uint32_t b = blockIdx.x;
   if ((B & 7u) == 0) b = (blockIdx.x & 7u) * (B >> 3) + (blockIdx.x >> 3);
-  bucket_body<PART_NT, PART_LOG2W, AGG, HALIGNED, FULL>(S, staging, seg, bstride, T, U, H, &ctl->status,
+  bucket_body<PART_NT, PART_LOG2W, AGG, HALIGNED, FULL, PART_TK>(S, staging, seg, bstride, T, U, H, &ctl->status,
                                                         &ctl->nitems, items, item_cap, CL2, b);
 }
 
@@ -689,12 +669,12 @@ __device__ __forceinline__ void rows_body(BinSmem<NT, LOG2W>& S, const uint32_t*
         for (uint32_t j = 0; j < nrows; ++j) a += r[(uint64_t)j * row_stride];
         if (H_out) H_out[p0 + i] = a;
       }
-      S.s[pw(i)] = a;
+      S.s[i] = a;
     }
     __syncthreads();
     if constexpr (FULL) {
       const uint32_t klast = p0 + pcnt - 1;
-      pbase += project_piece<NT, P / NT, false>(S, status, nitems, items, item_cap, CL2, pbase, p0, pcnt, klast, 0);
+      pbase += project_piece<NT, P / NT, false>(S, status, nitems, items, item_cap, CL2, pbase, p0, pcnt, klast);
     }
   }
 }

@@ -173,7 +173,7 @@ __global__ __launch_bounds__(NT) void k_scan(const uint32_t* __restrict__ rows, 
     uint32_t i0 = 0;
     if (nit) {
       i0 = atomicAdd(&ctl->nitems, (uint32_t)nit);
-      if ((uint64_t)i0 + nit > item_cap) { set_status(ctl, ST_INTERNAL); i0 = 0xFFFFFFFFu; }
+      if ((uint64_t)i0 + nit > item_cap) { set_status(ctl, ST_INT_ITEMS); i0 = 0xFFFFFFFFu; }
     }
     s_item0 = i0;
   }

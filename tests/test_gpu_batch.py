@@ -71,6 +71,23 @@ class Batch:
                                      f"positions, first {bad[:4]}")
 
 
+BARRAY_BYTES = 120  # sizeof(BArray) in the workspace tables
+BSTATE_BYTES = 32
+
+
+def raw_status(batch):
+    """The batch's raw device status word and the nonzero per-array status
+    words, for failure messages."""
+    torch.cuda.synchronize()
+    ws = batch.ws
+    word = int(ws[:4].view(torch.int32).item()) & 0xFFFFFFFF
+    off = (256 + batch.count * BARRAY_BYTES + 255) // 256 * 256
+    st = ws[off:off + batch.count * BSTATE_BYTES].view(torch.int32).view(batch.count, 8).cpu().numpy()
+    bad = [(i, hex(int(st[i, 6]) & 0xFFFFFFFF), batch.items[i][5].size, batch.items[i][1])
+           for i in range(batch.count) if st[i, 6] != 0]
+    return f"status word {word:#x}; arrays (index, status, n, U): {bad}"
+
+
 def mixed_specs(seed_shift=0):
     rng = np.random.default_rng(w.BASE_SEED + 50 + seed_shift)
     specs = []
@@ -111,12 +128,14 @@ def test_fused_every_config(ds, batch, cfg):
     ds.check(st)
     assert plan.units > 0 and plan.grid > 0
     ds.check(ds.dialsort_batch_launch(plan))
-    assert ds.dialsort_status_sync(batch.ws) == ds.DIALSORT_OK
+    st = ds.dialsort_status_sync(batch.ws)
+    assert st == ds.DIALSORT_OK, raw_status(batch)
     batch.check(f"config {cfg}")
     # a second launch of the same plan recomputes everything
     batch.poison()
     ds.check(ds.dialsort_batch_launch(plan))
-    assert ds.dialsort_status_sync(batch.ws) == ds.DIALSORT_OK
+    st = ds.dialsort_status_sync(batch.ws)
+    assert st == ds.DIALSORT_OK, raw_status(batch)
     batch.check(f"config {cfg}, relaunch")
 
 
