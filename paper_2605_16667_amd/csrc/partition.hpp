@@ -87,14 +87,35 @@ __device__ __forceinline__ void partition_tile(PartSmem<NT, BMAXT, TK>& S, const
       if (!ok) v[u][i] = 0xFFFFFFFFu;
     }
   }
-  __syncthreads();
+  // Equality merging pays only where many lanes share a bucket: a tile takes
+  // it when some wave finds 8 or more of its first 64 keys (one per lane) in
+  // the bucket of its lowest lane's key.  Either way every count is exact.
+  bool crowd = false;
+  if constexpr (AGG != 0) {
+    const uint32_t x0 = v[0][0];
+    const uint32_t bk = x0 != 0xFFFFFFFFu ? x0 >> LOG2W : 0xFFFFFFFFu;
+    const uint32_t lead = __builtin_amdgcn_readfirstlane(bk);
+    crowd = lead != 0xFFFFFFFFu && __popcll(__ballot(bk == lead)) >= 8;
+  }
+  const bool merge = __syncthreads_or(crowd);
   WaveAgg st;
+  if (merge) {
 #pragma unroll
-  for (int u = 0; u < GPT; ++u) {
+    for (int u = 0; u < GPT; ++u) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const bool ok = v[u][i] != 0xFFFFFFFFu;
-      wave_count<AGG>(S.cnt, ok ? (v[u][i] >> LOG2W) : 0u, ok, st);
+      for (int i = 0; i < 4; ++i) {
+        const bool ok = v[u][i] != 0xFFFFFFFFu;
+        wave_count<AGG>(S.cnt, ok ? (v[u][i] >> LOG2W) : 0u, ok, st);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < GPT; ++u) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const bool ok = v[u][i] != 0xFFFFFFFFu;
+        wave_count<0>(S.cnt, ok ? (v[u][i] >> LOG2W) : 0u, ok, st);
+      }
     }
   }
   if (__syncthreads_or(bad) && tid == 0) atomicOr(status, ST_RANGE);
@@ -124,26 +145,51 @@ __device__ __forceinline__ void partition_tile(PartSmem<NT, BMAXT, TK>& S, const
   // place the relative keys at cursors taken from the bucket starts, RG groups
   // of 4 keys at a time: that round's cursor atomics first, then its stores
   constexpr int RG = GPT < 4 ? GPT : 4;
-  WaveAgg st2;
+  if (merge) {
+    WaveAgg st2;
 #pragma unroll
-  for (int u0 = 0; u0 < GPT; u0 += RG) {
-    RankTicket tk[RG][4];
+    for (int u0 = 0; u0 < GPT; u0 += RG) {
+      RankTicket tk[RG][4];
 #pragma unroll
-    for (int u = 0; u < RG; ++u) {
+      for (int u = 0; u < RG; ++u) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const uint32_t x = v[u0 + u][i];
-        const bool ok = x != 0xFFFFFFFFu;
-        tk[u][i] = wave_rank_issue<AGG>(S.cnt, ok ? (x >> LOG2W) : 0u, ok, st2);
+        for (int i = 0; i < 4; ++i) {
+          const uint32_t x = v[u0 + u][i];
+          const bool ok = x != 0xFFFFFFFFu;
+          tk[u][i] = wave_rank_issue<AGG>(S.cnt, ok ? (x >> LOG2W) : 0u, ok, st2);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < RG; ++u) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint32_t x = v[u0 + u][i];
+          const uint32_t pos = wave_rank_finish(tk[u][i]);
+          if (x != 0xFFFFFFFFu) S.stage[pos] = (uint16_t)(x & WM);
+        }
       }
     }
+  } else {
+    // one returning atomic per key, RG groups in flight
 #pragma unroll
-    for (int u = 0; u < RG; ++u) {
+    for (int u0 = 0; u0 < GPT; u0 += RG) {
+      uint32_t pos[RG][4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const uint32_t x = v[u0 + u][i];
-        const uint32_t pos = wave_rank_finish(tk[u][i]);
-        if (x != 0xFFFFFFFFu) S.stage[pos] = (uint16_t)(x & WM);
+      for (int u = 0; u < RG; ++u) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint32_t x = v[u0 + u][i];
+          pos[u][i] = 0;
+          if (x != 0xFFFFFFFFu) pos[u][i] = atomicAdd(&S.cnt[x >> LOG2W], 1u);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < RG; ++u) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint32_t x = v[u0 + u][i];
+          if (x != 0xFFFFFFFFu) S.stage[pos[u][i]] = (uint16_t)(x & WM);
+        }
       }
     }
   }
@@ -171,7 +217,7 @@ __global__ __launch_bounds__(P1_NT) void k_partition(const uint32_t* __restrict_
 // Pass 2 helpers
 // ---------------------------------------------------------------------------
 
-constexpr int BK_SQ = 4;            // 16-byte quads (8 keys each) per lane per gather step
+constexpr int BK_SQ = 4;            // 16-byte quads (8 keys each) per lane per gather chunk
 constexpr uint32_t BK_LRCAP = 256;  // long-run list entries
 
 // LDS state of a bucket (or of a row sum): counters of one bucket of W = 2^LOG2W
@@ -200,123 +246,92 @@ enum GatherMode { GM_PACKED, GM_HALF, GM_DIRECT };
 // GM_HALF: 32-bit counters for the keys whose relative value lies in half
 // `half` (x >> 15 == half, W = 2^16).  GM_DIRECT: 32-bit counters for all keys
 // (W <= 2^15).
-// Lanes own whole segments: with T >= NT tiles, lane tid takes tiles tid,
-// tid + NT, ...; with fewer tiles, lps = NT / T (rounded down to a power of
-// two) lanes share each tile's segment, sub-lane s taking its quads s, s + lps,
-// ....  Each lane loads its quads as aligned 16-byte quads of 8 keys, BK_SQ
-// quads per step, two steps ahead of the counting (segments are short, so the
-// loads of one tile must overlap the counting of earlier ones), and fetches the
-// bounds of its segments two tiles ahead of the loads that need them.
+// Tiles go to the waves in groups of 64, one tile per lane: group g to wave
+// g mod NW, or, with fewer groups than waves, NW / G waves to each group,
+// which split its quads between them.  A lane holds its tile's segment
+// [s, e) of tile-local key indices and the wave walks the segments of the
+// group in chunks of BK_SQ 16-byte quads (8 keys each) per lane, all lanes in
+// step, up to the group's longest segment.  Every lane issues every load of a
+// chunk -- past the end of its segment it reads the segment's last quad again,
+// and without a segment quad 0 -- so the loads have no branches around them
+// and stay in flight together; masks keep keys outside [s, e) out of the count.
+// The bounds of a wave's next group are loaded before its current group is
+// counted.
 template <int NT, int LOG2W, int AGG, GatherMode GM, int TK>
 __device__ __forceinline__ void bucket_gather(BinSmem<NT, LOG2W>& S, const uint16_t* __restrict__ staging,
                                               const uint16_t* __restrict__ seg, uint32_t bstride, uint32_t T,
                                               uint32_t b, uint32_t half) {
+  static_assert(TK % 8 == 0 && TK <= 32768, "tile-local key indices and quad offsets fit 16 bits");
+  constexpr uint32_t NW = NT / WAVE;
   WaveAgg st;
-  const uint32_t tid = threadIdx.x;
+  const uint32_t lane = lane_id(), w = threadIdx.x / WAVE;
   const uint4* sq = reinterpret_cast<const uint4*>(staging);
-  uint32_t lps = 1;  // lanes per segment (uniform)
-  while (lps < (uint32_t)NT && (uint64_t)T * lps * 2 <= (uint64_t)NT) lps *= 2;
-  const uint32_t sub = tid & (lps - 1);
-  const uint32_t tstep = NT / lps;
-  const uint32_t qstep = 8u * lps;  // key index distance between a lane's quads
-  // cursor: tile t, segment [s16, e16) as tile-local key indices (<= TK), next
-  // quad at tile-local key index ql (a multiple of 8); 32-bit arithmetic only.
-  // Loads run two steps ahead of the counting, and segment bounds two tiles
-  // ahead of the loads that need them.
-  uint32_t t = tid / lps;
-  uint32_t ns1 = 0, ne1 = 0, ns2 = 0, ne2 = 0;  // bounds of tiles t and t + tstep
-  auto fetch = [&](uint32_t tt, uint32_t& lo, uint32_t& hi) {
-    if (tt < T) { const uint16_t* row = seg + (uint64_t)tt * bstride; lo = row[b]; hi = row[b + 1]; }
+  if (T == 0) return;
+  const uint32_t G = (T + WAVE - 1) / WAVE;  // groups of 64 tiles
+  const uint32_t wpg = G < NW ? NW / G : 1;  // waves per group
+  const uint32_t gstep = NW / wpg;           // groups between a wave's groups
+  const uint32_t sub = w % wpg;
+  if (w >= gstep * wpg) return;  // spare waves when NW is not a multiple of G
+  // segment bounds of this lane's tile in group g (a clamped row past the end)
+  auto bounds = [&](uint32_t g, uint32_t& lo, uint32_t& hi) {
+    uint32_t t = g * WAVE + lane;
+    t = t < T ? t : T - 1;
+    const uint16_t* row = seg + (uint64_t)t * bstride;
+    lo = row[b];
+    hi = row[b + 1];
   };
-  fetch(t, ns1, ne1);
-  fetch(t + tstep, ns2, ne2);
-  uint32_t s16 = 0, e16 = 0, ql = 0;
-  auto open = [&]() {  // open tile t; its bounds are in ns1/ne1
-    // a segment never leaves its tile's slice of staging
-    e16 = ne1 < (uint32_t)TK ? ne1 : (uint32_t)TK;
-    s16 = ns1 < e16 ? ns1 : e16;
-    ql = (s16 & ~7u) + 8u * sub;
-    ns1 = ns2;
-    ne1 = ne2;
-    fetch(t + 2 * tstep, ns2, ne2);
-  };
-  auto advance = [&]() {
-    while (t < T && ql >= e16) {
-      t += tstep;
-      if (t < T) open();
-    }
-  };
-  auto load = [&](uint4* d, bool has) {
-    const uint64_t q0 = (((uint64_t)t * TK) + ql) >> 3;
+  uint32_t g = w / wpg;
+  uint32_t lo = 0, hi = 0;
+  if (g < G) bounds(g, lo, hi);
+  for (; g < G; g += gstep) {
+    uint32_t nlo, nhi;
+    bounds(g + gstep < G ? g + gstep : g, nlo, nhi);
+    const uint32_t t = g * WAVE + lane;
+    uint32_t e = hi < (uint32_t)TK ? hi : (uint32_t)TK;  // a segment never leaves its tile
+    uint32_t s = lo < e ? lo : e;
+    if (t >= T) s = e = 0;
+    const uint32_t q0 = s >> 3;
+    const uint32_t nq = e > s ? ((e + 7) >> 3) - q0 : 0;
+    const uint32_t kmax = wave_max(nq);
+    const uint64_t qb = nq ? (uint64_t)t * (TK / 8) + q0 : 0;
+    const uint32_t qlast = nq ? nq - 1 : 0;
+    for (uint32_t k0 = sub * BK_SQ; k0 < kmax; k0 += wpg * BK_SQ) {
+      uint4 d[BK_SQ];
 #pragma unroll
-    for (int j = 0; j < BK_SQ; ++j) {
-      d[j] = make_uint4(0, 0, 0, 0);
-      if (has && ql + qstep * j < e16) d[j] = sq[q0 + (uint64_t)lps * j];
-    }
-  };
-  if (t < T) open();
-  advance();
-  // stage 0 (counted this step) and stage 1 (in flight), each with its segment
-  bool has = t < T;
-  uint4 d[BK_SQ];
-  load(d, has);
-  uint32_t cs = s16, ce = e16, cq = ql;
-  ql += qstep * BK_SQ;
-  advance();
-  bool has1 = t < T;
-  uint4 d1[BK_SQ];
-  load(d1, has1);
-  uint32_t cs1 = s16, ce1 = e16, cq1 = ql;
-  for (;;) {
-    // the cursor only moves forward: no data in stage 0 means none later
-    if (!__any(has)) break;
-    // issue the loads two steps ahead before counting this step
-    ql += qstep * BK_SQ;
-    advance();
-    const bool has2 = t < T;
-    uint4 d2[BK_SQ];
-    load(d2, has2);
+      for (int j = 0; j < BK_SQ; ++j) {
+        const uint32_t k = k0 + j < qlast ? k0 + j : qlast;
+        d[j] = sq[qb + k];
+      }
 #pragma unroll
-    for (int j = 0; j < BK_SQ; ++j) {
-      // valid keys of this quad: tile-local indices [cs, ce) within [q, q + 8)
-      const int32_t q = (int32_t)(cq + qstep * j);
-      const int32_t lob = max((int32_t)cs - q, 0), hib = min((int32_t)ce - q, 8);
-      uint32_t qm = hib > lob ? ((1u << hib) - 1u) & ~((1u << lob) - 1u) : 0u;
-      qm = has ? qm : 0u;
-      const uint32_t wds[4] = {d[j].x, d[j].y, d[j].z, d[j].w};
+      for (int j = 0; j < BK_SQ; ++j) {
+        // valid keys of this quad: tile-local indices [s, e) within [q, q + 8)
+        const int32_t q = (int32_t)((q0 + k0 + j) * 8);
+        const int32_t lob = max((int32_t)s - q, 0), hib = min((int32_t)e - q, 8);
+        const uint32_t qm = hib > lob ? ((1u << hib) - 1u) & ~((1u << lob) - 1u) : 0u;
+        const uint32_t wds[4] = {d[j].x, d[j].y, d[j].z, d[j].w};
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const uint32_t x = (e & 1) ? (wds[e >> 1] >> 16) : (wds[e >> 1] & 0xFFFFu);
-        bool ok = (qm >> e) & 1u;
-        if (GM == GM_HALF) ok = ok && (x >> 15) == half;
-        WaveGroups g;
-        const uint32_t n = wave_merge_count<AGG>(x, ok, st, g);
-        // lanes without a count issue nothing: as no-ops they would all hit
-        // one word (zero-filled quads, merged group members) and serialise
-        if (n) {
-          if (GM == GM_PACKED) {
-            atomicAdd(&S.s[x >> 1], n << ((x & 1u) << 4));
-          } else if (GM == GM_HALF) {
-            atomicAdd(&S.s[x & 0x7FFFu], n);
-          } else {
-            atomicAdd(&S.s[x], n);
+        for (int m = 0; m < 8; ++m) {
+          const uint32_t x = (m & 1) ? (wds[m >> 1] >> 16) : (wds[m >> 1] & 0xFFFFu);
+          bool ok = (qm >> m) & 1u;
+          if (GM == GM_HALF) ok = ok && (x >> 15) == half;
+          WaveGroups grp;
+          const uint32_t n = wave_merge_count<AGG>(x, ok, st, grp);
+          // lanes without a count issue nothing: as no-ops they would all hit
+          // one word (masked keys, merged group members) and serialise
+          if (n) {
+            if (GM == GM_PACKED) {
+              atomicAdd(&S.s[x >> 1], n << ((x & 1u) << 4));
+            } else if (GM == GM_HALF) {
+              atomicAdd(&S.s[x & 0x7FFFu], n);
+            } else {
+              atomicAdd(&S.s[x], n);
+            }
           }
         }
       }
     }
-#pragma unroll
-    for (int j = 0; j < BK_SQ; ++j) {
-      d[j] = d1[j];
-      d1[j] = d2[j];
-    }
-    has = has1;
-    cs = cs1;
-    ce = ce1;
-    cq = cq1;
-    has1 = has2;
-    cs1 = s16;
-    ce1 = e16;
-    cq1 = ql;
+    lo = nlo;
+    hi = nhi;
   }
 }
 
