@@ -170,7 +170,7 @@ __device__ __forceinline__ void unit_part(BatchSmem<NT, LOG2W>& S, const BArray*
   const uint32_t umax = (uint32_t)(A.U - 1);
   for (uint32_t c = first; c < first + count; ++c)
     partition_tile<NT, BT_BMAX, 3, true, LOG2W, BT_TK>(S.part, A.keys, A.n, umax, A.B, A.staging, A.seg, A.bstride, status,
-                                                c);
+                                                       c, nullptr);
   unit_signal(&st->a_done, count);
 }
 
@@ -194,8 +194,18 @@ __device__ __forceinline__ uint64_t unit_bucket(BatchSmem<NT, LOG2W>& S, const B
   const BArray& A = *Ap;
   const uint64_t waited = unit_wait(&st->a_done, A.na);
   for (uint32_t b = first; b < first + count; ++b) {
-    bucket_body<NT, LOG2W, 3, true, true, BT_TK>(S.bin, A.staging, A.seg, A.bstride, A.na, A.U, A.H, status, &st->nitems,
-                                          A.items, A.item_cap, BT_CL2, b);
+    uint64_t base, total;
+    bucket_extent<NT>(S.bin, A.seg, A.bstride, A.na, b, &base, &total);
+    BucketPart bp;
+    bp.b = b;
+    bp.t0 = 0;
+    bp.t1 = A.na;
+    bp.P = 1;
+    bp.base = base;
+    bp.acc = nullptr;
+    bp.done = nullptr;
+    bucket_body<NT, LOG2W, 3, true, true, BT_TK>(S.bin, A.staging, A.seg, A.bstride, A.U, A.H, status, &st->nitems,
+                                                 A.items, A.item_cap, BT_CL2, bp);
     __syncthreads();
   }
   const uint32_t old = unit_signal(&st->b_done, count);

@@ -35,6 +35,7 @@ namespace {
 constexpr int FILL_NT = 256;
 constexpr int FILL_CL2 = 11;  // fill items of at most 2048 positions (one wave each)
 constexpr int SCAN_NT = 256;
+constexpr uint64_t PART_NCU = 256;  // compute units of the target (MI355X)
 
 enum Kind { K_EMPTY, K_LDS32S, K_LDS32, K_LDS16, K_PART, K_GLOBAL, K_NONE };
 
@@ -43,6 +44,8 @@ struct Layout {
   uint32_t G = 1;        // LDS paths: workgroups (= partial rows)
   uint64_t per = 0;      // LDS paths: keys per workgroup (multiple of 4)
   uint32_t B = 0, T = 0, bstride = 0;  // PART
+  uint32_t X = 0;        // PART: extra workgroups for the parts of heavy buckets
+  uint64_t chunk = 0;    // PART: keys per part of a heavy bucket
   bool rows_in_ws = false;
   uint64_t row_stride = 0;
   bool scan = false;     // full projection
@@ -51,6 +54,8 @@ struct Layout {
   uint64_t limit = 0;
   uint64_t item_cap = 0;
   size_t off_tile = 0, off_items = 0, off_rows = 0, off_stage = 0, off_seg = 0, bytes = 0;
+  size_t off_z = 0, nz = 0;  // PART: cleared words: bucket-total counters, tile ticket, done counters, scratch
+  size_t off_done = 0, off_scratch = 0;
 };
 
 // Choose the number of LDS workgroups: enough to stream the keys at full
@@ -95,6 +100,10 @@ Layout plan(uint64_t n, uint64_t U, int mode) {
     L.B = (uint32_t)cdiv(U, PART_W);
     L.T = (uint32_t)cdiv(n, PART_TK);
     L.bstride = (uint32_t)align_up(L.B + 1, 8);
+    // a bucket of more than two chunks is counted by several workgroups; a
+    // chunk is the keys per CU of an even spread (at least 2^18)
+    L.chunk = std::max<uint64_t>(1ull << 18, cdiv(n, PART_NCU));
+    L.X = n > 2 * L.chunk ? (uint32_t)std::min<uint64_t>(cdiv(n, L.chunk), 2 * PART_NCU) : 0;
   }
   if (L.kind == K_LDS32S || L.kind == K_LDS32 || L.kind == K_LDS16) {
     L.per = align_up(cdiv(n, L.G), 4);
@@ -122,26 +131,37 @@ Layout plan(uint64_t n, uint64_t U, int mode) {
   if (L.kind == K_PART) {
     L.off_stage = off; off = align_up(off + (align_up(n, 8) + 16) * 2, ALIGN);
     L.off_seg = off; off = align_up(off + (size_t)L.T * L.bstride * 2, ALIGN);
+    // one cleared region: bucket-total counters, done counters, scratch rows
+    L.off_z = off;
+    L.off_done = off + align_up((size_t)colsum_rows(L.B) * L.B * 4, 64);
+    L.off_scratch = L.off_done + align_up(SPLIT_SLOTS * 4, 64);
+    off = L.off_scratch + (L.X > 0 ? (size_t)SPLIT_SLOTS * PART_W * 4 : 0);
+    L.nz = (off - L.off_z) / 4;
+    off = align_up(off, ALIGN);
   }
   L.bytes = off + ALIGN;  // slack for aligning the caller's pointer
   return L;
 }
 
-// k_init: clear the control block, the look-back flags, and optionally H.
-__global__ void k_init(Ctl* ctl, uint64_t* tiles, uint64_t ntiles, uint32_t* H, uint64_t nH) {
+// k_init: clear the control block, the look-back flags, the bucket-total
+// counters, and optionally H.
+__global__ void k_init(Ctl* ctl, uint64_t* tiles, uint64_t ntiles, uint32_t* z, uint64_t nz, uint32_t* H,
+                       uint64_t nH) {
   const uint64_t tid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   uint32_t* c = reinterpret_cast<uint32_t*>(ctl);
   if (tid < sizeof(Ctl) / 4) c[tid] = 0;
   for (uint64_t i = tid; i < ntiles; i += stride) tiles[i] = 0;
+  for (uint64_t i = tid; i < nz; i += stride) z[i] = 0;
   for (uint64_t i = tid; i < nH; i += stride) H[i] = 0;
 }
 
 dialsort_status launch_init(char* base, const Layout& L, uint32_t* H, uint64_t nH, hipStream_t s) {
-  const uint64_t work = std::max<uint64_t>(std::max<uint64_t>(64, L.scan ? L.scan_tiles : 0), nH);
+  const uint64_t nz = L.kind == K_PART ? L.nz : 0;
+  const uint64_t work = std::max<uint64_t>(std::max<uint64_t>(std::max<uint64_t>(64, L.scan ? L.scan_tiles : 0), nH), nz);
   const uint32_t grid = (uint32_t)std::min<uint64_t>(cdiv(work, 256), 2048);
   DS_LAUNCH(k_init, dim3(grid), dim3(256), s, (Ctl*)base, (uint64_t*)(base + L.off_tile),
-            L.scan ? L.scan_tiles : 0, H, nH);
+            L.scan ? L.scan_tiles : 0, (uint32_t*)(base + L.off_z), nz, H, nH);
   return DIALSORT_OK;
 }
 
@@ -168,19 +188,26 @@ dialsort_status launch_ingest(const uint32_t* keys, uint64_t n, uint64_t U, uint
     case K_PART: {
       uint16_t* stg = (uint16_t*)(base + L.off_stage);
       uint16_t* seg = (uint16_t*)(base + L.off_seg);
+      SplitPlan plan;
+      plan.colsum = (uint32_t*)(base + L.off_z);
+      plan.rows = colsum_rows(L.B);
+      plan.done = (uint32_t*)(base + L.off_done);
+      plan.scratch = (uint32_t*)(base + L.off_scratch);
+      plan.chunk = L.chunk;
+      plan.X = L.X;
       if (L.B <= 1024) {
-        if (ka) DS_LAUNCH((k_partition<1024, 3, true>), dim3(L.T), dim3(P1_NT), s, keys, n, umax, L.B, stg, seg, L.bstride, ctl);
-        else DS_LAUNCH((k_partition<1024, 3, false>), dim3(L.T), dim3(P1_NT), s, keys, n, umax, L.B, stg, seg, L.bstride, ctl);
+        if (ka) DS_LAUNCH((k_partition<1024, 3, true>), dim3(L.T), dim3(P1_NT), s, keys, n, umax, L.B, stg, seg, L.bstride, ctl, plan);
+        else DS_LAUNCH((k_partition<1024, 3, false>), dim3(L.T), dim3(P1_NT), s, keys, n, umax, L.B, stg, seg, L.bstride, ctl, plan);
       } else {
-        if (ka) DS_LAUNCH((k_partition<PART_BMAX, 3, true>), dim3(L.T), dim3(P1_NT), s, keys, n, umax, L.B, stg, seg, L.bstride, ctl);
-        else DS_LAUNCH((k_partition<PART_BMAX, 3, false>), dim3(L.T), dim3(P1_NT), s, keys, n, umax, L.B, stg, seg, L.bstride, ctl);
+        if (ka) DS_LAUNCH((k_partition<PART_BMAX, 3, true>), dim3(L.T), dim3(P1_NT), s, keys, n, umax, L.B, stg, seg, L.bstride, ctl, plan);
+        else DS_LAUNCH((k_partition<PART_BMAX, 3, false>), dim3(L.T), dim3(P1_NT), s, keys, n, umax, L.B, stg, seg, L.bstride, ctl, plan);
       }
       FillItem* items = (FillItem*)(base + L.off_items);
       const uint32_t icap = (uint32_t)std::min<uint64_t>(L.item_cap, 0xFFFFFFF0ull);
       const bool ha = aligned16(H);
-#define DS_BUCKET(HA, FULL)                                                                                      \
-  DS_LAUNCH((k_bucket<3, HA, FULL>), dim3(L.B), dim3(PART_NT), s, stg, seg, L.bstride, L.T, L.B, U, H, ctl, items, \
-            icap, FILL_CL2)
+#define DS_BUCKET(HA, FULL)                                                                                   \
+  DS_LAUNCH((k_bucket<3, HA, FULL>), dim3(L.B + L.X), dim3(PART_NT), s, stg, seg, L.bstride, L.T, L.B, U, H, ctl, \
+            items, icap, FILL_CL2, plan)
       if (!L.scan) {
         if (ha) DS_BUCKET(true, false); else DS_BUCKET(false, false);
       } else {

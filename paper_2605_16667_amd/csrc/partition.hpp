@@ -46,6 +46,28 @@ constexpr int PART_NT = 1024;    // pass-2 workgroup
 constexpr int P1_NT = 512;       // pass-1 workgroup (two per CU)
 constexpr uint32_t PART_BMAX = 8192;
 constexpr uint64_t PART_UMAX = (uint64_t)PART_W * PART_BMAX;  // 2^29
+constexpr uint32_t SPLIT_SLOTS = 16;  // heavy buckets that may be split between workgroups in one call
+constexpr uint32_t HEAVY_MAX = 512;   // heavy buckets ranked for the slots (the first ones in bucket order)
+
+// Rows of bucket-total counters the partition adds into (tile t into row t mod
+// rows): enough rows to spread the atomics, at most 8192 counters in all.
+__host__ __device__ constexpr uint32_t colsum_rows(uint32_t B) {
+  return B <= 256 ? 16u : (B <= 1024 ? 4u : (B <= 4096 ? 2u : 1u));
+}
+
+// Heavy-bucket splitting on the partitioned path.  The partition adds each
+// tile's bucket counts into colsum (row tile mod rows); the bucket pass reads
+// the totals back and lets several workgroups count a heavy bucket, each into
+// the bucket's scratch row of 32-bit counters.  colsum, done and scratch are
+// cleared before the partition runs.
+struct SplitPlan {
+  uint32_t* colsum;   // rows x B bucket-total counters
+  uint32_t rows;      // colsum_rows(B)
+  uint32_t* done;     // per slot: parts finished
+  uint32_t* scratch;  // SPLIT_SLOTS rows of PART_W counters
+  uint64_t chunk;     // keys per part of a split bucket
+  uint32_t X;         // extra workgroups of the bucket pass
+};
 
 // ---------------------------------------------------------------------------
 // Pass 1
@@ -60,11 +82,13 @@ struct PartSmem {
 // Tile `tile` of TK keys (NT threads; TK <= 65536 so segment starts fit in uint16).  seg: T rows of `bstride` uint16
 // (bstride >= B + 1, multiple of 8).  Invalid keys are parked as 0xFFFFFFFF
 // (U <= 2^29 here, so no valid key has that value).  Bucket of x: x >> LOG2W.
+// plan (optional): the tile adds its bucket counts into counter row tile mod
+// plan->rows.
 template <int NT, int BMAXT, int AGG, bool ALIGNED, int LOG2W, int TK>
 __device__ __forceinline__ void partition_tile(PartSmem<NT, BMAXT, TK>& S, const uint32_t* __restrict__ keys, uint64_t n,
                                                uint32_t umax, uint32_t B, uint16_t* __restrict__ staging,
                                                uint16_t* __restrict__ seg, uint32_t bstride, uint32_t* status,
-                                               uint32_t tile) {
+                                               uint32_t tile, const SplitPlan* plan) {
   constexpr int GPT = TK / 4 / NT;  // key groups of 4 per thread
   static_assert(GPT >= 1, "a tile gives every thread at least one group");
   constexpr uint32_t WM = (1u << LOG2W) - 1;
@@ -130,6 +154,7 @@ __device__ __forceinline__ void partition_tile(PartSmem<NT, BMAXT, TK>& S, const
     const uint32_t i = tid * CPT + j;
     loc[j] = i <= B ? S.cnt[i] : 0;
     sum += loc[j];
+    if (plan != nullptr && i < B && loc[j]) atomicAdd(&plan->colsum[(tile & (plan->rows - 1)) * B + i], loc[j]);
   }
   uint32_t total;
   uint32_t pre = block_exclusive_sum<NT>(sum, S.scan_tmp, &total);
@@ -203,14 +228,35 @@ __device__ __forceinline__ void partition_tile(PartSmem<NT, BMAXT, TK>& S, const
   __syncthreads();  // S is reused by the caller's next tile
 }
 
+// Block sum over NT threads (result in every thread).  Ends with a barrier, so
+// that S.red may be written by the next block operation at once: without it a
+// fast wave could overwrite S.red while slower waves still read it, and the
+// waves would then see different sums.
+template <int NT, typename SM>
+__device__ __forceinline__ uint64_t block_sum(SM& S, uint64_t x) {
+  const uint32_t lane = lane_id(), w = threadIdx.x / WAVE;
+  x = wave_sum(x);
+  __syncthreads();
+  if (lane == 0) S.red[w] = x;
+  __syncthreads();
+  uint64_t a = 0;
+  for (uint32_t i = 0; i < NT / WAVE; ++i) a += S.red[i];
+  __syncthreads();
+  // the same in every lane: keep it in scalar registers
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
 template <int BMAXT, int AGG, bool ALIGNED>
 __global__ __launch_bounds__(P1_NT) void k_partition(const uint32_t* __restrict__ keys, uint64_t n,
                                                      uint32_t umax, uint32_t B,
                                                      uint16_t* __restrict__ staging,
-                                                     uint16_t* __restrict__ seg, uint32_t bstride, Ctl* ctl) {
+                                                     uint16_t* __restrict__ seg, uint32_t bstride, Ctl* ctl,
+                                                     SplitPlan plan) {
   __shared__ PartSmem<P1_NT, BMAXT, PART_TK> S;
-  partition_tile<P1_NT, BMAXT, AGG, ALIGNED, PART_LOG2W, PART_TK>(S, keys, n, umax, B, staging, seg, bstride, &ctl->status,
-                                                         blockIdx.x);
+  partition_tile<P1_NT, BMAXT, AGG, ALIGNED, PART_LOG2W, PART_TK>(S, keys, n, umax, B, staging, seg, bstride,
+                                                                 &ctl->status, blockIdx.x, &plan);
 }
 
 // ---------------------------------------------------------------------------
@@ -256,27 +302,30 @@ enum GatherMode { GM_PACKED, GM_HALF, GM_DIRECT };
 // and without a segment quad 0 -- so the loads have no branches around them
 // and stay in flight together; masks keep keys outside [s, e) out of the count.
 // The bounds of a wave's next group are loaded before its current group is
-// counted.
+// counted.  Only tiles [t0, t1) are visited; returns the number of keys in the
+// segments this thread owned (each segment belongs to one lane of one wave).
 template <int NT, int LOG2W, int AGG, GatherMode GM, int TK>
-__device__ __forceinline__ void bucket_gather(BinSmem<NT, LOG2W>& S, const uint16_t* __restrict__ staging,
-                                              const uint16_t* __restrict__ seg, uint32_t bstride, uint32_t T,
-                                              uint32_t b, uint32_t half) {
+__device__ __forceinline__ uint32_t bucket_gather(BinSmem<NT, LOG2W>& S, const uint16_t* __restrict__ staging,
+                                                  const uint16_t* __restrict__ seg, uint32_t bstride, uint32_t t0,
+                                                  uint32_t t1, uint32_t b, uint32_t half) {
   static_assert(TK % 8 == 0 && TK <= 32768, "tile-local key indices and quad offsets fit 16 bits");
   constexpr uint32_t NW = NT / WAVE;
   WaveAgg st;
   const uint32_t lane = lane_id(), w = threadIdx.x / WAVE;
   const uint4* sq = reinterpret_cast<const uint4*>(staging);
-  if (T == 0) return;
+  uint32_t counted = 0;
+  if (t1 <= t0) return 0;
+  const uint32_t T = t1 - t0;               // tiles t0 + i, i < T
   const uint32_t G = (T + WAVE - 1) / WAVE;  // groups of 64 tiles
   const uint32_t wpg = G < NW ? NW / G : 1;  // waves per group
   const uint32_t gstep = NW / wpg;           // groups between a wave's groups
   const uint32_t sub = w % wpg;
-  if (w >= gstep * wpg) return;  // spare waves when NW is not a multiple of G
+  if (w >= gstep * wpg) return 0;  // spare waves when NW is not a multiple of G
   // segment bounds of this lane's tile in group g (a clamped row past the end)
   auto bounds = [&](uint32_t g, uint32_t& lo, uint32_t& hi) {
-    uint32_t t = g * WAVE + lane;
-    t = t < T ? t : T - 1;
-    const uint16_t* row = seg + (uint64_t)t * bstride;
+    uint32_t i = g * WAVE + lane;
+    i = i < T ? i : T - 1;
+    const uint16_t* row = seg + (uint64_t)(t0 + i) * bstride;
     lo = row[b];
     hi = row[b + 1];
   };
@@ -286,10 +335,12 @@ __device__ __forceinline__ void bucket_gather(BinSmem<NT, LOG2W>& S, const uint1
   for (; g < G; g += gstep) {
     uint32_t nlo, nhi;
     bounds(g + gstep < G ? g + gstep : g, nlo, nhi);
-    const uint32_t t = g * WAVE + lane;
+    const uint32_t i = g * WAVE + lane;
+    const uint32_t t = t0 + i;
     uint32_t e = hi < (uint32_t)TK ? hi : (uint32_t)TK;  // a segment never leaves its tile
     uint32_t s = lo < e ? lo : e;
-    if (t >= T) s = e = 0;
+    if (i >= T) s = e = 0;
+    if (sub == 0) counted += e - s;  // waves sharing a group count its keys once
     const uint32_t q0 = s >> 3;
     const uint32_t nq = e > s ? ((e + 7) >> 3) - q0 : 0;
     const uint32_t kmax = wave_max(nq);
@@ -333,6 +384,7 @@ __device__ __forceinline__ void bucket_gather(BinSmem<NT, LOG2W>& S, const uint1
     lo = nlo;
     hi = nhi;
   }
+  return counted;
 }
 
 // Count of relative bin k on the packed path (no field wrapped).
@@ -341,25 +393,6 @@ __device__ __forceinline__ uint32_t packed_count(const SM& S, uint32_t k) {
   return (S.s[k >> 1] >> ((k & 1u) << 4)) & 0xFFFFu;
 }
 
-// Block sum over NT threads (result in every thread).  Ends with a barrier, so
-// that S.red may be written by the next block operation at once: without it a
-// fast wave could overwrite S.red while slower waves still read it, and the
-// waves would then see different sums.
-template <int NT, typename SM>
-__device__ __forceinline__ uint64_t block_sum(SM& S, uint64_t x) {
-  const uint32_t lane = lane_id(), w = threadIdx.x / WAVE;
-  x = wave_sum(x);
-  __syncthreads();
-  if (lane == 0) S.red[w] = x;
-  __syncthreads();
-  uint64_t a = 0;
-  for (uint32_t i = 0; i < NT / WAVE; ++i) a += S.red[i];
-  __syncthreads();
-  // the same in every lane: keep it in scalar registers
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
-  return ((uint64_t)hi << 32) | lo;
-}
 
 // Append fill items for this thread's bins: the thread owns NB consecutive bins
 // starting at relative bin j0, whose counts come from count(j) and sum to len;
@@ -558,91 +591,279 @@ __device__ __forceinline__ uint64_t project_piece(SM& S, uint32_t* status, uint3
 // ---------------------------------------------------------------------------
 // Pass 2
 // ---------------------------------------------------------------------------
-// Bucket b of W = 2^LOG2W bins (T tiles): H receives bins [b*W, min((b+1)*W, U)).
-// FULL also appends the fill items of the bucket's sorted run.  With W = 2^16
-// the bucket is counted into packed 16-bit fields; a field that passed 0xFFFF
-// shows up as a sum of all fields below the number of keys gathered (a wrap of
-// a low field costs 65535, of a high field 65536), and the bucket is then
-// counted again, exactly, in two halves of 2^15 bins with 32-bit counters.
-template <int NT, int LOG2W, int AGG, bool HALIGNED, bool FULL, int TK>
-__device__ __forceinline__ void bucket_body(BinSmem<NT, LOG2W>& S, const uint16_t* __restrict__ staging,
-                                            const uint16_t* __restrict__ seg, uint32_t bstride, uint32_t T,
-                                            uint64_t U, uint32_t* __restrict__ H, uint32_t* status,
-                                            uint32_t* nitems, FillItem* __restrict__ items, uint32_t item_cap,
-                                            int CL2, uint32_t b) {
-  constexpr uint32_t W = 1u << LOG2W;
-  using SM = BinSmem<NT, LOG2W>;
-  const uint32_t tid = threadIdx.x;
-  const uint64_t hb = (uint64_t)b * W;
-  const uint32_t cnt = (uint32_t)(U - hb < W ? U - hb : W);
-  const uint32_t klast = (uint32_t)(hb + cnt - 1);
-
-  // where the bucket's run starts (keys of earlier buckets) and its length; the
-  // pass also brings the segment bounds into the caches for the gather, whose
-  // lanes visit the same tiles
+// Where bucket b's sorted run starts (the keys of buckets before b: the sum of
+// seg[t][b] over the tiles) and how many keys it holds.  Result in every thread.
+template <int NT, typename SM>
+__device__ __forceinline__ void bucket_extent(SM& S, const uint16_t* __restrict__ seg, uint32_t bstride, uint32_t T,
+                                              uint32_t b, uint64_t* base, uint64_t* total) {
   uint64_t mb = 0, mt = 0;
 #pragma unroll 4
-  for (uint32_t tt = tid; tt < T; tt += NT) {
-    const uint16_t* row = seg + (uint64_t)tt * bstride;
+  for (uint32_t t = threadIdx.x; t < T; t += NT) {
+    const uint16_t* row = seg + (uint64_t)t * bstride;
     const uint32_t lo = row[b], hi = row[b + 1];
     mb += lo;
     mt += hi - lo;
   }
-  const uint64_t base = block_sum<NT>(S, mb);
-  const uint64_t total = block_sum<NT>(S, mt);
-  for (uint32_t i = tid; i < SM::WORDS; i += NT) S.s[i] = 0;
-  __syncthreads();
-  bucket_gather<NT, LOG2W, AGG, SM::PACKED ? GM_PACKED : GM_DIRECT, TK>(S, staging, seg, bstride, T, b, 0);
-  __syncthreads();
+  *base = block_sum<NT>(S, mb);
+  *total = block_sum<NT>(S, mt);
+}
 
-  if constexpr (!SM::PACKED) {
-    // ---- W <= 2^15: 32-bit counters ----------------------------------------
-    for (uint32_t i = tid; i < cnt; i += NT) H[hb + i] = S.s[i];
-    if constexpr (FULL) {
-      if (total) project_piece<NT, W / NT, false>(S, status, nitems, items, item_cap, CL2, base, hb, cnt, klast);
-    }
-    return;
-  } else {
-    // ---- packed fields: H from whole words, and the sum of the fields ------
-    uint64_t fsum = 0;
-    for (uint32_t wv = tid; wv < (cnt + 1) / 2; wv += NT) {
+// One part of bucket b: its segments in tiles [t0, t1), part p of P.  With
+// P == 1 the part is the whole bucket and writes H with plain stores; with
+// P > 1 (a heavy bucket) every part adds its counts into a cleared row of
+// 32-bit scratch counters with global atomics, and the part that finishes last
+// copies the row into H and projects the bucket from it.  base: keys of the
+// buckets before b.
+struct BucketPart {
+  uint32_t b, t0, t1, P;
+  uint64_t base;
+  uint32_t* acc;   // P > 1: the bucket's scratch row
+  uint32_t* done;  // P > 1: parts finished so far (starts at 0)
+};
+
+// Bins [lo, lo + len) of LDS counters into H[hb + lo + ...]: stored, or (add)
+// added where nonzero.  PACKED_SRC reads bin j from the 16-bit field j of the
+// packed words, else from word j - lo0 (32-bit counters of a piece starting at
+// lo0).
+template <int NT, bool PACKED_SRC, bool HALIGNED, typename SM>
+__device__ __forceinline__ void emit_bins(const SM& S, uint32_t* __restrict__ H, uint64_t hb, uint32_t lo0,
+                                          uint32_t len, bool add) {
+  const uint32_t tid = threadIdx.x;
+  if constexpr (PACKED_SRC) {
+    // len bins from bin 0, two per word
+    for (uint32_t wv = tid; wv < (len + 1) / 2; wv += NT) {
       const uint32_t k = 2 * wv;
       const uint32_t word = S.s[wv];
       const uint32_t c0 = word & 0xFFFFu, c1 = word >> 16;
-      fsum += c0 + c1;
-      if (HALIGNED && k + 1 < cnt) {
+      if (add) {
+        if (c0) atomicAdd(&H[hb + k], c0);
+        if (c1 && k + 1 < len) atomicAdd(&H[hb + k + 1], c1);
+      } else if (HALIGNED && k + 1 < len) {
         *reinterpret_cast<uint2*>(H + hb + k) = make_uint2(c0, c1);
       } else {
         H[hb + k] = c0;
-        if (k + 1 < cnt) H[hb + k + 1] = c1;
+        if (k + 1 < len) H[hb + k + 1] = c1;
       }
     }
-    if (block_sum<NT>(S, fsum) == total) {
-      if constexpr (FULL) {
-        if (total) project_piece<NT, W / NT, true>(S, status, nitems, items, item_cap, CL2, base, hb, cnt, klast);
-      }
-      return;
-    }
-
-    // ---- a field wrapped: two halves of 2^15 bins with 32-bit counters -----
-    uint64_t hbase = base;  // where the current half's run starts
-    for (uint32_t half = 0; half < 2; ++half) {
-      const uint32_t hb0 = half << 15;
-      if (hb0 >= cnt) break;
-      const uint32_t hcnt = cnt - hb0 < (1u << 15) ? cnt - hb0 : (1u << 15);
-      __syncthreads();
-      for (uint32_t i = tid; i < SM::WORDS; i += NT) S.s[i] = 0;
-      if (tid == 0) S.n = 0;
-      __syncthreads();
-      bucket_gather<NT, LOG2W, AGG, GM_HALF, TK>(S, staging, seg, bstride, T, b, half);
-      __syncthreads();
-      for (uint32_t i = tid; i < hcnt; i += NT) H[hb + hb0 + i] = S.s[i];
-      if constexpr (FULL) {
-        hbase += project_piece<NT, (1u << 15) / NT, false>(S, status, nitems, items, item_cap, CL2, hbase,
-                                                           hb + hb0, hcnt, klast);
+  } else {
+    for (uint32_t i = tid; i < len; i += NT) {
+      const uint32_t c = S.s[i];
+      if (add) {
+        if (c) atomicAdd(&H[hb + lo0 + i], c);
+      } else {
+        H[hb + lo0 + i] = c;
       }
     }
   }
+}
+
+// Bucket b of W = 2^LOG2W bins: H receives bins [b*W, min((b+1)*W, U)), and
+// FULL also appends the fill items of the bucket's sorted run.  With W = 2^16
+// the bucket is counted into packed 16-bit fields; a field that passed 0xFFFF
+// shows up as a sum of all fields below the number of keys gathered (a wrap of
+// a low field costs 65535, of a high field 65536), and the part is then
+// counted again, exactly, in two halves of 2^15 bins with 32-bit counters.
+template <int NT, int LOG2W, int AGG, bool HALIGNED, bool FULL, int TK>
+__device__ __forceinline__ void bucket_body(BinSmem<NT, LOG2W>& S, const uint16_t* __restrict__ staging,
+                                            const uint16_t* __restrict__ seg, uint32_t bstride, uint64_t U,
+                                            uint32_t* __restrict__ H, uint32_t* status, uint32_t* nitems,
+                                            FillItem* __restrict__ items, uint32_t item_cap, int CL2,
+                                            const BucketPart& bp) {
+  constexpr uint32_t W = 1u << LOG2W;
+  using SM = BinSmem<NT, LOG2W>;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t b = bp.b;
+  const uint64_t hb = (uint64_t)b * W;
+  const uint32_t cnt = (uint32_t)(U - hb < W ? U - hb : W);
+  const uint32_t klast = (uint32_t)(hb + cnt - 1);
+  const bool split = bp.P > 1;
+
+  for (uint32_t i = tid; i < SM::WORDS; i += NT) S.s[i] = 0;
+  __syncthreads();
+  const uint32_t mine =
+      bucket_gather<NT, LOG2W, AGG, SM::PACKED ? GM_PACKED : GM_DIRECT, TK>(S, staging, seg, bstride, bp.t0, bp.t1, b, 0);
+  // the block sums end with barriers: every LDS count is in place afterwards
+  const uint64_t gathered = block_sum<NT>(S, (uint64_t)mine);
+
+  // a split part adds into its bucket's scratch row instead of H
+  uint32_t* const dst = split ? bp.acc : H;
+  const uint64_t dhb = split ? 0 : hb;
+  if constexpr (!SM::PACKED) {
+    // ---- W <= 2^15: 32-bit counters ----------------------------------------
+    emit_bins<NT, false, HALIGNED>(S, dst, dhb, 0, cnt, split);
+    if constexpr (FULL) {
+      if (!split && gathered)
+        project_piece<NT, W / NT, false>(S, status, nitems, items, item_cap, CL2, bp.base, hb, cnt, klast);
+    }
+  } else {
+    uint64_t fsum = 0;
+    for (uint32_t wv = tid; wv < SM::WORDS; wv += NT) {
+      const uint32_t word = S.s[wv];
+      fsum += (word & 0xFFFFu) + (word >> 16);
+    }
+    if (block_sum<NT>(S, fsum) == gathered) {
+      // ---- no field wrapped ------------------------------------------------
+      emit_bins<NT, true, HALIGNED>(S, dst, dhb, 0, cnt, split);
+      if constexpr (FULL) {
+        if (!split && gathered)
+          project_piece<NT, W / NT, true>(S, status, nitems, items, item_cap, CL2, bp.base, hb, cnt, klast);
+      }
+    } else {
+      // ---- a field wrapped: two halves of 2^15 bins with 32-bit counters ---
+      uint64_t hbase = bp.base;  // where the current half's run starts
+      for (uint32_t half = 0; half < 2; ++half) {
+        const uint32_t hb0 = half << 15;
+        if (hb0 >= cnt) break;
+        const uint32_t hcnt = cnt - hb0 < (1u << 15) ? cnt - hb0 : (1u << 15);
+        __syncthreads();
+        for (uint32_t i = tid; i < SM::WORDS; i += NT) S.s[i] = 0;
+        __syncthreads();
+        bucket_gather<NT, LOG2W, AGG, GM_HALF, TK>(S, staging, seg, bstride, bp.t0, bp.t1, b, half);
+        __syncthreads();
+        emit_bins<NT, false, HALIGNED>(S, dst, dhb, hb0, hcnt, split);
+        if constexpr (FULL) {
+          if (!split)
+            hbase += project_piece<NT, (1u << 15) / NT, false>(S, status, nitems, items, item_cap, CL2, hbase,
+                                                               hb + hb0, hcnt, klast);
+        }
+      }
+    }
+  }
+  if (!split) return;
+
+  // ---- a part of a heavy bucket: the last part to finish completes it ------
+  // every wave waits until its own atomics are acknowledged; then thread 0
+  // counts the part as done
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (tid == 0) S.n = __hip_atomic_fetch_add(bp.done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  if (S.n != bp.P - 1) return;
+  constexpr uint32_t PW = W < (1u << 15) ? W : (1u << 15);  // bins per piece
+  uint64_t pbase = bp.base;
+  for (uint32_t p0 = 0; p0 < cnt; p0 += PW) {
+    const uint32_t pcnt = cnt - p0 < PW ? cnt - p0 : PW;
+    __syncthreads();
+    // every part's adds are complete: read them with device-scope loads
+    for (uint32_t i = tid; i < PW; i += NT) {
+      uint32_t c = 0;
+      if (i < pcnt) {
+        c = __hip_atomic_load(&bp.acc[p0 + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        H[hb + p0 + i] = c;
+      }
+      S.s[i] = c;
+    }
+    __syncthreads();
+    if constexpr (FULL)
+      pbase += project_piece<NT, PW / NT, false>(S, status, nitems, items, item_cap, CL2, pbase, hb + p0, pcnt,
+                                                 klast);
+  }
+}
+
+// The split plan, computed by every workgroup of the bucket pass from the
+// partition's bucket-total counters (the same result in each): which part of
+// which bucket workgroup `blk` counts, and the run start of that bucket.  A
+// bucket is heavy when it holds more than 2 * chunk keys; the SPLIT_SLOTS
+// heaviest (among the first HEAVY_MAX heavy buckets in bucket order) get
+// scratch slots and want ceil(total / chunk) - 1 extra parts each, handed out
+// heaviest first while the X extra workgroups last.  Workgroup i < B takes part 0 of a bucket
+// (XCD-aware order: blocks are dispatched round-robin over 8 XCDs, so each XCD
+// takes a contiguous range of buckets); workgroup B + e takes extra part e, if
+// it exists.  Returns false for a workgroup without a part.
+template <int NT, typename SM>
+__device__ __forceinline__ bool plan_part(SM& S, const SplitPlan& plan, uint32_t B, uint32_t T, uint32_t blk,
+                                          BucketPart& bp) {
+  static_assert(SM::WORDS >= PART_BMAX + 3 * SPLIT_SLOTS + HEAVY_MAX, "totals and tables fit the counters");
+  static_assert(HEAVY_MAX <= NT, "one thread per listed heavy bucket");
+  uint32_t* tot = S.s;               // per bucket
+  uint32_t* tab = S.s + PART_BMAX;   // per slot: bucket, first extra part, extra parts wanted
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t i = tid; i < B; i += NT) tot[i] = 0;
+  __syncthreads();
+  const uint32_t ncnt = plan.rows * B;
+#pragma unroll 4
+  for (uint32_t i = tid; i < ncnt; i += NT) {
+    const uint32_t v = plan.colsum[i];
+    if (v) atomicAdd(&tot[i % B], v);
+  }
+  __syncthreads();
+  // heavy buckets, listed in bucket order (at most HEAVY_MAX of them), then
+  // ranked by total, heaviest first (ties: lower bucket first)
+  uint32_t* hl = tab + 3 * SPLIT_SLOTS;  // heavy list: bucket indices
+  uint32_t nheavy = 0;
+  for (uint32_t r0 = 0; r0 < B; r0 += NT) {
+    const uint32_t bb = r0 + tid;
+    const uint32_t heavy = plan.X > 0 && bb < B && (uint64_t)tot[bb] > 2 * plan.chunk ? 1u : 0u;
+    uint32_t round_heavy;
+    const uint32_t at = nheavy + block_exclusive_sum<NT>(heavy, reinterpret_cast<uint32_t*>(S.red), &round_heavy);
+    if (heavy && at < HEAVY_MAX) hl[at] = bb;
+    nheavy += round_heavy;
+  }
+  if (nheavy > HEAVY_MAX) nheavy = HEAVY_MAX;
+  __syncthreads();
+  if (tid < nheavy) {
+    const uint32_t mb = hl[tid];
+    const uint32_t mt = tot[mb];
+    uint32_t rank = 0;
+    for (uint32_t j = 0; j < nheavy; ++j) {
+      const uint32_t ob = hl[j], ot = tot[ob];
+      rank += (ot > mt || (ot == mt && ob < mb)) ? 1u : 0u;
+    }
+    if (rank < SPLIT_SLOTS) {
+      tab[3 * rank] = mb;
+      const uint64_t w = ((uint64_t)mt + plan.chunk - 1) / plan.chunk - 1;
+      tab[3 * rank + 2] = w < plan.X ? (uint32_t)w : plan.X;
+    }
+  }
+  __syncthreads();
+  const uint32_t nslot = nheavy < SPLIT_SLOTS ? nheavy : SPLIT_SLOTS;
+  if (tid == 0) {
+    uint32_t first = 0;  // extra parts go to the slots in rank order
+    for (uint32_t sl = 0; sl < nslot; ++sl) {
+      tab[3 * sl + 1] = first;
+      first += tab[3 * sl + 2];
+    }
+  }
+  __syncthreads();
+  // extra parts a slot got: its wants, cut at X
+  auto got = [&](uint32_t sl) -> uint32_t {
+    const uint32_t first = tab[3 * sl + 1], want = tab[3 * sl + 2];
+    return first >= plan.X ? 0u : (want < plan.X - first ? want : plan.X - first);
+  };
+  uint32_t b = 0, p = 0;
+  if (blk < B) {
+    b = blk;
+    if ((B & 7u) == 0) b = (blk & 7u) * (B >> 3) + (blk >> 3);
+  } else {
+    const uint32_t e = blk - B;
+    bool found = false;
+    for (uint32_t sl = 0; sl < nslot; ++sl) {
+      const uint32_t first = tab[3 * sl + 1];
+      if (e >= first && e < first + got(sl)) {
+        b = tab[3 * sl];
+        p = 1 + (e - first);
+        found = true;
+      }
+    }
+    if (!found) return false;  // the same in every thread
+  }
+  bp.b = b;
+  bp.P = 1;
+  bp.acc = nullptr;
+  bp.done = nullptr;
+  for (uint32_t sl = 0; sl < nslot; ++sl) {
+    if (tab[3 * sl] == b && got(sl) > 0) {
+      bp.P = 1 + got(sl);
+      bp.acc = plan.scratch + (uint64_t)sl * PART_W;
+      bp.done = plan.done + sl;
+    }
+  }
+  bp.t0 = (uint32_t)((uint64_t)p * T / bp.P);
+  bp.t1 = (uint32_t)((uint64_t)(p + 1) * T / bp.P);
+  uint64_t below = 0;
+  for (uint32_t bb = tid; bb < b; bb += NT) below += tot[bb];
+  bp.base = block_sum<NT>(S, below);  // ends with a barrier: S.s is free again
+  return true;
 }
 
 template <int AGG, bool HALIGNED, bool FULL>
@@ -650,13 +871,12 @@ __global__ __launch_bounds__(PART_NT) void k_bucket(const uint16_t* __restrict__
                                                     const uint16_t* __restrict__ seg, uint32_t bstride,
                                                     uint32_t T, uint32_t B, uint64_t U, uint32_t* __restrict__ H,
                                                     Ctl* ctl, FillItem* __restrict__ items, uint32_t item_cap,
-                                                    int CL2) {
+                                                    int CL2, SplitPlan plan) {
   __shared__ __align__(16) BinSmem<PART_NT, PART_LOG2W> S;
-  // XCD-aware bucket order: blocks are dispatched round-robin over 8 XCDs
-  uint32_t b = blockIdx.x;
-  if ((B & 7u) == 0) b = (blockIdx.x & 7u) * (B >> 3) + (blockIdx.x >> 3);
-  bucket_body<PART_NT, PART_LOG2W, AGG, HALIGNED, FULL, PART_TK>(S, staging, seg, bstride, T, U, H, &ctl->status,
-                                                        &ctl->nitems, items, item_cap, CL2, b);
+  BucketPart bp;
+  if (!plan_part<PART_NT>(S, plan, B, T, blockIdx.x, bp)) return;
+  bucket_body<PART_NT, PART_LOG2W, AGG, HALIGNED, FULL, PART_TK>(S, staging, seg, bstride, U, H, &ctl->status,
+                                                                &ctl->nitems, items, item_cap, CL2, bp);
 }
 
 // ---------------------------------------------------------------------------
