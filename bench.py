@@ -12,11 +12,20 @@ fields of the same line:
   plain    n = 2^20 uniform keys, U = 2^16 (latency of one sort)
   skewed   n = 2^28, U = 2^16, half the keys one hot value, the rest Zipf(1.2);
            beside it the same n and U with uniform keys
+  batch    4096 uneven arrays: one autotuned fused launch replayed from a HIP
+           graph, against one launch sequence per array; per-array p50/p99
+  serve    a Poisson request stream through the serving engine at several
+           loads, against serial plain sorts; p50/p99 latency and keys/s
 The roofline object is for the kernel that takes the most time per step,
 measured with HIP events recorded on the launch stream around every kernel of
 every timed step (dialsort_set_launch_events).  Its algorithmic bytes are the
-method's compulsory traffic that this kernel is responsible for (see the table
-ALGO_BYTES below).
+method's compulsory traffic that this kernel is responsible for (algo_bytes
+below); its `traffic` is the HBM bytes per launch that rocprofv3 counted for
+this very kernel source (profiles/large_uniform_sort_counters.txt: FETCH_SIZE
+and WRITE_SIZE scaled by what they read for a plain device copy), or null when
+the kernels changed since the counters were taken.  path_roofline relates the
+whole step to the path's algorithmic bytes, against the 8 TB/s peak and
+against the bandwidth a plain device copy reaches on the same GPU.
 """
 
 from __future__ import annotations
@@ -71,21 +80,69 @@ class HipEvents:
             self.lib.hipEventDestroy(ev)
 
 
-def algo_bytes(name: str, n: int, U: int) -> int:
+def algo_bytes(name: str, n: int, U: int, mode: str) -> int:
     """Compulsory bytes of the method handled by one launch of kernel `name`:
-    ingestion reads the keys (4n), the histogram is written once (4U) and read
-    once by the projection (4U), the projection writes the output (4n).  Partial
-    rows, staging and fill-item traffic are the implementation's own and count
-    against the kernel."""
+    ingestion reads the keys (4n), the histogram is written once (4U) and, in a
+    sort, read once by the projection (4U), which writes the output (4n).  The
+    kernel that produces H also reads it for the projection (k_bucket from LDS,
+    k_scan as it goes); the fill only writes.  Partial rows, staging, counters
+    and fill items are the implementation's own and count against the kernel."""
+    full = mode == "sort"
     if "k_hist" in name or "k_partition" in name:
         return 4 * n
-    if "k_bucket" in name:
-        return 4 * U
-    if "k_scan" in name:
-        return 4 * U
+    if "k_bucket" in name or "k_scan" in name:
+        return (8 if full else 4) * U
     if "k_fill" in name:
         return 4 * n
     return 0
+
+
+def source_digest() -> str:
+    """sha256 over the library's kernel and host sources (names and contents)."""
+    import hashlib
+
+    d = os.path.join(ROOT, "paper_2605_16667_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        h.update(f.encode())
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _kname(s: str) -> str:
+    return s.replace("ds::", "").replace("(", "").replace(")", "").replace(" ", "")
+
+
+def profiled_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if it
+    was taken on the current sources: FETCH_SIZE and WRITE_SIZE (KiB per
+    dispatch) each times the factor that maps the same counter onto the bytes of
+    a plain device copy.  None when absent or stale."""
+    path = os.path.join(ROOT, "profiles", "large_uniform_sort_counters.txt")
+    try:
+        lines = open(path).read().splitlines()
+    except OSError:
+        return None
+    digest, fs, ws, vals = None, None, None, {}
+    for ln in lines:
+        if ln.startswith("# source-sha256:"):
+            digest = ln.split(":", 1)[1].strip()
+        elif ln.startswith("# scale:"):
+            parts = dict(x.split("=") for x in ln.split(":", 1)[1].split())
+            fs, ws = float(parts["fetch"]), float(parts["write"])
+        elif not ln.startswith("#") and ln.strip():
+            cols = ln.split()
+            if len(cols) >= 4 and cols[-3] in ("FETCH_SIZE", "WRITE_SIZE"):
+                vals[(_kname(" ".join(cols[:-3])), cols[-3])] = float(cols[-1])
+    if digest != source_digest() or fs is None:
+        return None
+    k = _kname(kernel)
+    f, w_ = vals.get((k, "FETCH_SIZE")), vals.get((k, "WRITE_SIZE"))
+    if f is None or w_ is None:
+        return None
+    return {"bytes": (f * fs + w_ * ws) * 1024.0, "fetch_bytes": f * fs * 1024.0, "write_bytes": w_ * ws * 1024.0,
+            "source": "profiles/large_uniform_sort_counters.txt"}
 
 
 def time_calls(ds, hip, call, K, W, n, U, nev=12):
@@ -129,13 +186,47 @@ def time_calls(ds, hip, call, K, W, n, U, nev=12):
     }
 
 
-def roofline_of(res, n, U):
+def roofline_of(res, n, U, mode):
     kname, kst = max(res["kernels"].items(), key=lambda kv: kv[1]["avg_ms"])
     name = kname.split(":", 1)[1]
-    b = algo_bytes(name, n, U)
+    b = algo_bytes(name, n, U, mode)
     ach = b / (kst["avg_ms"] * 1e-3)
+    tr = profiled_traffic(name)
     return {"bound": "hbm", "kernel": name, "achieved": ach / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-            "frac": ach / HBM_PEAK, "traffic": None, "avg_ms": kst["avg_ms"], "algo_bytes": b}
+            "frac": ach / HBM_PEAK, "traffic": tr["bytes"] if tr else None, "avg_ms": kst["avg_ms"],
+            "algo_bytes": b, "traffic_detail": tr}
+
+
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    """Bytes read plus bytes written per second by a plain device-to-device copy
+    (torch's copy kernel) of nbytes: the bandwidth this GPU reaches on a pure
+    stream, the practical ceiling beside the 8 TB/s peak."""
+    import torch
+
+    a = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda")
+    a.fill_(1)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (ms * 1e-3)
+
+
+def with_copy_ceiling(pr, copy_bps):
+    pr = dict(pr)
+    pr["copy_GBps"] = copy_bps / 1e9
+    pr["frac_of_copy"] = pr["achieved_GBps"] * 1e9 / copy_bps
+    return pr
 
 
 def verify_sort(keys, U, H, out):
@@ -178,7 +269,7 @@ def run_sort_workload(ds, hip, keys, U, K, W, mode="sort"):
     res["keys_per_s"] = n / (res["ms_per_step"] * 1e-3)
     res["path_roofline"] = {"algo_bytes": algo, "achieved_GBps": algo / (res["ms_per_step"] * 1e-3) / 1e9,
                             "frac": algo / (res["ms_per_step"] * 1e-3) / HBM_PEAK}
-    res["roofline"] = roofline_of(res, n, U)
+    res["roofline"] = roofline_of(res, n, U, mode)
     del H, out, ws
     return res
 
@@ -484,16 +575,20 @@ def main():
         del a, b
     extra = {}
 
+    copy_bps = copy_bandwidth()
+    log(f"device copy: {copy_bps / 1e9:.0f} GB/s (read + write)")
     n, U = 10**8, 1 << 24
     log(f"large: generating n={n} U={U}")
     keys = w.uniform(n, U, w.BASE_SEED + 1, "cuda")
     torch.cuda.synchronize()
     log("large: sort")
     main_res = run_sort_workload(ds, hip, keys, U, K, W, "sort")
+    main_res["path_roofline"] = with_copy_ceiling(main_res["path_roofline"], copy_bps)
     log(f"large: {main_res['ms_per_step']:.4f} ms/step verified={main_res['verified']}")
     if "hist" in todo:
         log("large: histogram-only")
         r = run_sort_workload(ds, hip, keys, U, K, W, "hist")
+        r["path_roofline"] = with_copy_ceiling(r["path_roofline"], copy_bps)
         extra["histogram_only"] = {k: r[k] for k in ("ms_per_step", "best_ms", "median_ms", "cv", "keys_per_s",
                                                      "path_roofline", "roofline", "verified", "kernels")}
     cpu = None
