@@ -229,8 +229,8 @@ __device__ __forceinline__ uint64_t unit_fill(BatchSmem<NT, LOG2W>& S, const BAr
       const FillItem I = A.items[j];
       // an item always lies inside its array; anything else is a broken
       // invariant, reported instead of written
-      const bool valid = I.k <= I.klast && I.klast < A.U && I.o <= I.p0 && I.p0 < I.p1 && I.p1 <= A.n &&
-                         I.p1 - (I.p0 & ~3ull) <= (1ull << BT_CL2);
+      const bool valid = I.k <= I.klast && I.klast < A.U && I.klast - I.k < FILL_SPAN_MAX && I.o <= I.p0 &&
+                         I.p0 < I.p1 && I.p1 <= A.n && I.p1 - (I.p0 & ~3ull) <= (1ull << BT_CL2);
       if (!valid) {
         if (lane_id() == 0) atomicOr(status, ST_INT_ITEM);
         continue;

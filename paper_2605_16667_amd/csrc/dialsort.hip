@@ -255,8 +255,8 @@ dialsort_status launch_fill(const uint32_t* H, uint32_t* out, char* base, const 
   Ctl* ctl = (Ctl*)base;
   const FillItem* items = (const FillItem*)(base + L.off_items);
   if (L.limit == 0) return DIALSORT_OK;
-  // one resident round of workgroups (4 per CU at 256 threads), or fewer
-  const uint32_t grid = (uint32_t)std::min<uint64_t>(cdiv(L.item_cap, FILL_NT / WAVE), 256 * 4);
+  // one resident round of workgroups (7 per CU at 256 threads), or fewer
+  const uint32_t grid = (uint32_t)std::min<uint64_t>(cdiv(L.item_cap, FILL_NT / WAVE), 256 * 7);
   const uint32_t icap = (uint32_t)std::min<uint64_t>(L.item_cap, 0xFFFFFFF0ull);
   if (aligned16(out))
     DS_LAUNCH((k_fill<FILL_NT, FILL_CL2, true>), dim3(grid), dim3(FILL_NT), s, H, out, ctl, items, icap);

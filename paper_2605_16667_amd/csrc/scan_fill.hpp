@@ -258,13 +258,18 @@ __global__ __launch_bounds__(NT) void k_scan(const uint32_t* __restrict__ rows, 
 // with a0 = p0 rounded down to a multiple of 4; an item always fits in [0, C)
 // of that frame.  The wave's LDS: val[0, C) holds the key marked at each run
 // start, val[C + s] the key carried into 32-position segment s (the last mark
-// before it), flag[s] the marks of segment s.  LDS operations of one wave take
-// effect in program order, so no fence is needed between the phases.
+// before it), flag[s] the marks of segment s.  Keys are kept as 16-bit offsets
+// from the item's first bin (an item spans at most FILL_SPAN_MAX bins), which
+// halves the wave's LDS and doubles the waves a CU holds.  LDS operations of
+// one wave take effect in program order, so no fence is needed between the
+// phases.
+constexpr uint32_t FILL_SPAN_MAX = 65536;  // bins of one fill item (klast - k < this)
+
 template <int CL2>
 struct WaveFillSmem {
   static constexpr uint32_t C = 1u << CL2;
   static constexpr uint32_t NFW = C / 32;
-  __align__(16) uint32_t val[C + NFW];
+  __align__(16) uint16_t val[C + NFW];
   uint32_t flag[NFW];
 };
 
@@ -304,7 +309,7 @@ __device__ __forceinline__ void wave_fill_item(WaveFillSmem<CL2>& S, const uint3
     for (int j = 0; j < 4; ++j) {
       if (h[j] > 0 && ok < p1) {
         const uint32_t pos = ok <= p0 ? lb : (uint32_t)(ok - a0);
-        S.val[pos] = (uint32_t)(k0 + j);
+        S.val[pos] = (uint16_t)(k0 + j - I.k);
         atomicOr(&S.flag[pos >> 5], 1u << (pos & 31));
       }
       ok += h[j];
@@ -332,19 +337,20 @@ __device__ __forceinline__ void wave_fill_item(WaveFillSmem<CL2>& S, const uint3
   // at position p is the last mark at or before p in the segment, else the
   // segment's carried key
   const uint32_t nq = (le + 3) >> 2;
+  const uint32_t kf = I.k;
   for (uint32_t q = lane; q < nq; q += WAVE) {
     const uint32_t sg = q >> 3;
     const uint32_t fw = S.flag[sg];
     uint32_t r0, r1, r2, r3;
     if (fw == 0) {
-      r0 = r1 = r2 = r3 = S.val[C + sg];
+      r0 = r1 = r2 = r3 = kf + S.val[C + sg];
     } else {
       const uint32_t base = sg * 32u + 31u;
       const uint32_t m0 = fw & mk0, m1 = fw & mk1, m2 = fw & mk2, m3 = fw & mk3;
-      r0 = S.val[m0 ? base - __clz(m0) : C + sg];
-      r1 = S.val[m1 ? base - __clz(m1) : C + sg];
-      r2 = S.val[m2 ? base - __clz(m2) : C + sg];
-      r3 = S.val[m3 ? base - __clz(m3) : C + sg];
+      r0 = kf + S.val[m0 ? base - __clz(m0) : C + sg];
+      r1 = kf + S.val[m1 ? base - __clz(m1) : C + sg];
+      r2 = kf + S.val[m2 ? base - __clz(m2) : C + sg];
+      r3 = kf + S.val[m3 ? base - __clz(m3) : C + sg];
     }
     const uint32_t i0 = q << 2;
     if (OALIGNED && i0 >= lb && i0 + 4 <= le) {
@@ -362,7 +368,7 @@ __device__ __forceinline__ void wave_fill_item(WaveFillSmem<CL2>& S, const uint3
 // workgroup takes items on its own.
 template <int NT, int CL2, bool OALIGNED>
 __global__ __launch_bounds__(NT) void k_fill(const uint32_t* __restrict__ H, uint32_t* __restrict__ out,
-                                             const Ctl* ctl, const FillItem* __restrict__ items,
+                                             Ctl* ctl, const FillItem* __restrict__ items,
                                              uint32_t item_cap) {
   constexpr uint32_t NW = NT / WAVE;
   __shared__ WaveFillSmem<CL2> S[NW];
@@ -371,6 +377,12 @@ __global__ __launch_bounds__(NT) void k_fill(const uint32_t* __restrict__ H, uin
   const uint32_t nitems = (ctl->status & ST_INTERNAL) ? 0u : (ctl->nitems < item_cap ? ctl->nitems : item_cap);
   for (uint32_t it = blockIdx.x * NW + w; it < nitems; it += gridDim.x * NW) {
     const FillItem I = items[it];
+    // every producer cuts items well inside the 16-bit key offsets; anything
+    // else is a broken invariant, reported instead of written
+    if (I.klast < I.k || I.klast - I.k >= FILL_SPAN_MAX || I.p1 < I.p0 || I.p1 - (I.p0 & ~3ull) > (1ull << CL2)) {
+      if (lane_id() == 0) atomicOr(&ctl->status, ST_INT_ITEM);
+      continue;
+    }
     wave_fill_item<CL2, OALIGNED>(S[w], H, out, I);
   }
 }
