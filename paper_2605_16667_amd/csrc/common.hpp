@@ -63,13 +63,14 @@ __device__ __forceinline__ T wave_sum(T x) {
   return x;
 }
 
+// Maximum over the wave, in a scalar register (the same in every lane).
 __device__ __forceinline__ uint32_t wave_max(uint32_t x) {
 #pragma unroll
   for (int d = WAVE / 2; d >= 1; d >>= 1) {
     const uint32_t y = __shfl_xor(x, d, WAVE);
     x = y > x ? y : x;
   }
-  return x;
+  return __builtin_amdgcn_readfirstlane(x);
 }
 
 // Exclusive prefix sum over a block of NT threads.  smem needs NT/64 + 1
