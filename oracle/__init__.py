@@ -5,7 +5,10 @@ of ``bench.py`` may import this package.  The product (the HIP library and its
 Python binding) never does, and shares no code with it.
 
 ``dialsort_oracle.c`` states the method as the paper defines it: ingestion,
-Eq. (1) (Sec. 3.3), then the ordered projection, Eq. (2) (Sec. 3.3).  This
+Eq. (1) (Sec. 3.3), then the ordered projection, Eq. (2) (Sec. 3.3), and the
+queries that read H directly (frequency, presence and range-count, from the
+paragraph on the canonical ordered state in Sec. 3.3; prefix and select, the
+running count and the projection read at one position).  This
 module compiles that file with gcc (``build()``), loads it with ctypes and
 marshals numpy arrays.  ``crn.py`` holds the Conflict Resolution Network model of
 Sec. 6, used by tests only.
@@ -50,6 +53,15 @@ def _load() -> ctypes.CDLL:
         lib.oracle_reconstruct.restype = ctypes.c_int
         lib.oracle_sort.argtypes = [p, u64, u64, p, p]
         lib.oracle_sort.restype = ctypes.c_int
+        for name in ("oracle_frequency", "oracle_presence"):
+            getattr(lib, name).argtypes = [p, u64, p, u64, p]
+            getattr(lib, name).restype = None
+        lib.oracle_range_count.argtypes = [p, u64, p, p, u64, p]
+        lib.oracle_range_count.restype = None
+        lib.oracle_prefix.argtypes = [p, u64, p]
+        lib.oracle_prefix.restype = None
+        lib.oracle_select.argtypes = [p, u64, p, u64, p]
+        lib.oracle_select.restype = None
         _lib = lib
     return _lib
 
@@ -97,3 +109,50 @@ def sort(keys, U: int, in_place: bool = False) -> Tuple[int, np.ndarray, np.ndar
     out = k if in_place else np.empty_like(k)
     st = _load().oracle_sort(_ptr(k), k.size, U, H.ctypes.data_as(ctypes.c_void_p), _ptr(out))
     return st, H, out
+
+
+# ---- queries on H (Sec. 3.3, the paragraph on the canonical ordered state) ----
+
+
+def _u64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.uint64))
+
+
+def frequency(H, q) -> np.ndarray:
+    """H[k] for every query key k (0 outside [0, U))."""
+    h, qq = _as_u32(H), _as_u32(q)
+    out = np.zeros(max(qq.size, 1), dtype=np.uint32)
+    _load().oracle_frequency(_ptr(h), h.size, _ptr(qq), qq.size, _ptr(out))
+    return out[: qq.size]
+
+
+def presence(H, q) -> np.ndarray:
+    """1 where the query key occurs (H[k] > 0), else 0 (uint8)."""
+    h, qq = _as_u32(H), _as_u32(q)
+    out = np.zeros(max(qq.size, 1), dtype=np.uint8)
+    _load().oracle_presence(_ptr(h), h.size, _ptr(qq), qq.size, _ptr(out))
+    return out[: qq.size]
+
+
+def range_count(H, a, b) -> np.ndarray:
+    """Keys in [a, b) for every query, bounds cut at U (uint64)."""
+    h, aa, bb = _as_u32(H), _u64(a), _u64(b)
+    out = np.zeros(max(aa.size, 1), dtype=np.uint64)
+    _load().oracle_range_count(_ptr(h), h.size, _ptr(aa), _ptr(bb), aa.size, _ptr(out))
+    return out[: aa.size]
+
+
+def prefix(H) -> np.ndarray:
+    """P[k] = H[0] + ... + H[k-1], k = 0 .. U (uint64, U + 1 entries)."""
+    h = _as_u32(H)
+    P = np.zeros(h.size + 1, dtype=np.uint64)
+    _load().oracle_prefix(_ptr(h), h.size, _ptr(P))
+    return P
+
+
+def select(H, r) -> np.ndarray:
+    """The element at position r of the ordered projection (0xFFFFFFFF past the end)."""
+    h, rr = _as_u32(H), _u64(r)
+    out = np.zeros(max(rr.size, 1), dtype=np.uint32)
+    _load().oracle_select(_ptr(h), h.size, _ptr(rr), rr.size, _ptr(out))
+    return out[: rr.size]

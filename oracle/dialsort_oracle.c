@@ -83,3 +83,57 @@ int oracle_sort(const uint32_t *keys, uint64_t n, uint64_t U, uint32_t *H, uint3
     /* Theorem "thm:correct", item 3: the projection has exactly n elements. */
     return written == n ? ORACLE_OK : ORACLE_EOVERFLOW;
 }
+
+/* ---- Queries on H (Sec. 3.3, the paragraph on the canonical ordered state):
+ * answered from H alone, without the ordered projection. */
+
+/* frequency(k) = H[k]; a key outside [0, U) occurs 0 times. */
+void oracle_frequency(const uint32_t *H, uint64_t U, const uint32_t *q, uint64_t nq, uint32_t *out) {
+    uint64_t i;
+    for (i = 0; i < nq; ++i) out[i] = (uint64_t)q[i] < U ? H[q[i]] : 0;
+}
+
+/* presence(k) = 1 when k occurs in the input, i.e. H[k] > 0. */
+void oracle_presence(const uint32_t *H, uint64_t U, const uint32_t *q, uint64_t nq, uint8_t *out) {
+    uint64_t i;
+    for (i = 0; i < nq; ++i) out[i] = ((uint64_t)q[i] < U && H[q[i]] > 0) ? 1 : 0;
+}
+
+/* range-count(a, b): the keys in [a, b), summed bin by bin as the paper states
+ * it (O(b - a)); bounds past U are cut at U, and a >= b counts nothing. */
+void oracle_range_count(const uint32_t *H, uint64_t U, const uint64_t *a, const uint64_t *b, uint64_t nq,
+                        uint64_t *out) {
+    uint64_t i, k;
+    for (i = 0; i < nq; ++i) {
+        uint64_t lo = a[i] < U ? a[i] : U, hi = b[i] < U ? b[i] : U, s = 0;
+        for (k = lo; k < hi; ++k) s += H[k];
+        out[i] = s;
+    }
+}
+
+/* P[k] = H[0] + ... + H[k-1] for k = 0 .. U (U + 1 entries). */
+void oracle_prefix(const uint32_t *H, uint64_t U, uint64_t *P) {
+    uint64_t k, s = 0;
+    for (k = 0; k < U; ++k) {
+        P[k] = s;
+        s += H[k];
+    }
+    P[U] = s;
+}
+
+/* select(r): the element at position r of the ordered projection (Eq. (2)),
+ * found by walking the bins in ascending order; 0xFFFFFFFF when r >= sum H. */
+void oracle_select(const uint32_t *H, uint64_t U, const uint64_t *r, uint64_t nq, uint32_t *out) {
+    uint64_t i, k;
+    for (i = 0; i < nq; ++i) {
+        uint64_t acc = 0;
+        out[i] = 0xFFFFFFFFu;
+        for (k = 0; k < U; ++k) {
+            acc += H[k];
+            if (acc > r[i]) {
+                out[i] = (uint32_t)k;
+                break;
+            }
+        }
+    }
+}

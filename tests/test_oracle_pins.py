@@ -225,3 +225,51 @@ MUTANTS = {
 def test_pins_reject_planted_mistakes(name):
     h, p = MUTANTS[name]
     assert not pins_accept(h, p), name
+
+
+# ---- queries on H (Sec. 3.3, the paragraph on the canonical ordered state) ----
+# Each is pinned to the keys themselves (not to H): counting, membership and
+# order statistics of the input multiset computed by numpy.
+
+
+@pytest.mark.parametrize("U,n", [(1, 5), (7, 40), (300, 1000), (4096, 20000), (70000, 5000)])
+def test_queries_against_the_keys(U, n):
+    rng = np.random.default_rng(U * 31 + n)
+    keys = rng.integers(0, U, n).astype(np.uint32)
+    st, H = oracle.histogram(keys, U)
+    assert st == oracle.OK
+    q = np.concatenate([rng.integers(0, U + 3, 200), [0, U - 1, U, 0xFFFFFFFF]]).astype(np.uint32)
+    # frequency(k): how many keys equal k, by comparing every key with k
+    freq = np.array([np.count_nonzero(keys == x) for x in q], dtype=np.uint32)
+    assert np.array_equal(oracle.frequency(H, q), freq)
+    # presence(k): does k occur among the keys
+    assert np.array_equal(oracle.presence(H, q), np.isin(q, keys).astype(np.uint8))
+    # range-count(a, b): keys with a <= x < b, bounds beyond U included
+    a = rng.integers(0, U + 5, 100).astype(np.uint64)
+    b = rng.integers(0, U + 5, 100).astype(np.uint64)
+    a = np.concatenate([a, [0, 0, U, 2**33]]).astype(np.uint64)
+    b = np.concatenate([b, [U, 2**33, U, 2**34]]).astype(np.uint64)
+    k64 = keys.astype(np.uint64)
+    want = np.array([np.count_nonzero((k64 >= x) & (k64 < y)) for x, y in zip(a, b)], dtype=np.uint64)
+    assert np.array_equal(oracle.range_count(H, a, b), want)
+    # prefix: P[k] = number of keys below k
+    P = oracle.prefix(H)
+    assert P.size == U + 1 and P[0] == 0 and P[U] == n
+    ks = np.unique(np.concatenate([rng.integers(0, U + 1, 50), [0, U]]))
+    assert np.array_equal(P[ks], np.array([np.count_nonzero(k64 < x) for x in ks], dtype=np.uint64))
+    # select(r): the r-th smallest key (np.sort, a comparison sort), past the end 0xFFFFFFFF
+    r = np.concatenate([rng.integers(0, n, 100), [0, n - 1, n, n + 7]]).astype(np.uint64)
+    srt = np.sort(keys)
+    want_sel = np.array([srt[int(x)] if x < n else 0xFFFFFFFF for x in r], dtype=np.uint32)
+    assert np.array_equal(oracle.select(H, r), want_sel)
+
+
+def test_queries_on_the_worked_example():
+    # the abacus example's histogram (Fig. fig:abacus caption): H = [1,2,0,3,1,2]
+    H = np.array([1, 2, 0, 3, 1, 2], dtype=np.uint32)
+    assert list(oracle.frequency(H, [0, 1, 2, 3, 6])) == [1, 2, 0, 3, 0]
+    assert list(oracle.presence(H, [2, 3, 5, 6])) == [0, 1, 1, 0]
+    assert list(oracle.range_count(H, [0, 1, 3, 4], [6, 4, 4, 2])) == [9, 5, 3, 0]
+    assert list(oracle.prefix(H)) == [0, 1, 3, 3, 6, 7, 9]
+    # the projection <0,1,1,3,3,3,4,5,5>, read position by position
+    assert list(oracle.select(H, range(10))) == [0, 1, 1, 3, 3, 3, 4, 5, 5, 0xFFFFFFFF]
