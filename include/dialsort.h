@@ -304,6 +304,50 @@ const char *dialsort_strerror(dialsort_status status);
 /* The hipError_t of the most recent failed HIP call in this thread (0 if none). */
 int dialsort_last_hip_error(void);
 
+/* ---- Queries on H ------------------------------------------------------------
+ *
+ * H is the canonical ordered state (Sec. 3.3, the paragraph on the canonical
+ * ordered state): frequency(k), presence(k) and range-count(a, b) are answered
+ * from H without building the ordered projection.  range-count and select read
+ * the running count P[k] = H[0] + ... + H[k-1] (k = 0 .. U), built once by
+ * dialsort_prefix; select(r) is the element at position r of the projection
+ * (Eq. (2)) read without writing it.  H and P may have come from any source
+ * (dialsort_histogram, a batch, a served request, the caller).  Every query
+ * call enqueues one kernel on `stream` and returns; q, a, b, r and out are
+ * device arrays of nq entries owned by the caller.  nq == 0 enqueues nothing. */
+
+/* out[i] = H[q[i]] when q[i] < U, else 0 (a key outside the universe occurs 0
+ * times).  H: U uint32; q, out: nq uint32, 4-byte aligned. */
+dialsort_status dialsort_query_frequency(const uint32_t *H, uint64_t U, const uint32_t *q, uint64_t nq,
+                                         uint32_t *out, hipStream_t stream);
+
+/* out[i] = 1 when q[i] < U and H[q[i]] > 0, else 0 (the presence test of Sec.
+ * 2.6, on the ingested state).  out: nq bytes. */
+dialsort_status dialsort_query_presence(const uint32_t *H, uint64_t U, const uint32_t *q, uint64_t nq,
+                                        uint8_t *out, hipStream_t stream);
+
+/* Bytes of device workspace for dialsort_prefix (0 for U outside [1, 2^32]). */
+size_t dialsort_prefix_workspace_bytes(uint64_t U);
+
+/* P[k] = H[0] + ... + H[k-1] for k = 0 .. U: P has U + 1 uint64 entries,
+ * 8-byte aligned, not overlapping H; P[U] = sum H.  Sums saturate at
+ * 2^62 - 1 (never reached by a histogram of at most 2^32 - 1 keys).  One
+ * workspace serves one call at a time. */
+dialsort_status dialsort_prefix(const uint32_t *H, uint64_t U, uint64_t *P, void *ws, size_t ws_bytes,
+                                hipStream_t stream);
+
+/* out[i] = the number of keys in [a[i], b[i]) = P[min(b, U)] - P[min(a, b, U)]:
+ * bounds past U are cut at U and a >= b counts nothing.  P from
+ * dialsort_prefix; a, b, out: nq uint64, 8-byte aligned. */
+dialsort_status dialsort_query_range_count(const uint64_t *P, uint64_t U, const uint64_t *a, const uint64_t *b,
+                                           uint64_t nq, uint64_t *out, hipStream_t stream);
+
+/* out[i] = the element at position r[i] of the ordered projection (Eq. (2)):
+ * the k with P[k] <= r[i] < P[k + 1]; 0xFFFFFFFF when r[i] >= P[U].  P from
+ * dialsort_prefix; r: nq uint64 (8-byte aligned), out: nq uint32. */
+dialsort_status dialsort_query_select(const uint64_t *P, uint64_t U, const uint64_t *r, uint64_t nq,
+                                      uint32_t *out, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

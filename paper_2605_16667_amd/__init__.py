@@ -98,6 +98,12 @@ def _load() -> ctypes.CDLL:
         "dialsort_last_hip_error": (ctypes.c_int, []),
         "dialsort_set_launch_events": (st, [p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]),
         "dialsort_launch_name": (ctypes.c_char_p, [ctypes.c_uint32]),
+        "dialsort_query_frequency": (st, [p, u64, p, u64, p, p]),
+        "dialsort_query_presence": (st, [p, u64, p, u64, p, p]),
+        "dialsort_prefix_workspace_bytes": (sz, [u64]),
+        "dialsort_prefix": (st, [p, u64, p, p, sz, p]),
+        "dialsort_query_range_count": (st, [p, u64, p, p, u64, p, p]),
+        "dialsort_query_select": (st, [p, u64, p, u64, p, p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -113,7 +119,9 @@ EXPORTED = ("dialsort_workspace_bytes", "dialsort_histogram", "dialsort_reconstr
             "dialsort_server_create", "dialsort_server_destroy", "dialsort_server_submit", "dialsort_server_poll",
             "dialsort_server_drain", "dialsort_server_info", "dialsort_server_release", "dialsort_status_sync",
             "dialsort_result_total", "dialsort_strerror", "dialsort_last_hip_error",
-            "dialsort_set_launch_events", "dialsort_launch_name")
+            "dialsort_set_launch_events", "dialsort_launch_name", "dialsort_query_frequency",
+            "dialsort_query_presence", "dialsort_prefix_workspace_bytes", "dialsort_prefix",
+            "dialsort_query_range_count", "dialsort_query_select")
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -313,3 +321,41 @@ def dialsort_set_launch_events(events, cap: int, count) -> int:
 def dialsort_launch_name(i: int) -> Optional[str]:
     r = _lib.dialsort_launch_name(i)
     return r.decode() if r else None
+
+
+# ---- queries on H (frequency, presence, range-count, prefix, select) ----------
+
+
+def dialsort_query_frequency(H: torch.Tensor, U: int, q: torch.Tensor, out: torch.Tensor, stream=None) -> int:
+    if out.numel() < q.numel():
+        return DIALSORT_EINVAL
+    return _lib.dialsort_query_frequency(_ptr(H), U, _ptr(q), q.numel(), _ptr(out), _stream(stream))
+
+
+def dialsort_query_presence(H: torch.Tensor, U: int, q: torch.Tensor, out: torch.Tensor, stream=None) -> int:
+    if out.numel() < q.numel() or out.element_size() != 1:
+        return DIALSORT_EINVAL
+    return _lib.dialsort_query_presence(_ptr(H), U, _ptr(q), q.numel(), _ptr(out), _stream(stream))
+
+
+def dialsort_prefix_workspace_bytes(U: int) -> int:
+    return _lib.dialsort_prefix_workspace_bytes(U)
+
+
+def dialsort_prefix(H: torch.Tensor, U: int, P: torch.Tensor, ws: torch.Tensor, stream=None) -> int:
+    if P.numel() < U + 1 or P.element_size() != 8:
+        return DIALSORT_EINVAL
+    return _lib.dialsort_prefix(_ptr(H), U, _ptr(P), _ptr(ws), ws.numel(), _stream(stream))
+
+
+def dialsort_query_range_count(P: torch.Tensor, U: int, a: torch.Tensor, b: torch.Tensor, out: torch.Tensor,
+                               stream=None) -> int:
+    if b.numel() != a.numel() or out.numel() < a.numel():
+        return DIALSORT_EINVAL
+    return _lib.dialsort_query_range_count(_ptr(P), U, _ptr(a), _ptr(b), a.numel(), _ptr(out), _stream(stream))
+
+
+def dialsort_query_select(P: torch.Tensor, U: int, r: torch.Tensor, out: torch.Tensor, stream=None) -> int:
+    if out.numel() < r.numel():
+        return DIALSORT_EINVAL
+    return _lib.dialsort_query_select(_ptr(P), U, _ptr(r), r.numel(), _ptr(out), _stream(stream))
