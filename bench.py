@@ -16,6 +16,8 @@ fields of the same line:
            graph, against one launch sequence per array; per-array p50/p99
   serve    a Poisson request stream through the serving engine at several
            loads, against serial plain sorts; p50/p99 latency and keys/s
+  query    queries on the large workload's histogram: the running count over
+           2^24 bins, and 2^20 frequency/presence/range-count/select queries
 The roofline object is for the kernel that takes the most time per step,
 measured with HIP events recorded on the launch stream around every kernel of
 every timed step (dialsort_set_launch_events).  Its algorithmic bytes are the
@@ -517,6 +519,62 @@ def run_serve_workload(ds, hip, num, loads, batch_cfg, arena_gib=8):
     return res
 
 
+def run_query_workload(ds, keys, U, K, W, nq=1 << 20):
+    """Queries on the histogram of the large workload (Sec. 3.3, the canonical
+    ordered state): the running count P over U bins, then nq frequency,
+    presence, range-count and select queries with seeded random arguments."""
+    import torch
+
+    dev = keys.device
+    H = torch.empty(U, dtype=torch.int32, device=dev)
+    ws = ds.workspace(ds.dialsort_workspace_bytes(keys.numel(), U, ds.DIALSORT_MODE_HISTOGRAM), dev)
+    ds.check(ds.dialsort_histogram(keys, U, H, ws))
+    P = torch.empty(U + 1, dtype=torch.int64, device=dev)
+    pws = ds.workspace(ds.dialsort_prefix_workspace_bytes(U), dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(20260321 + 40)
+    q = torch.randint(0, U, (nq,), generator=g, device=dev, dtype=torch.int32)
+    a = torch.randint(0, U, (nq,), generator=g, device=dev, dtype=torch.int64)
+    b = torch.clamp(a + torch.randint(0, 1 << 16, (nq,), generator=g, device=dev, dtype=torch.int64), max=U)
+    r = torch.randint(0, keys.numel(), (nq,), generator=g, device=dev, dtype=torch.int64)
+    o32 = torch.empty(nq, dtype=torch.int32, device=dev)
+    o8 = torch.empty(nq, dtype=torch.uint8, device=dev)
+    o64 = torch.empty(nq, dtype=torch.int64, device=dev)
+    calls = {
+        "prefix": lambda: ds.check(ds.dialsort_prefix(H, U, P, pws)),
+        "frequency": lambda: ds.check(ds.dialsort_query_frequency(H, U, q, o32)),
+        "presence": lambda: ds.check(ds.dialsort_query_presence(H, U, q, o8)),
+        "range_count": lambda: ds.check(ds.dialsort_query_range_count(P, U, a, b, o64)),
+        "select": lambda: ds.check(ds.dialsort_query_select(P, U, r, o32)),
+    }
+    res = {"U": U, "n": keys.numel(), "queries_per_call": nq}
+    for name, call in calls.items():
+        for _ in range(W):
+            call()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0.record()
+        for _ in range(K):
+            call()
+        t1.record()
+        torch.cuda.synchronize()
+        us = t0.elapsed_time(t1) / K * 1e3
+        entry = {"us": us}
+        if name == "prefix":
+            entry["GBps"] = (4 * U + 8 * (U + 1)) / (us * 1e-6) / 1e9  # H read once, P written once
+        else:
+            entry["queries_per_s"] = nq / (us * 1e-6)
+        res[name] = entry
+    # a spot check against the keys (sorted with torch on the device)
+    srt = torch.sort(keys.to(torch.int64) & 0xFFFFFFFF).values
+    ok = bool(torch.equal(o32[:4096].to(torch.int64) & 0xFFFFFFFF, srt[r[:4096]]))
+    res["verified_select_sample"] = ok
+    del H, P, pws, q, a, b, r, o32, o8, o64, srt, ws
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(keys_dev, U, budget_s=12.0, max_runs=5):
     """The oracle as it stands, on this host, on the same keys (sequential C)."""
     import oracle
@@ -542,7 +600,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workloads", default="large,hist,plain,skewed,batch,serve")
+    ap.add_argument("--workloads", default="large,hist,query,plain,skewed,batch,serve")
     ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--serve-loads", default="0.7,1.5,3.0",
                     help="arrival rates, as multiples of 1 / (mean serial service time)")
@@ -591,6 +649,9 @@ def main():
         r["path_roofline"] = with_copy_ceiling(r["path_roofline"], copy_bps)
         extra["histogram_only"] = {k: r[k] for k in ("ms_per_step", "best_ms", "median_ms", "cv", "keys_per_s",
                                                      "path_roofline", "roofline", "verified", "kernels")}
+    if "query" in todo:
+        log("queries on the large workload's histogram")
+        extra["queries"] = run_query_workload(ds, keys, U, max(K // 2, 5), 2)
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle)")

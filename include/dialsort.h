@@ -54,6 +54,7 @@ typedef enum {
 #define DIALSORT_MODE_HISTOGRAM 0  /* dialsort_histogram */
 #define DIALSORT_MODE_SORT 1       /* dialsort_sort */
 #define DIALSORT_MODE_RECONSTRUCT 2 /* dialsort_reconstruct: pass n = out_cap */
+#define DIALSORT_MODE_ACCUMULATE 3  /* dialsort_histogram_accumulate */
 
 /* One array of a batch: the same meaning as the arguments of dialsort_sort.
  * out may equal keys (in place); any other overlap is EINVAL. */
@@ -73,6 +74,20 @@ size_t dialsort_workspace_bytes(uint64_t n, uint64_t U, int mode);
  * it.  n == 0 gives H == 0.  n > 2^32 - 1 is EOVERFLOW. */
 dialsort_status dialsort_histogram(const uint32_t *keys, uint64_t n, uint64_t U, uint32_t *H,
                                    void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Accumulating ingestion, for keys that arrive in pieces (streaming): H[k] +=
+ * |{ i : keys[i] == k }| for every k in [0, U), so that ingesting a key stream
+ * piece by piece leaves in H the histogram of the whole stream (Eq. (1) is a
+ * sum over the keys, and the CRN merge is additive: Sec. 6, Lemma "lem:crn").
+ * The paper notes that streaming can overlap ingestion and projection given
+ * extra synchronisation (Sec. 4, remark after the complexity theorem); here
+ * pieces are ordered on `stream`, and dialsort_reconstruct projects H once
+ * the stream ends.  A bin that would pass 2^32 - 1 is reported as EOVERFLOW
+ * by dialsort_status_sync() (H is then unspecified), and so is a key >= U as
+ * ERANGE.  The workspace size is dialsort_workspace_bytes(n, U,
+ * DIALSORT_MODE_ACCUMULATE). */
+dialsort_status dialsort_histogram_accumulate(const uint32_t *keys, uint64_t n, uint64_t U, uint32_t *H,
+                                              void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Ordered projection only (Sec. 3.3, Eq. (2)): writes k exactly H[k] times for
  * k = 0 .. U-1 into out, in ascending k, stopping after out_cap elements.  The

@@ -53,6 +53,8 @@ def _load() -> ctypes.CDLL:
         lib.oracle_reconstruct.restype = ctypes.c_int
         lib.oracle_sort.argtypes = [p, u64, u64, p, p]
         lib.oracle_sort.restype = ctypes.c_int
+        lib.oracle_histogram_accumulate.argtypes = [p, u64, u64, p]
+        lib.oracle_histogram_accumulate.restype = ctypes.c_int
         for name in ("oracle_frequency", "oracle_presence"):
             getattr(lib, name).argtypes = [p, u64, p, u64, p]
             getattr(lib, name).restype = None
@@ -85,6 +87,15 @@ def histogram(keys, U: int) -> Tuple[int, np.ndarray]:
     H = np.zeros(U, dtype=np.uint32)
     st = _load().oracle_histogram(_ptr(k), k.size, U, H.ctypes.data_as(ctypes.c_void_p))
     return st, H
+
+
+def histogram_accumulate(keys, U: int, H) -> Tuple[int, np.ndarray]:
+    """Eq. (1) over one more piece of a key stream: returns (status, H + counts)."""
+    k = _as_u32(keys)
+    h = _as_u32(H).copy()
+    assert h.size == U
+    st = _load().oracle_histogram_accumulate(_ptr(k), k.size, U, h.ctypes.data_as(ctypes.c_void_p))
+    return st, h
 
 
 def reconstruct(H, out_cap: Optional[int] = None) -> Tuple[int, np.ndarray]:

@@ -137,3 +137,18 @@ void oracle_select(const uint32_t *H, uint64_t U, const uint64_t *r, uint64_t nq
         }
     }
 }
+
+/* Eq. (1) over one more piece of a key stream: H[x] := H[x] + 1 for every key
+ * x of the piece, H not cleared.  A count passing 2^32 - 1 is EOVERFLOW. */
+int oracle_histogram_accumulate(const uint32_t *keys, uint64_t n, uint64_t U, uint32_t *H) {
+    uint64_t i;
+    if (U == 0 || U > ((uint64_t)1 << 32) || H == NULL) return ORACLE_EINVAL;
+    if (n > 0 && keys == NULL) return ORACLE_EINVAL;
+    for (i = 0; i < n; ++i) {
+        uint64_t x = keys[i];
+        if (x >= U) return ORACLE_ERANGE;
+        if (H[x] == 0xFFFFFFFFu) return ORACLE_EOVERFLOW;
+        H[x] = H[x] + 1;
+    }
+    return ORACLE_OK;
+}

@@ -20,7 +20,7 @@ from typing import Optional, Sequence, Tuple
 import torch
 
 DIALSORT_OK, DIALSORT_EINVAL, DIALSORT_ERANGE, DIALSORT_EOVERFLOW, DIALSORT_EWORKSPACE, DIALSORT_EHIP = range(6)
-DIALSORT_MODE_HISTOGRAM, DIALSORT_MODE_SORT, DIALSORT_MODE_RECONSTRUCT = 0, 1, 2
+DIALSORT_MODE_HISTOGRAM, DIALSORT_MODE_SORT, DIALSORT_MODE_RECONSTRUCT, DIALSORT_MODE_ACCUMULATE = 0, 1, 2, 3
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdialsort.so")
@@ -68,6 +68,7 @@ def _load() -> ctypes.CDLL:
     sig = {
         "dialsort_workspace_bytes": (sz, [u64, u64, ctypes.c_int]),
         "dialsort_histogram": (st, [p, u64, u64, p, p, sz, p]),
+        "dialsort_histogram_accumulate": (st, [p, u64, u64, p, p, sz, p]),
         "dialsort_reconstruct": (st, [p, u64, p, u64, p, sz, p]),
         "dialsort_sort": (st, [p, u64, u64, p, p, p, sz, p]),
         "dialsort_batched_workspace_bytes": (sz, [ctypes.POINTER(dialsort_desc), ctypes.c_uint32]),
@@ -112,7 +113,8 @@ def _load() -> ctypes.CDLL:
 
 
 _lib = _load()
-EXPORTED = ("dialsort_workspace_bytes", "dialsort_histogram", "dialsort_reconstruct", "dialsort_sort",
+EXPORTED = ("dialsort_workspace_bytes", "dialsort_histogram", "dialsort_histogram_accumulate",
+            "dialsort_reconstruct", "dialsort_sort",
             "dialsort_batched_workspace_bytes", "dialsort_sort_batched", "dialsort_sort_each",
             "dialsort_batch_prepare", "dialsort_batch_launch", "dialsort_batch_autotune",
             "dialsort_batch_default_config", "dialsort_batch_times", "dialsort_server_footprint",
@@ -164,6 +166,12 @@ def workspace(nbytes: int, device="cuda") -> torch.Tensor:
 
 def dialsort_histogram(keys: torch.Tensor, U: int, H: torch.Tensor, ws: torch.Tensor, stream=None) -> int:
     return _lib.dialsort_histogram(_ptr(keys), keys.numel(), U, _ptr(H), _ptr(ws), ws.numel(), _stream(stream))
+
+
+def dialsort_histogram_accumulate(keys: torch.Tensor, U: int, H: torch.Tensor, ws: torch.Tensor,
+                                  stream=None) -> int:
+    return _lib.dialsort_histogram_accumulate(_ptr(keys), keys.numel(), U, _ptr(H), _ptr(ws), ws.numel(),
+                                              _stream(stream))
 
 
 def dialsort_sort(keys: torch.Tensor, U: int, H: torch.Tensor, out: torch.Tensor, ws: torch.Tensor,

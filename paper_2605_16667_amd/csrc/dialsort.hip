@@ -265,6 +265,22 @@ dialsort_status launch_fill(const uint32_t* H, uint32_t* out, char* base, const 
   return DIALSORT_OK;
 }
 
+// Accumulating ingestion: the keys' histogram goes to a scratch row T of the
+// workspace (after the ingestion's own workspace), then k_accumulate adds T
+// into H, reporting a bin that passes 2^32 - 1 as ST_OVERFLOW.
+size_t accumulate_ws_off(uint64_t n, uint64_t U) { return align_up(plan(n, U, DIALSORT_MODE_HISTOGRAM).bytes, ALIGN); }
+size_t accumulate_ws_bytes(uint64_t n, uint64_t U) { return accumulate_ws_off(n, U) + align_up(U * 4, ALIGN) + ALIGN; }
+
+__global__ void k_accumulate(uint32_t* __restrict__ H, const uint32_t* __restrict__ T, uint64_t U, Ctl* ctl) {
+  bool wrapped = false;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < U; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t a = H[i], s = a + T[i];
+    wrapped |= s < a;
+    H[i] = s;
+  }
+  if (__any(wrapped) && lane_id() == 0) set_status(ctl, ST_OVERFLOW);
+}
+
 dialsort_status check_common(uint64_t U, const void* ws, size_t ws_bytes, size_t need) {
   if (U == 0 || U > U_MAX) return DIALSORT_EINVAL;
   if (!ws || ws_bytes < need) return DIALSORT_EWORKSPACE;
@@ -340,6 +356,7 @@ extern "C" {
 
 size_t dialsort_workspace_bytes(uint64_t n, uint64_t U, int mode) {
   if (U == 0 || U > U_MAX) return 0;
+  if (mode == DIALSORT_MODE_ACCUMULATE) return accumulate_ws_bytes(n, U);
   return plan(n, U, mode).bytes;
 }
 
@@ -352,6 +369,22 @@ dialsort_status dialsort_histogram(const uint32_t* keys, uint64_t n, uint64_t U,
   DS_TRY(check_common(U, ws, ws_bytes, dialsort_workspace_bytes(n, U, DIALSORT_MODE_HISTOGRAM)));
   CallScope scope(stream);
   return run_sort(keys, n, U, H, nullptr, ws, DIALSORT_MODE_HISTOGRAM, stream);
+}
+
+dialsort_status dialsort_histogram_accumulate(const uint32_t* keys, uint64_t n, uint64_t U, uint32_t* H, void* ws,
+                                              size_t ws_bytes, hipStream_t stream) {
+  if (U == 0 || U > U_MAX || !H || (n && !keys)) return DIALSORT_EINVAL;
+  if (!aligned4(keys) || !aligned4(H)) return DIALSORT_EINVAL;
+  if (n > N_MAX) return DIALSORT_EOVERFLOW;
+  if (overlap(keys, n * 4, H, U * 4)) return DIALSORT_EINVAL;
+  DS_TRY(check_common(U, ws, ws_bytes, accumulate_ws_bytes(n, U)));
+  CallScope scope(stream);
+  char* base = ws_base(ws);
+  uint32_t* T = (uint32_t*)(base + accumulate_ws_off(n, U));
+  DS_TRY(run_sort(keys, n, U, T, nullptr, ws, DIALSORT_MODE_HISTOGRAM, stream));
+  const uint32_t grid = (uint32_t)std::min<uint64_t>(cdiv(U, 256), 256 * 8);
+  DS_LAUNCH(k_accumulate, dim3(grid), dim3(256), stream, H, T, U, (Ctl*)base);
+  return DIALSORT_OK;
 }
 
 dialsort_status dialsort_sort(const uint32_t* keys, uint64_t n, uint64_t U, uint32_t* H, uint32_t* out, void* ws,

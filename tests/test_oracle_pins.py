@@ -273,3 +273,25 @@ def test_queries_on_the_worked_example():
     assert list(oracle.prefix(H)) == [0, 1, 3, 3, 6, 7, 9]
     # the projection <0,1,1,3,3,3,4,5,5>, read position by position
     assert list(oracle.select(H, range(10))) == [0, 1, 1, 3, 3, 3, 4, 5, 5, 0xFFFFFFFF]
+
+
+def test_accumulate_is_ingestion_of_the_whole_stream():
+    """Ingesting a stream piece by piece gives the histogram of the whole stream
+    (numpy's bincount of the concatenation); a count past 2^32 - 1 overflows."""
+    rng = np.random.default_rng(77)
+    U = 5000
+    pieces = [rng.integers(0, U, m).astype(np.uint32) for m in (0, 1, 999, 4096, 17, 20000)]
+    H = np.zeros(U, dtype=np.uint32)
+    for p in pieces:
+        st, H = oracle.histogram_accumulate(p, U, H)
+        assert st == oracle.OK
+    whole = np.concatenate(pieces)
+    assert np.array_equal(H, np.bincount(whole, minlength=U).astype(np.uint32))
+    st, H2 = oracle.histogram_accumulate(np.array([U], dtype=np.uint32), U, H)
+    assert st == oracle.ERANGE
+    near = np.zeros(4, dtype=np.uint32)
+    near[2] = 0xFFFFFFFE
+    st, near = oracle.histogram_accumulate(np.array([2], dtype=np.uint32), 4, near)
+    assert st == oracle.OK and near[2] == 0xFFFFFFFF
+    st, _ = oracle.histogram_accumulate(np.array([2], dtype=np.uint32), 4, near)
+    assert st == oracle.EOVERFLOW
