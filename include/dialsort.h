@@ -75,6 +75,21 @@ size_t dialsort_workspace_bytes(uint64_t n, uint64_t U, int mode);
 dialsort_status dialsort_histogram(const uint32_t *keys, uint64_t n, uint64_t U, uint32_t *H,
                                    void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* Keys from a universe that starts at lo: the order-isomorphism phi(x) =
+ * x - lo (mod 2^32) of the General Self-Indexing Principle (Sec. 3.4,
+ * Proposition "General Self-Indexing Principle") maps [lo, lo + U) onto
+ * [0, U) in order, and its inverse lo + k is applied as the projection writes.
+ * H[k] counts the key lo + k; out receives the keys themselves in phi order.
+ * lo = 0 is dialsort_histogram / dialsort_sort.  Signed int32 keys are the
+ * case lo = 0x80000000 (phi flips the sign bit) with U = 2^32, or lo = the
+ * smallest value's bit pattern for a narrower signed range.  A key outside
+ * [lo, lo + U) (mod 2^32) is ERANGE.  Workspace sizes and every other
+ * convention are those of dialsort_histogram / dialsort_sort. */
+dialsort_status dialsort_histogram_offset(const uint32_t *keys, uint64_t n, uint32_t lo, uint64_t U, uint32_t *H,
+                                          void *ws, size_t ws_bytes, hipStream_t stream);
+dialsort_status dialsort_sort_offset(const uint32_t *keys, uint64_t n, uint32_t lo, uint64_t U, uint32_t *H,
+                                     uint32_t *out, void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* Accumulating ingestion, for keys that arrive in pieces (streaming): H[k] +=
  * |{ i : keys[i] == k }| for every k in [0, U), so that ingesting a key stream
  * piece by piece leaves in H the histogram of the whole stream (Eq. (1) is a

@@ -6,6 +6,7 @@ Python binding) never does, and shares no code with it.
 
 ``dialsort_oracle.c`` states the method as the paper defines it: ingestion,
 Eq. (1) (Sec. 3.3), then the ordered projection, Eq. (2) (Sec. 3.3), and the
+sort over a universe that starts anywhere (phi of Sec. 3.4), and the
 queries that read H directly (frequency, presence and range-count, from the
 paragraph on the canonical ordered state in Sec. 3.3; prefix and select, the
 running count and the projection read at one position).  This
@@ -55,6 +56,8 @@ def _load() -> ctypes.CDLL:
         lib.oracle_sort.restype = ctypes.c_int
         lib.oracle_histogram_accumulate.argtypes = [p, u64, u64, p]
         lib.oracle_histogram_accumulate.restype = ctypes.c_int
+        lib.oracle_sort_offset.argtypes = [p, u64, ctypes.c_uint32, u64, p, p]
+        lib.oracle_sort_offset.restype = ctypes.c_int
         for name in ("oracle_frequency", "oracle_presence"):
             getattr(lib, name).argtypes = [p, u64, p, u64, p]
             getattr(lib, name).restype = None
@@ -96,6 +99,16 @@ def histogram_accumulate(keys, U: int, H) -> Tuple[int, np.ndarray]:
     assert h.size == U
     st = _load().oracle_histogram_accumulate(_ptr(k), k.size, U, h.ctypes.data_as(ctypes.c_void_p))
     return st, h
+
+
+def sort_offset(keys, lo: int, U: int) -> Tuple[int, np.ndarray, np.ndarray]:
+    """Sec. 3.4 with phi(x) = x - lo (mod 2^32): returns (status, H, out)."""
+    k = _as_u32(keys)
+    H = np.zeros(U, dtype=np.uint32)
+    out = np.empty_like(k)
+    st = _load().oracle_sort_offset(_ptr(k), k.size, lo & 0xFFFFFFFF, U, H.ctypes.data_as(ctypes.c_void_p),
+                                    _ptr(out))
+    return st, H, out
 
 
 def reconstruct(H, out_cap: Optional[int] = None) -> Tuple[int, np.ndarray]:

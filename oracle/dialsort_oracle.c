@@ -152,3 +152,22 @@ int oracle_histogram_accumulate(const uint32_t *keys, uint64_t n, uint64_t U, ui
     }
     return ORACLE_OK;
 }
+
+/* The General Self-Indexing Principle (Sec. 3.4) with phi(x) = x - lo (mod
+ * 2^32), an order-isomorphism from [lo, lo + U) onto [0, U): Eq. (1) over
+ * phi(x), then Eq. (2) emitting phi^-1(k) = lo + k, H[k] times. */
+int oracle_sort_offset(const uint32_t *keys, uint64_t n, uint32_t lo, uint64_t U, uint32_t *H, uint32_t *out) {
+    uint64_t i, k, r, pos = 0;
+    if (U == 0 || U > ((uint64_t)1 << 32) || H == NULL) return ORACLE_EINVAL;
+    if (n > 0 && (keys == NULL || out == NULL)) return ORACLE_EINVAL;
+    if (n > (uint64_t)0xFFFFFFFFu) return ORACLE_EOVERFLOW;
+    for (k = 0; k < U; ++k) H[k] = 0;
+    for (i = 0; i < n; ++i) {
+        uint64_t x = (uint32_t)(keys[i] - lo);
+        if (x >= U) return ORACLE_ERANGE;
+        H[x] = H[x] + 1;
+    }
+    for (k = 0; k < U; ++k)
+        for (r = 0; r < H[k]; ++r) out[pos++] = (uint32_t)(lo + k);
+    return pos == n ? ORACLE_OK : ORACLE_EOVERFLOW;
+}

@@ -69,6 +69,8 @@ def _load() -> ctypes.CDLL:
         "dialsort_workspace_bytes": (sz, [u64, u64, ctypes.c_int]),
         "dialsort_histogram": (st, [p, u64, u64, p, p, sz, p]),
         "dialsort_histogram_accumulate": (st, [p, u64, u64, p, p, sz, p]),
+        "dialsort_histogram_offset": (st, [p, u64, ctypes.c_uint32, u64, p, p, sz, p]),
+        "dialsort_sort_offset": (st, [p, u64, ctypes.c_uint32, u64, p, p, p, sz, p]),
         "dialsort_reconstruct": (st, [p, u64, p, u64, p, sz, p]),
         "dialsort_sort": (st, [p, u64, u64, p, p, p, sz, p]),
         "dialsort_batched_workspace_bytes": (sz, [ctypes.POINTER(dialsort_desc), ctypes.c_uint32]),
@@ -114,6 +116,7 @@ def _load() -> ctypes.CDLL:
 
 _lib = _load()
 EXPORTED = ("dialsort_workspace_bytes", "dialsort_histogram", "dialsort_histogram_accumulate",
+            "dialsort_histogram_offset", "dialsort_sort_offset",
             "dialsort_reconstruct", "dialsort_sort",
             "dialsort_batched_workspace_bytes", "dialsort_sort_batched", "dialsort_sort_each",
             "dialsort_batch_prepare", "dialsort_batch_launch", "dialsort_batch_autotune",
@@ -172,6 +175,21 @@ def dialsort_histogram_accumulate(keys: torch.Tensor, U: int, H: torch.Tensor, w
                                   stream=None) -> int:
     return _lib.dialsort_histogram_accumulate(_ptr(keys), keys.numel(), U, _ptr(H), _ptr(ws), ws.numel(),
                                               _stream(stream))
+
+
+def dialsort_histogram_offset(keys: torch.Tensor, lo: int, U: int, H: torch.Tensor, ws: torch.Tensor,
+                              stream=None) -> int:
+    return _lib.dialsort_histogram_offset(_ptr(keys), keys.numel(), lo & 0xFFFFFFFF, U, _ptr(H), _ptr(ws),
+                                          ws.numel(), _stream(stream))
+
+
+def dialsort_sort_offset(keys: torch.Tensor, lo: int, U: int, H: torch.Tensor, out: torch.Tensor,
+                         ws: torch.Tensor, stream=None) -> int:
+    """Keys in [lo, lo + U) (mod 2^32); lo may be given as a signed int32."""
+    if out.numel() < keys.numel():
+        return DIALSORT_EINVAL
+    return _lib.dialsort_sort_offset(_ptr(keys), keys.numel(), lo & 0xFFFFFFFF, U, _ptr(H), _ptr(out), _ptr(ws),
+                                     ws.numel(), _stream(stream))
 
 
 def dialsort_sort(keys: torch.Tensor, U: int, H: torch.Tensor, out: torch.Tensor, ws: torch.Tensor,

@@ -166,7 +166,7 @@ dialsort_status launch_init(char* base, const Layout& L, uint32_t* H, uint64_t n
 }
 
 // Ingestion: H (or partial rows) from keys.
-dialsort_status launch_ingest(const uint32_t* keys, uint64_t n, uint64_t U, uint32_t* H, char* base,
+dialsort_status launch_ingest(const uint32_t* keys, uint64_t n, uint64_t U, uint32_t lo, uint32_t* H, char* base,
                               const Layout& L, hipStream_t s) {
   Ctl* ctl = (Ctl*)base;
   const uint32_t umax = (uint32_t)(U - 1);
@@ -174,16 +174,16 @@ dialsort_status launch_ingest(const uint32_t* keys, uint64_t n, uint64_t U, uint
   uint32_t* rows = L.rows_in_ws ? (uint32_t*)(base + L.off_rows) : H;
   switch (L.kind) {
     case K_LDS32S:
-      if (ka) DS_LAUNCH((k_hist_lds<1024, 4096, false, 3, true, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
-      else DS_LAUNCH((k_hist_lds<1024, 4096, false, 3, false, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
+      if (ka) DS_LAUNCH((k_hist_lds<1024, 4096, false, 3, true, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo);
+      else DS_LAUNCH((k_hist_lds<1024, 4096, false, 3, false, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo);
       break;
     case K_LDS32:
-      if (ka) DS_LAUNCH((k_hist_lds<1024, 32768, false, 3, true, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
-      else DS_LAUNCH((k_hist_lds<1024, 32768, false, 3, false, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
+      if (ka) DS_LAUNCH((k_hist_lds<1024, 32768, false, 3, true, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo);
+      else DS_LAUNCH((k_hist_lds<1024, 32768, false, 3, false, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo);
       break;
     case K_LDS16:
-      if (ka) DS_LAUNCH((k_hist_lds<1024, 32768, true, 3, true, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
-      else DS_LAUNCH((k_hist_lds<1024, 32768, true, 3, false, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl);
+      if (ka) DS_LAUNCH((k_hist_lds<1024, 32768, true, 3, true, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo);
+      else DS_LAUNCH((k_hist_lds<1024, 32768, true, 3, false, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo);
       break;
     case K_PART: {
       uint16_t* stg = (uint16_t*)(base + L.off_stage);
@@ -196,11 +196,11 @@ dialsort_status launch_ingest(const uint32_t* keys, uint64_t n, uint64_t U, uint
       plan.chunk = L.chunk;
       plan.X = L.X;
       if (L.B <= 1024) {
-        if (ka) DS_LAUNCH((k_partition<1024, 3, true>), dim3(L.T), dim3(P1_NT), s, keys, n, umax, L.B, stg, seg, L.bstride, ctl, plan);
-        else DS_LAUNCH((k_partition<1024, 3, false>), dim3(L.T), dim3(P1_NT), s, keys, n, umax, L.B, stg, seg, L.bstride, ctl, plan);
+        if (ka) DS_LAUNCH((k_partition<1024, 3, true>), dim3(L.T), dim3(P1_NT), s, keys, n, umax, L.B, stg, seg, L.bstride, ctl, plan, lo);
+        else DS_LAUNCH((k_partition<1024, 3, false>), dim3(L.T), dim3(P1_NT), s, keys, n, umax, L.B, stg, seg, L.bstride, ctl, plan, lo);
       } else {
-        if (ka) DS_LAUNCH((k_partition<PART_BMAX, 3, true>), dim3(L.T), dim3(P1_NT), s, keys, n, umax, L.B, stg, seg, L.bstride, ctl, plan);
-        else DS_LAUNCH((k_partition<PART_BMAX, 3, false>), dim3(L.T), dim3(P1_NT), s, keys, n, umax, L.B, stg, seg, L.bstride, ctl, plan);
+        if (ka) DS_LAUNCH((k_partition<PART_BMAX, 3, true>), dim3(L.T), dim3(P1_NT), s, keys, n, umax, L.B, stg, seg, L.bstride, ctl, plan, lo);
+        else DS_LAUNCH((k_partition<PART_BMAX, 3, false>), dim3(L.T), dim3(P1_NT), s, keys, n, umax, L.B, stg, seg, L.bstride, ctl, plan, lo);
       }
       FillItem* items = (FillItem*)(base + L.off_items);
       const uint32_t icap = (uint32_t)std::min<uint64_t>(L.item_cap, 0xFFFFFFF0ull);
@@ -218,8 +218,8 @@ dialsort_status launch_ingest(const uint32_t* keys, uint64_t n, uint64_t U, uint
     }
     case K_GLOBAL: {
       const uint32_t grid = (uint32_t)std::min<uint64_t>(cdiv(n, 256 * 4), 4096);
-      if (ka) DS_LAUNCH((k_hist_global<256, 3, true>), dim3(grid), dim3(256), s, keys, n, umax, H, ctl);
-      else DS_LAUNCH((k_hist_global<256, 3, false>), dim3(grid), dim3(256), s, keys, n, umax, H, ctl);
+      if (ka) DS_LAUNCH((k_hist_global<256, 3, true>), dim3(grid), dim3(256), s, keys, n, umax, H, ctl, lo);
+      else DS_LAUNCH((k_hist_global<256, 3, false>), dim3(grid), dim3(256), s, keys, n, umax, H, ctl, lo);
       break;
     }
     default:
@@ -251,7 +251,8 @@ dialsort_status launch_scan(const uint32_t* rows, uint32_t nrows, uint64_t row_s
   return DIALSORT_OK;
 }
 
-dialsort_status launch_fill(const uint32_t* H, uint32_t* out, char* base, const Layout& L, hipStream_t s) {
+dialsort_status launch_fill(const uint32_t* H, uint32_t* out, uint32_t lo, char* base, const Layout& L,
+                            hipStream_t s) {
   Ctl* ctl = (Ctl*)base;
   const FillItem* items = (const FillItem*)(base + L.off_items);
   if (L.limit == 0) return DIALSORT_OK;
@@ -259,9 +260,9 @@ dialsort_status launch_fill(const uint32_t* H, uint32_t* out, char* base, const 
   const uint32_t grid = (uint32_t)std::min<uint64_t>(cdiv(L.item_cap, FILL_NT / WAVE), 256 * 7);
   const uint32_t icap = (uint32_t)std::min<uint64_t>(L.item_cap, 0xFFFFFFF0ull);
   if (aligned16(out))
-    DS_LAUNCH((k_fill<FILL_NT, FILL_CL2, true>), dim3(grid), dim3(FILL_NT), s, H, out, ctl, items, icap);
+    DS_LAUNCH((k_fill<FILL_NT, FILL_CL2, true>), dim3(grid), dim3(FILL_NT), s, H, out, ctl, items, icap, lo);
   else
-    DS_LAUNCH((k_fill<FILL_NT, FILL_CL2, false>), dim3(grid), dim3(FILL_NT), s, H, out, ctl, items, icap);
+    DS_LAUNCH((k_fill<FILL_NT, FILL_CL2, false>), dim3(grid), dim3(FILL_NT), s, H, out, ctl, items, icap, lo);
   return DIALSORT_OK;
 }
 
@@ -288,13 +289,13 @@ dialsort_status check_common(uint64_t U, const void* ws, size_t ws_bytes, size_t
 }
 
 // histogram or sort, after argument checks
-dialsort_status run_sort(const uint32_t* keys, uint64_t n, uint64_t U, uint32_t* H, uint32_t* out, void* ws,
+dialsort_status run_sort(const uint32_t* keys, uint64_t n, uint64_t U, uint32_t lo, uint32_t* H, uint32_t* out, void* ws,
                          int mode, hipStream_t s) {
   const Layout L = plan(n, U, mode);
   char* base = ws_base(ws);
   const bool zeroH = L.kind == K_EMPTY || L.kind == K_GLOBAL;
   DS_TRY(launch_init(base, L, H, zeroH ? U : 0, s));
-  DS_TRY(launch_ingest(keys, n, U, H, base, L, s));
+  DS_TRY(launch_ingest(keys, n, U, lo, H, base, L, s));
   const uint32_t* rows = L.rows_in_ws ? (const uint32_t*)(base + L.off_rows) : H;
   const uint32_t nrows = L.rows_in_ws ? L.G : 1;
   if (mode == DIALSORT_MODE_HISTOGRAM) {
@@ -304,7 +305,7 @@ dialsort_status run_sort(const uint32_t* keys, uint64_t n, uint64_t U, uint32_t*
   if (L.kind != K_PART)
     DS_TRY(launch_scan(rows, nrows, L.rows_in_ws ? L.row_stride : 0, L.rows_in_ws ? H : nullptr, U, base, L,
                        true, 0, s));
-  DS_TRY(launch_fill(H, out, base, L, s));
+  DS_TRY(launch_fill(H, out, lo, base, L, s));
   return DIALSORT_OK;
 }
 
@@ -344,7 +345,7 @@ dialsort_status loop_run(const dialsort_desc* d, uint32_t count, void* ws, size_
   DS_TRY(launch_init(base, L0, nullptr, 0, s));
   char* sub = base + ALIGN;
   for (uint32_t i = 0; i < count; ++i) {
-    DS_TRY(run_sort(d[i].keys, d[i].n, d[i].U, d[i].H, d[i].out, sub, DIALSORT_MODE_SORT, s));
+    DS_TRY(run_sort(d[i].keys, d[i].n, d[i].U, 0, d[i].H, d[i].out, sub, DIALSORT_MODE_SORT, s));
     DS_LAUNCH(k_or_status, dim3(1), dim3(64), s, (Ctl*)base, (const Ctl*)sub);
   }
   return DIALSORT_OK;
@@ -368,7 +369,7 @@ dialsort_status dialsort_histogram(const uint32_t* keys, uint64_t n, uint64_t U,
   if (overlap(keys, n * 4, H, U * 4)) return DIALSORT_EINVAL;
   DS_TRY(check_common(U, ws, ws_bytes, dialsort_workspace_bytes(n, U, DIALSORT_MODE_HISTOGRAM)));
   CallScope scope(stream);
-  return run_sort(keys, n, U, H, nullptr, ws, DIALSORT_MODE_HISTOGRAM, stream);
+  return run_sort(keys, n, U, 0, H, nullptr, ws, DIALSORT_MODE_HISTOGRAM, stream);
 }
 
 dialsort_status dialsort_histogram_accumulate(const uint32_t* keys, uint64_t n, uint64_t U, uint32_t* H, void* ws,
@@ -381,10 +382,33 @@ dialsort_status dialsort_histogram_accumulate(const uint32_t* keys, uint64_t n, 
   CallScope scope(stream);
   char* base = ws_base(ws);
   uint32_t* T = (uint32_t*)(base + accumulate_ws_off(n, U));
-  DS_TRY(run_sort(keys, n, U, T, nullptr, ws, DIALSORT_MODE_HISTOGRAM, stream));
+  DS_TRY(run_sort(keys, n, U, 0, T, nullptr, ws, DIALSORT_MODE_HISTOGRAM, stream));
   const uint32_t grid = (uint32_t)std::min<uint64_t>(cdiv(U, 256), 256 * 8);
   DS_LAUNCH(k_accumulate, dim3(grid), dim3(256), stream, H, T, U, (Ctl*)base);
   return DIALSORT_OK;
+}
+
+dialsort_status dialsort_histogram_offset(const uint32_t* keys, uint64_t n, uint32_t lo, uint64_t U, uint32_t* H,
+                                          void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (U == 0 || U > U_MAX || !H || (n && !keys)) return DIALSORT_EINVAL;
+  if (!aligned4(keys) || !aligned4(H)) return DIALSORT_EINVAL;
+  if (n > N_MAX) return DIALSORT_EOVERFLOW;
+  if (overlap(keys, n * 4, H, U * 4)) return DIALSORT_EINVAL;
+  DS_TRY(check_common(U, ws, ws_bytes, dialsort_workspace_bytes(n, U, DIALSORT_MODE_HISTOGRAM)));
+  CallScope scope(stream);
+  return run_sort(keys, n, U, lo, H, nullptr, ws, DIALSORT_MODE_HISTOGRAM, stream);
+}
+
+dialsort_status dialsort_sort_offset(const uint32_t* keys, uint64_t n, uint32_t lo, uint64_t U, uint32_t* H,
+                                     uint32_t* out, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (U == 0 || U > U_MAX || !H || (n && (!keys || !out))) return DIALSORT_EINVAL;
+  if (!aligned4(keys) || !aligned4(H) || !aligned4(out)) return DIALSORT_EINVAL;
+  if (n > N_MAX) return DIALSORT_EOVERFLOW;
+  if (overlap(keys, n * 4, H, U * 4) || overlap(out, n * 4, H, U * 4)) return DIALSORT_EINVAL;
+  if (out != keys && overlap(keys, n * 4, out, n * 4)) return DIALSORT_EINVAL;
+  DS_TRY(check_common(U, ws, ws_bytes, dialsort_workspace_bytes(n, U, DIALSORT_MODE_SORT)));
+  CallScope scope(stream);
+  return run_sort(keys, n, U, lo, H, out, ws, DIALSORT_MODE_SORT, stream);
 }
 
 dialsort_status dialsort_sort(const uint32_t* keys, uint64_t n, uint64_t U, uint32_t* H, uint32_t* out, void* ws,
@@ -396,7 +420,7 @@ dialsort_status dialsort_sort(const uint32_t* keys, uint64_t n, uint64_t U, uint
   if (out != keys && overlap(keys, n * 4, out, n * 4)) return DIALSORT_EINVAL;
   DS_TRY(check_common(U, ws, ws_bytes, dialsort_workspace_bytes(n, U, DIALSORT_MODE_SORT)));
   CallScope scope(stream);
-  return run_sort(keys, n, U, H, out, ws, DIALSORT_MODE_SORT, stream);
+  return run_sort(keys, n, U, 0, H, out, ws, DIALSORT_MODE_SORT, stream);
 }
 
 dialsort_status dialsort_reconstruct(const uint32_t* H, uint64_t U, uint32_t* out, uint64_t out_cap, void* ws,
@@ -411,7 +435,7 @@ dialsort_status dialsort_reconstruct(const uint32_t* H, uint64_t U, uint32_t* ou
   CallScope scope(stream);
   DS_TRY(launch_init(base, L, nullptr, 0, stream));
   DS_TRY(launch_scan(H, 1, 0, nullptr, U, base, L, true, 1, stream));
-  DS_TRY(launch_fill(H, out, base, L, stream));
+  DS_TRY(launch_fill(H, out, 0, base, L, stream));
   return DIALSORT_OK;
 }
 

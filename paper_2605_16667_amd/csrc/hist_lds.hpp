@@ -28,10 +28,12 @@
 namespace ds {
 
 // Load up to 4 keys of group [e0, e0+4) clipped at `end`; returns how many are
-// valid (a prefix of v).
+// valid (a prefix of v).  Each key is mapped to its index x - lo (mod 2^32),
+// the order-isomorphism phi of Sec. 3.4 for a universe that starts at lo.
 template <bool ALIGNED>
 __device__ __forceinline__ uint32_t load_group(const uint32_t* __restrict__ keys, uint64_t e0, uint64_t end,
-                                               uint32_t v[4]) {
+                                               uint32_t v[4], uint32_t lo) {
+  uint32_t c = 0;
   if (e0 + 4 <= end) {
     if constexpr (ALIGNED) {
       const uint4 q = *reinterpret_cast<const uint4*>(keys + e0);
@@ -39,14 +41,16 @@ __device__ __forceinline__ uint32_t load_group(const uint32_t* __restrict__ keys
     } else {
       v[0] = keys[e0]; v[1] = keys[e0 + 1]; v[2] = keys[e0 + 2]; v[3] = keys[e0 + 3];
     }
-    return 4;
-  }
-  uint32_t c = 0;
+    c = 4;
+  } else {
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    v[i] = 0;
-    if (e0 + i < end) { v[i] = keys[e0 + i]; c = i + 1; }
+    for (int i = 0; i < 4; ++i) {
+      v[i] = 0;
+      if (e0 + i < end) { v[i] = keys[e0 + i]; c = i + 1; }
+    }
   }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] -= lo;
   return c;
 }
 
@@ -98,7 +102,7 @@ struct HistSmem {
 template <int NT, bool PACKED, int AGG, bool ALIGNED, int UNR, typename SM>
 __device__ __forceinline__ void hist_slab(SM& S, const uint32_t* __restrict__ keys, uint64_t beg, uint64_t end,
                                           uint32_t umax, uint32_t U, uint32_t* __restrict__ row,
-                                          uint32_t* status) {
+                                          uint32_t* status, uint32_t lo = 0) {
   const uint32_t nwords = PACKED ? (U + 1) / 2 : U;
   const uint32_t tid = threadIdx.x;
   for (uint32_t i = tid; i < nwords; i += NT) S.s[i] = 0;
@@ -115,7 +119,7 @@ __device__ __forceinline__ void hist_slab(SM& S, const uint32_t* __restrict__ ke
     uint32_t v[UNR][4];
     uint32_t nv[UNR];
 #pragma unroll
-    for (int u = 0; u < UNR; ++u) nv[u] = load_group<ALIGNED>(keys, g0 + ((uint64_t)u * NT + tid) * 4, end, v[u]);
+    for (int u = 0; u < UNR; ++u) nv[u] = load_group<ALIGNED>(keys, g0 + ((uint64_t)u * NT + tid) * 4, end, v[u], lo);
     uint32_t cc[UNR][4];
     uint32_t old[UNR][4];
 #pragma unroll
@@ -192,25 +196,25 @@ __device__ __forceinline__ void hist_slab(SM& S, const uint32_t* __restrict__ ke
 template <int NT, int CAP, bool PACKED, int AGG, bool ALIGNED, int UNR>
 __global__ __launch_bounds__(NT) void k_hist_lds(const uint32_t* __restrict__ keys, uint64_t n, uint64_t per,
                                                  uint32_t umax, uint32_t U, uint32_t* __restrict__ rows,
-                                                 uint64_t row_stride, Ctl* ctl) {
+                                                 uint64_t row_stride, Ctl* ctl, uint32_t lo) {
   __shared__ HistSmem<CAP, PACKED> S;
   const uint64_t beg = (uint64_t)blockIdx.x * per;
   const uint64_t end = beg + per < n ? beg + per : n;
   hist_slab<NT, PACKED, AGG, ALIGNED, UNR>(S, keys, beg, end, umax, U, rows + (uint64_t)blockIdx.x * row_stride,
-                                                  &ctl->status);
+                                                  &ctl->status, lo);
 }
 
 // Direct global atomics into a zeroed H, after the same wave merge.  Used when
 // n is small next to U, or U is too large for the partitioned path.
 template <int NT, int AGG, bool ALIGNED>
 __global__ __launch_bounds__(NT) void k_hist_global(const uint32_t* __restrict__ keys, uint64_t n, uint32_t umax,
-                                                    uint32_t* __restrict__ H, Ctl* ctl) {
+                                                    uint32_t* __restrict__ H, Ctl* ctl, uint32_t lo) {
   bool bad = false;
   WaveAgg st;
   const uint64_t stride = (uint64_t)gridDim.x * NT * 4;
   for (uint64_t g0 = (uint64_t)blockIdx.x * NT * 4; g0 < n; g0 += stride) {
     uint32_t v[4];
-    const uint32_t c = load_group<ALIGNED>(keys, g0 + (uint64_t)threadIdx.x * 4, n, v);
+    const uint32_t c = load_group<ALIGNED>(keys, g0 + (uint64_t)threadIdx.x * 4, n, v, lo);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const bool valid = (uint32_t)i < c;

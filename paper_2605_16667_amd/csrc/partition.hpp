@@ -88,7 +88,7 @@ template <int NT, int BMAXT, int AGG, bool ALIGNED, int LOG2W, int TK>
 __device__ __forceinline__ void partition_tile(PartSmem<NT, BMAXT, TK>& S, const uint32_t* __restrict__ keys, uint64_t n,
                                                uint32_t umax, uint32_t B, uint16_t* __restrict__ staging,
                                                uint16_t* __restrict__ seg, uint32_t bstride, uint32_t* status,
-                                               uint32_t tile, const SplitPlan* plan) {
+                                               uint32_t tile, const SplitPlan* plan, uint32_t lo = 0) {
   constexpr int GPT = TK / 4 / NT;  // key groups of 4 per thread
   static_assert(GPT >= 1, "a tile gives every thread at least one group");
   constexpr uint32_t WM = (1u << LOG2W) - 1;
@@ -102,7 +102,7 @@ __device__ __forceinline__ void partition_tile(PartSmem<NT, BMAXT, TK>& S, const
   bool bad = false;
 #pragma unroll
   for (int u = 0; u < GPT; ++u) {
-    const uint32_t c = load_group<ALIGNED>(keys, tb + ((uint64_t)u * NT + tid) * 4, te, v[u]);
+    const uint32_t c = load_group<ALIGNED>(keys, tb + ((uint64_t)u * NT + tid) * 4, te, v[u], lo);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const bool valid = (uint32_t)i < c;
@@ -253,10 +253,10 @@ __global__ __launch_bounds__(P1_NT) void k_partition(const uint32_t* __restrict_
                                                      uint32_t umax, uint32_t B,
                                                      uint16_t* __restrict__ staging,
                                                      uint16_t* __restrict__ seg, uint32_t bstride, Ctl* ctl,
-                                                     SplitPlan plan) {
+                                                     SplitPlan plan, uint32_t lo) {
   __shared__ PartSmem<P1_NT, BMAXT, PART_TK> S;
   partition_tile<P1_NT, BMAXT, AGG, ALIGNED, PART_LOG2W, PART_TK>(S, keys, n, umax, B, staging, seg, bstride,
-                                                                 &ctl->status, blockIdx.x, &plan);
+                                                                 &ctl->status, blockIdx.x, &plan, lo);
 }
 
 // ---------------------------------------------------------------------------

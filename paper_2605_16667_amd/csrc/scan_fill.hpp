@@ -275,7 +275,7 @@ struct WaveFillSmem {
 
 template <int CL2, bool OALIGNED>
 __device__ __forceinline__ void wave_fill_item(WaveFillSmem<CL2>& S, const uint32_t* __restrict__ H,
-                                               uint32_t* __restrict__ out, const FillItem& I) {
+                                               uint32_t* __restrict__ out, const FillItem& I, uint32_t lo = 0) {
   constexpr uint32_t C = 1u << CL2;
   constexpr uint32_t NFW = C / 32;
   static_assert(NFW <= (uint32_t)WAVE, "one flag word per lane at most");
@@ -337,7 +337,7 @@ __device__ __forceinline__ void wave_fill_item(WaveFillSmem<CL2>& S, const uint3
   // at position p is the last mark at or before p in the segment, else the
   // segment's carried key
   const uint32_t nq = (le + 3) >> 2;
-  const uint32_t kf = I.k;
+  const uint32_t kf = I.k + lo;  // phi^-1 (Sec. 3.4): bin k holds key lo + k
   for (uint32_t q = lane; q < nq; q += WAVE) {
     const uint32_t sg = q >> 3;
     const uint32_t fw = S.flag[sg];
@@ -369,7 +369,7 @@ __device__ __forceinline__ void wave_fill_item(WaveFillSmem<CL2>& S, const uint3
 template <int NT, int CL2, bool OALIGNED>
 __global__ __launch_bounds__(NT) void k_fill(const uint32_t* __restrict__ H, uint32_t* __restrict__ out,
                                              Ctl* ctl, const FillItem* __restrict__ items,
-                                             uint32_t item_cap) {
+                                             uint32_t item_cap, uint32_t lo) {
   constexpr uint32_t NW = NT / WAVE;
   __shared__ WaveFillSmem<CL2> S[NW];
   const uint32_t w = threadIdx.x / WAVE;
@@ -383,7 +383,7 @@ __global__ __launch_bounds__(NT) void k_fill(const uint32_t* __restrict__ H, uin
       if (lane_id() == 0) atomicOr(&ctl->status, ST_INT_ITEM);
       continue;
     }
-    wave_fill_item<CL2, OALIGNED>(S[w], H, out, I);
+    wave_fill_item<CL2, OALIGNED>(S[w], H, out, I, lo);
   }
 }
 

@@ -295,3 +295,25 @@ def test_accumulate_is_ingestion_of_the_whole_stream():
     assert st == oracle.OK and near[2] == 0xFFFFFFFF
     st, _ = oracle.histogram_accumulate(np.array([2], dtype=np.uint32), 4, near)
     assert st == oracle.EOVERFLOW
+
+
+def test_offset_sort_is_the_order_of_the_domain():
+    """phi(x) = x - lo (Sec. 3.4): signed int32 keys come out in numpy's signed
+    order, and a universe that wraps past 2^32 - 1 keeps its order."""
+    rng = np.random.default_rng(91)
+    signed = rng.integers(-1000, 1001, 5000).astype(np.int32)
+    lo = -1000
+    st, H, out = oracle.sort_offset(signed.view(np.uint32), lo, 2001)
+    assert st == oracle.OK
+    assert np.array_equal(out.view(np.int32), np.sort(signed))
+    assert H[0] == np.count_nonzero(signed == -1000) and H[2000] == np.count_nonzero(signed == 1000)
+    lo = 0xFFFFFF00
+    wrap = ((lo + rng.integers(0, 512, 3000)) % 2**32).astype(np.uint32)
+    st, H, out = oracle.sort_offset(wrap, lo, 512)
+    assert st == oracle.OK
+    want = sorted(wrap.tolist(), key=lambda x: (x - lo) % 2**32)
+    assert out.tolist() == want
+    st, _, _ = oracle.sort_offset(np.array([lo - 1], dtype=np.uint32), lo, 512)
+    assert st == oracle.ERANGE
+    st, H0, out0 = oracle.sort_offset(signed.view(np.uint32) & 0, 0, 1)  # lo = 0 is the plain sort
+    assert st == oracle.OK and H0[0] == signed.size
