@@ -6,7 +6,8 @@ Python binding) never does, and shares no code with it.
 
 ``dialsort_oracle.c`` states the method as the paper defines it: ingestion,
 Eq. (1) (Sec. 3.3), then the ordered projection, Eq. (2) (Sec. 3.3), and the
-sort over a universe that starts anywhere (phi of Sec. 3.4), and the
+sort over a universe that starts anywhere (phi of Sec. 3.4), DialSort-Radix
+(Sec. 8, full int32 range), and the
 queries that read H directly (frequency, presence and range-count, from the
 paragraph on the canonical ordered state in Sec. 3.3; prefix and select, the
 running count and the projection read at one position).  This
@@ -58,6 +59,8 @@ def _load() -> ctypes.CDLL:
         lib.oracle_histogram_accumulate.restype = ctypes.c_int
         lib.oracle_sort_offset.argtypes = [p, u64, ctypes.c_uint32, u64, p, p]
         lib.oracle_sort_offset.restype = ctypes.c_int
+        lib.oracle_sort_radix.argtypes = [p, u64, ctypes.c_int, p, p]
+        lib.oracle_sort_radix.restype = ctypes.c_int
         for name in ("oracle_frequency", "oracle_presence"):
             getattr(lib, name).argtypes = [p, u64, p, u64, p]
             getattr(lib, name).restype = None
@@ -109,6 +112,15 @@ def sort_offset(keys, lo: int, U: int) -> Tuple[int, np.ndarray, np.ndarray]:
     st = _load().oracle_sort_offset(_ptr(k), k.size, lo & 0xFFFFFFFF, U, H.ctypes.data_as(ctypes.c_void_p),
                                     _ptr(out))
     return st, H, out
+
+
+def sort_radix(keys, is_signed: bool = False) -> Tuple[int, np.ndarray]:
+    """DialSort-Radix: LSD base 256, 4 passes (signed: sign bit flipped)."""
+    k = _as_u32(keys)
+    out = np.empty(max(k.size, 1), dtype=np.uint32)
+    tmp = np.empty(max(k.size, 1), dtype=np.uint32)
+    st = _load().oracle_sort_radix(_ptr(k), k.size, 1 if is_signed else 0, _ptr(out), _ptr(tmp))
+    return st, out[: k.size]
 
 
 def reconstruct(H, out_cap: Optional[int] = None) -> Tuple[int, np.ndarray]:

@@ -171,3 +171,41 @@ int oracle_sort_offset(const uint32_t *keys, uint64_t n, uint32_t lo, uint64_t U
         for (r = 0; r < H[k]; ++r) out[pos++] = (uint32_t)(lo + k);
     return pos == n ? ORACLE_OK : ORACLE_EOVERFLOW;
 }
+
+/* DialSort-Radix (Sec. 8, "Full int32 range"): LSD, base 256, 4 passes, no
+ * order comparison.  Each pass is DialSort on one 8-bit digit: Eq. (1) counts
+ * the digits into H[0, 256), the running count of H gives where each digit's
+ * run starts, and the keys are placed in input order within their digit's run
+ * (stable), so the passes compose.  Signed keys go through phi(x) = x with its
+ * sign bit flipped (Sec. 3.4), which maps int32 order onto uint32 order, and
+ * come back through the same flip.  tmp holds n keys. */
+int oracle_sort_radix(const uint32_t *keys, uint64_t n, int is_signed, uint32_t *out, uint32_t *tmp) {
+    uint64_t i;
+    int pass, d;
+    const uint32_t flip = is_signed ? 0x80000000u : 0u;
+    uint32_t *src = tmp, *dst = out;
+    if (n > 0 && (keys == NULL || out == NULL || tmp == NULL)) return ORACLE_EINVAL;
+    for (i = 0; i < n; ++i) tmp[i] = keys[i] ^ flip;
+    for (pass = 0; pass < 4; ++pass) {
+        uint64_t H[256], start[256], run = 0;
+        const int shift = 8 * pass;
+        for (d = 0; d < 256; ++d) H[d] = 0;
+        for (i = 0; i < n; ++i) H[(src[i] >> shift) & 255u] += 1;
+        for (d = 0; d < 256; ++d) {
+            start[d] = run;
+            run += H[d];
+        }
+        for (i = 0; i < n; ++i) {
+            const uint32_t x = src[i];
+            const uint32_t dg = (x >> shift) & 255u;
+            dst[start[dg]] = x;
+            start[dg] += 1;
+        }
+        /* the next pass reads what this one wrote */
+        src = dst;
+        dst = (dst == out) ? tmp : out;
+    }
+    /* four passes: the last one wrote into tmp */
+    for (i = 0; i < n; ++i) out[i] = src[i] ^ flip;
+    return ORACLE_OK;
+}

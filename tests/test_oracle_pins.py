@@ -317,3 +317,22 @@ def test_offset_sort_is_the_order_of_the_domain():
     assert st == oracle.ERANGE
     st, H0, out0 = oracle.sort_offset(signed.view(np.uint32) & 0, 0, 1)  # lo = 0 is the plain sort
     assert st == oracle.OK and H0[0] == signed.size
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 255, 1000, 70000])
+def test_radix_is_numpy_sort(n):
+    """DialSort-Radix over the full 32-bit range, signed and unsigned, equals a
+    comparison sort (numpy) -- including keys that differ only in one digit."""
+    rng = np.random.default_rng(n + 3)
+    u = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+    if n >= 4:
+        u[:4] = [0xFFFFFFFF, 0, 0x80000000, 0x7FFFFFFF]
+    st, out = oracle.sort_radix(u)
+    assert st == oracle.OK and np.array_equal(out, np.sort(u))
+    s = u.view(np.int32)
+    st, out = oracle.sort_radix(s, is_signed=True)
+    assert st == oracle.OK and np.array_equal(out.view(np.int32), np.sort(s))
+    # one digit at a time: keys equal above and below digit 2
+    d = (0x11220033 | (rng.integers(0, 256, n).astype(np.uint32) << 8)).astype(np.uint32)
+    st, out = oracle.sort_radix(d)
+    assert np.array_equal(out, np.sort(d))
