@@ -378,6 +378,20 @@ dialsort_status dialsort_query_range_count(const uint64_t *P, uint64_t U, const 
 dialsort_status dialsort_query_select(const uint64_t *P, uint64_t U, const uint64_t *r, uint64_t nq,
                                       uint32_t *out, hipStream_t stream);
 
+/* ---- DialSort-Radix: the whole 32-bit range ----------------------------------
+ *
+ * LSD, base 256, four passes, no order comparison (Sec. 8, "Full int32 range",
+ * Table "tab:radix"): each pass counts one 8-bit digit per tile (Eq. (1)),
+ * takes the running count over (digit, tile) as positions (Eq. (2)), and
+ * places every key stably within its digit.  out[0 .. n) = the keys in
+ * ascending order: as uint32, or, with is_signed != 0, as int32 (the sign bit
+ * is flipped on the first load and back on the last store, the phi of Sec.
+ * 3.4).  No histogram over the 2^32 keys is formed.  out may equal keys;
+ * any other overlap is EINVAL.  n > 2^32 - 1 is EOVERFLOW. */
+size_t dialsort_radix_workspace_bytes(uint64_t n);
+dialsort_status dialsort_sort_radix(const uint32_t *keys, uint64_t n, int is_signed, uint32_t *out, void *ws,
+                                    size_t ws_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -107,6 +107,8 @@ def _load() -> ctypes.CDLL:
         "dialsort_prefix": (st, [p, u64, p, p, sz, p]),
         "dialsort_query_range_count": (st, [p, u64, p, p, u64, p, p]),
         "dialsort_query_select": (st, [p, u64, p, u64, p, p]),
+        "dialsort_radix_workspace_bytes": (sz, [u64]),
+        "dialsort_sort_radix": (st, [p, u64, ctypes.c_int, p, p, sz, p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -126,7 +128,8 @@ EXPORTED = ("dialsort_workspace_bytes", "dialsort_histogram", "dialsort_histogra
             "dialsort_result_total", "dialsort_strerror", "dialsort_last_hip_error",
             "dialsort_set_launch_events", "dialsort_launch_name", "dialsort_query_frequency",
             "dialsort_query_presence", "dialsort_prefix_workspace_bytes", "dialsort_prefix",
-            "dialsort_query_range_count", "dialsort_query_select")
+            "dialsort_query_range_count", "dialsort_query_select", "dialsort_radix_workspace_bytes",
+            "dialsort_sort_radix")
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -385,3 +388,18 @@ def dialsort_query_select(P: torch.Tensor, U: int, r: torch.Tensor, out: torch.T
     if out.numel() < r.numel():
         return DIALSORT_EINVAL
     return _lib.dialsort_query_select(_ptr(P), U, _ptr(r), r.numel(), _ptr(out), _stream(stream))
+
+
+# ---- DialSort-Radix (the whole 32-bit range) ------------------------------------
+
+
+def dialsort_radix_workspace_bytes(n: int) -> int:
+    return _lib.dialsort_radix_workspace_bytes(n)
+
+
+def dialsort_sort_radix(keys: torch.Tensor, out: torch.Tensor, ws: torch.Tensor, is_signed: bool = False,
+                        stream=None) -> int:
+    if out.numel() < keys.numel():
+        return DIALSORT_EINVAL
+    return _lib.dialsort_sort_radix(_ptr(keys), keys.numel(), 1 if is_signed else 0, _ptr(out), _ptr(ws),
+                                    ws.numel(), _stream(stream))

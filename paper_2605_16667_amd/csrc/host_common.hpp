@@ -94,5 +94,7 @@ dialsort_status check_desc(const dialsort_desc& d);
 // every array is folded into the status word of ws.
 size_t loop_workspace_bytes(const dialsort_desc* d, uint32_t count);
 dialsort_status loop_run(const dialsort_desc* d, uint32_t count, void* ws, size_t ws_bytes, hipStream_t s);
+// Running count P[0 .. U] of H (query.hip); ws sized by dialsort_prefix_workspace_bytes(U).
+dialsort_status launch_prefix(const uint32_t* H, uint64_t U, uint64_t* P, void* ws, hipStream_t stream);
 
 }  // namespace dsh

@@ -162,6 +162,23 @@ size_t prefix_ws_bytes(uint64_t U) { return ALIGN + align_up(cdiv(U, PF_TB) * 8,
 
 }  // namespace
 
+namespace dsh {
+
+// The running count P of H (U + 1 entries) with the workspace laid out by
+// prefix_ws_bytes; arguments already checked.
+dialsort_status launch_prefix(const uint32_t* H, uint64_t U, uint64_t* P, void* ws, hipStream_t stream) {
+  char* base = ws_base(ws);
+  uint32_t* ticket = (uint32_t*)base;
+  uint64_t* state = (uint64_t*)(base + ALIGN);
+  const uint64_t ntiles = cdiv(U, PF_TB);
+  DS_LAUNCH(k_prefix_init, dim3((uint32_t)std::min<uint64_t>(cdiv(ntiles + 1, 256), 1024)), dim3(256), stream,
+            ticket, state, ntiles);
+  DS_LAUNCH(k_prefix, dim3((uint32_t)ntiles), dim3(PF_NT), stream, H, U, P, ticket, state);
+  return DIALSORT_OK;
+}
+
+}  // namespace dsh
+
 extern "C" {
 
 dialsort_status dialsort_query_frequency(const uint32_t* H, uint64_t U, const uint32_t* q, uint64_t nq,
@@ -190,15 +207,8 @@ dialsort_status dialsort_prefix(const uint32_t* H, uint64_t U, uint64_t* P, void
   if (!aligned4(H) || !aligned8(P)) return DIALSORT_EINVAL;
   if (overlap(H, U * 4, P, (U + 1) * 8)) return DIALSORT_EINVAL;
   if (!ws || ws_bytes < prefix_ws_bytes(U)) return DIALSORT_EWORKSPACE;
-  char* base = ws_base(ws);
-  uint32_t* ticket = (uint32_t*)base;
-  uint64_t* state = (uint64_t*)(base + ALIGN);
-  const uint64_t ntiles = cdiv(U, PF_TB);
   CallScope scope(stream);
-  DS_LAUNCH(k_prefix_init, dim3((uint32_t)std::min<uint64_t>(cdiv(ntiles + 1, 256), 1024)), dim3(256), stream,
-            ticket, state, ntiles);
-  DS_LAUNCH(k_prefix, dim3((uint32_t)ntiles), dim3(PF_NT), stream, H, U, P, ticket, state);
-  return DIALSORT_OK;
+  return dsh::launch_prefix(H, U, P, ws, stream);
 }
 
 dialsort_status dialsort_query_range_count(const uint64_t* P, uint64_t U, const uint64_t* a, const uint64_t* b,
