@@ -18,6 +18,7 @@ fields of the same line:
            loads, against serial plain sorts; p50/p99 latency and keys/s
   query    queries on the large workload's histogram: the running count over
            2^24 bins, and 2^20 frequency/presence/range-count/select queries
+  radix    DialSort-Radix over the whole signed int32 range, n = 1e7 and 1e8
 The roofline object is for the kernel that takes the most time per step,
 measured with HIP events recorded on the launch stream around every kernel of
 every timed step (dialsort_set_launch_events).  Its algorithmic bytes are the
@@ -575,6 +576,42 @@ def run_query_workload(ds, keys, U, K, W, nq=1 << 20):
     return res
 
 
+def run_radix_workload(ds, K, W, sizes=(10**7, 10**8)):
+    """DialSort-Radix over the whole signed int32 range (the paper's Table
+    tab:radix workload: uniform int32 keys), at each size: keys/s, verified
+    against torch's sort of the same keys."""
+    import torch
+
+    res = {}
+    for n in sizes:
+        g = torch.Generator(device="cuda")
+        g.manual_seed(20260321 + 60 + n % 1000)
+        keys = torch.randint(-2**31, 2**31, (n,), generator=g, device="cuda", dtype=torch.int64).to(torch.int32)
+        out = torch.empty_like(keys)
+        ws = ds.workspace(ds.dialsort_radix_workspace_bytes(n))
+        call = lambda: ds.check(ds.dialsort_sort_radix(keys, out, ws, is_signed=True))  # noqa: E731
+        for _ in range(W):
+            call()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0.record()
+        for _ in range(K):
+            call()
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / K
+        ok = bool(torch.equal(out, torch.sort(keys).values))
+        # four passes, each reading the keys twice and writing them once
+        res[str(n)] = {"ms": ms, "keys_per_s": n / (ms * 1e-3), "verified": ok,
+                       "GBps_moved": 4 * 12 * n / (ms * 1e-3) / 1e9}
+        del keys, out, ws
+        torch.cuda.empty_cache()
+    res["paper_context"] = {"keys_per_s": 38.2e6, "n": 10**7,
+                            "what": "DS-Radix, full int32 range, CPU (Table tab:radix)"}
+    return res
+
+
 def cpu_baseline(keys_dev, U, budget_s=12.0, max_runs=5):
     """The oracle as it stands, on this host, on the same keys (sequential C)."""
     import oracle
@@ -600,7 +637,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workloads", default="large,hist,query,plain,skewed,batch,serve")
+    ap.add_argument("--workloads", default="large,hist,query,plain,skewed,radix,batch,serve")
     ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--serve-loads", default="0.7,1.5,3.0",
                     help="arrival rates, as multiples of 1 / (mean serial service time)")
@@ -688,6 +725,9 @@ def main():
         del k3u
         torch.cuda.empty_cache()
 
+    if "radix" in todo:
+        log("radix: whole signed int32 range")
+        extra["radix"] = run_radix_workload(ds, max(K // 2, 5), 2)
     batch_cfg = None
     if "batch" in todo:
         extra["batched"] = run_batch_workload(ds, hip, args.batch_count, max(K // 4, 3), 2)
