@@ -37,7 +37,8 @@ def radix(ds, keys_u32, is_signed, in_place=False):
     return w.as_u32(out[:n])
 
 
-@pytest.mark.parametrize("n", [0, 1, 2, 4095, 4096, 4097, 100_000, (1 << 20) + 3, 10_000_000])
+@pytest.mark.parametrize("n", [0, 1, 2, 63, 65, 1023, 1025, 8191, 8192, 8193, 3 * 8192 + 5000, 100_000,
+                               (1 << 20) + 3, 10_000_000])
 @pytest.mark.parametrize("is_signed", [False, True])
 def test_radix_random_full_range(ds, n, is_signed):
     say(f"radix n={n} signed={is_signed}")
