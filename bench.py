@@ -85,18 +85,18 @@ class HipEvents:
 
 def algo_bytes(name: str, n: int, U: int, mode: str) -> int:
     """Compulsory bytes of the method handled by one launch of kernel `name`:
-    ingestion reads the keys (4n), the histogram is written once (4U) and, in a
-    sort, read once by the projection (4U), which writes the output (4n).  The
-    kernel that produces H also reads it for the projection (k_bucket from LDS,
-    k_scan as it goes); the fill only writes.  Partial rows, staging, counters
-    and fill items are the implementation's own and count against the kernel."""
-    full = mode == "sort"
+    ingestion reads the keys (4n), the histogram is written once (4U) by the
+    kernel that produces it (k_bucket, or k_scan from partial rows) and, in a
+    sort, read once by the projection, k_fill, which also writes the output
+    (4n).  The item boundaries k_bucket and k_scan derive come from data they
+    already hold.  Partial rows, staging, counters and fill items are the
+    implementation's own and count against the kernel."""
     if "k_hist" in name or "k_partition" in name:
         return 4 * n
     if "k_bucket" in name or "k_scan" in name:
-        return (8 if full else 4) * U
+        return 4 * U
     if "k_fill" in name:
-        return 4 * n
+        return 4 * n + 4 * U if mode == "sort" else 0
     return 0
 
 

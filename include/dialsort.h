@@ -90,6 +90,29 @@ dialsort_status dialsort_histogram_offset(const uint32_t *keys, uint64_t n, uint
 dialsort_status dialsort_sort_offset(const uint32_t *keys, uint64_t n, uint32_t lo, uint64_t U, uint32_t *H,
                                      uint32_t *out, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* Keys given as indices phi(s) in [0, U) of a finite totally ordered domain,
+ * with phi^-1 as a table (Sec. 3.4, the General Self-Indexing Principle: the
+ * projection emits phi^-1(k) H[k] times, and outside the integers a lookup
+ * table serves as phi^-1).  lut holds U 32-bit values, lut[k] = phi^-1(k)
+ * (device memory, read only).  H is the histogram of the indices, as in
+ * dialsort_sort, and out[0 .. n) receives lut[k] for the indices in
+ * nondecreasing order: the elements in the domain's order when lut is
+ * increasing.  lut must not overlap H or out; out may equal keys.  An index
+ * >= U is ERANGE.  Workspace: dialsort_workspace_bytes(n, U,
+ * DIALSORT_MODE_SORT). */
+dialsort_status dialsort_sort_lut(const uint32_t *keys, uint64_t n, uint64_t U, const uint32_t *lut, uint32_t *H,
+                                  uint32_t *out, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* The smallest and the largest key, compared as int32 when is_signed, else as
+ * uint32: minmax[0] = min, minmax[1] = max (two 32-bit words of device
+ * memory, written on `stream`).  They give the smallest offset map of Sec. 3.4
+ * that holds the keys (the min-max choice of phi): lo = min, U = max - min + 1
+ * (as a 64-bit count) for dialsort_sort_offset.  n == 0 leaves min above max:
+ * the pair (0xFFFFFFFF, 0), or (0x7FFFFFFF, 0x80000000) when is_signed.  No
+ * workspace; minmax must not overlap keys. */
+dialsort_status dialsort_key_range(const uint32_t *keys, uint64_t n, int is_signed, uint32_t *minmax,
+                                   hipStream_t stream);
+
 /* Accumulating ingestion, for keys that arrive in pieces (streaming): H[k] +=
  * |{ i : keys[i] == k }| for every k in [0, U), so that ingesting a key stream
  * piece by piece leaves in H the histogram of the whole stream (Eq. (1) is a

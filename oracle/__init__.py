@@ -6,8 +6,10 @@ Python binding) never does, and shares no code with it.
 
 ``dialsort_oracle.c`` states the method as the paper defines it: ingestion,
 Eq. (1) (Sec. 3.3), then the ordered projection, Eq. (2) (Sec. 3.3), and the
-sort over a universe that starts anywhere (phi of Sec. 3.4), DialSort-Radix
-(Sec. 8, full int32 range), and the
+sort over a universe that starts anywhere (phi of Sec. 3.4), the sort of a
+domain given by its index map with phi^-1 as a table and the key range that
+fixes the smallest offset map (both Sec. 3.4), DialSort-Radix (Sec. 8, full
+int32 range), and the
 queries that read H directly (frequency, presence and range-count, from the
 paragraph on the canonical ordered state in Sec. 3.3; prefix and select, the
 running count and the projection read at one position).  This
@@ -61,6 +63,10 @@ def _load() -> ctypes.CDLL:
         lib.oracle_sort_offset.restype = ctypes.c_int
         lib.oracle_sort_radix.argtypes = [p, u64, ctypes.c_int, p, p]
         lib.oracle_sort_radix.restype = ctypes.c_int
+        lib.oracle_sort_lut.argtypes = [p, u64, u64, p, p, p]
+        lib.oracle_sort_lut.restype = ctypes.c_int
+        lib.oracle_key_range.argtypes = [p, u64, ctypes.c_int, p]
+        lib.oracle_key_range.restype = ctypes.c_int
         for name in ("oracle_frequency", "oracle_presence"):
             getattr(lib, name).argtypes = [p, u64, p, u64, p]
             getattr(lib, name).restype = None
@@ -112,6 +118,27 @@ def sort_offset(keys, lo: int, U: int) -> Tuple[int, np.ndarray, np.ndarray]:
     st = _load().oracle_sort_offset(_ptr(k), k.size, lo & 0xFFFFFFFF, U, H.ctypes.data_as(ctypes.c_void_p),
                                     _ptr(out))
     return st, H, out
+
+
+def sort_lut(keys, U: int, lut) -> Tuple[int, np.ndarray, np.ndarray]:
+    """Sec. 3.4 with phi^-1 as a table: indices in [0, U), out = lut[k] per
+    index in ascending k.  Returns (status, H, out)."""
+    k = _as_u32(keys)
+    t = _as_u32(lut)
+    if t.size < U:
+        return EINVAL, None, None
+    H = np.zeros(U, dtype=np.uint32)
+    out = np.empty(max(k.size, 1), dtype=np.uint32)
+    st = _load().oracle_sort_lut(_ptr(k), k.size, U, _ptr(t), H.ctypes.data_as(ctypes.c_void_p), _ptr(out))
+    return st, H, out[: k.size]
+
+
+def key_range(keys, is_signed: bool = False) -> Tuple[int, int, int]:
+    """(status, min, max) as uint32 bit patterns (compared as int32 when signed)."""
+    k = _as_u32(keys)
+    mm = np.zeros(2, dtype=np.uint32)
+    st = _load().oracle_key_range(_ptr(k), k.size, 1 if is_signed else 0, _ptr(mm))
+    return st, int(mm[0]), int(mm[1])
 
 
 def sort_radix(keys, is_signed: bool = False) -> Tuple[int, np.ndarray]:

@@ -172,6 +172,53 @@ int oracle_sort_offset(const uint32_t *keys, uint64_t n, uint32_t lo, uint64_t U
     return pos == n ? ORACLE_OK : ORACLE_EOVERFLOW;
 }
 
+/* The General Self-Indexing Principle (Sec. 3.4) for a domain given by its
+ * index map: keys are the indices phi(s) in [0, U), and phi^-1 is the table
+ * lut (U entries).  Eq. (1) over the indices, then Eq. (2) emitting lut[k],
+ * H[k] times, for k ascending. */
+int oracle_sort_lut(const uint32_t *keys, uint64_t n, uint64_t U, const uint32_t *lut, uint32_t *H, uint32_t *out) {
+    uint64_t i, k, r, pos = 0;
+    if (U == 0 || U > ((uint64_t)1 << 32) || H == NULL || lut == NULL) return ORACLE_EINVAL;
+    if (n > 0 && (keys == NULL || out == NULL)) return ORACLE_EINVAL;
+    if (n > (uint64_t)0xFFFFFFFFu) return ORACLE_EOVERFLOW;
+    for (k = 0; k < U; ++k) H[k] = 0;
+    for (i = 0; i < n; ++i) {
+        if (keys[i] >= U) return ORACLE_ERANGE;
+        H[keys[i]] = H[keys[i]] + 1;
+    }
+    for (k = 0; k < U; ++k)
+        for (r = 0; r < H[k]; ++r) out[pos++] = lut[k];
+    return ORACLE_OK;
+}
+
+/* The smallest and largest key, one comparison of each key against each
+ * running bound, as int32 when is_signed: they fix the smallest offset map
+ * phi(x) = x - min of Sec. 3.4 that holds the keys.  n == 0 leaves
+ * (UINT32_MAX, 0), or (INT32_MAX, INT32_MIN) when signed. */
+int oracle_key_range(const uint32_t *keys, uint64_t n, int is_signed, uint32_t *minmax) {
+    uint64_t i;
+    if (minmax == NULL || (n > 0 && keys == NULL)) return ORACLE_EINVAL;
+    if (is_signed) {
+        int32_t lo = INT32_MAX, hi = INT32_MIN;
+        for (i = 0; i < n; ++i) {
+            int32_t x = (int32_t)keys[i];
+            if (x < lo) lo = x;
+            if (x > hi) hi = x;
+        }
+        minmax[0] = (uint32_t)lo;
+        minmax[1] = (uint32_t)hi;
+    } else {
+        uint32_t lo = 0xFFFFFFFFu, hi = 0;
+        for (i = 0; i < n; ++i) {
+            if (keys[i] < lo) lo = keys[i];
+            if (keys[i] > hi) hi = keys[i];
+        }
+        minmax[0] = lo;
+        minmax[1] = hi;
+    }
+    return ORACLE_OK;
+}
+
 /* DialSort-Radix (Sec. 8, "Full int32 range"): LSD, base 256, 4 passes, no
  * order comparison.  Each pass is DialSort on one 8-bit digit: Eq. (1) counts
  * the digits into H[0, 256), the running count of H gives where each digit's

@@ -71,6 +71,8 @@ def _load() -> ctypes.CDLL:
         "dialsort_histogram_accumulate": (st, [p, u64, u64, p, p, sz, p]),
         "dialsort_histogram_offset": (st, [p, u64, ctypes.c_uint32, u64, p, p, sz, p]),
         "dialsort_sort_offset": (st, [p, u64, ctypes.c_uint32, u64, p, p, p, sz, p]),
+        "dialsort_sort_lut": (st, [p, u64, u64, p, p, p, p, sz, p]),
+        "dialsort_key_range": (st, [p, u64, ctypes.c_int, p, p]),
         "dialsort_reconstruct": (st, [p, u64, p, u64, p, sz, p]),
         "dialsort_sort": (st, [p, u64, u64, p, p, p, sz, p]),
         "dialsort_batched_workspace_bytes": (sz, [ctypes.POINTER(dialsort_desc), ctypes.c_uint32]),
@@ -118,7 +120,7 @@ def _load() -> ctypes.CDLL:
 
 _lib = _load()
 EXPORTED = ("dialsort_workspace_bytes", "dialsort_histogram", "dialsort_histogram_accumulate",
-            "dialsort_histogram_offset", "dialsort_sort_offset",
+            "dialsort_histogram_offset", "dialsort_sort_offset", "dialsort_sort_lut", "dialsort_key_range",
             "dialsort_reconstruct", "dialsort_sort",
             "dialsort_batched_workspace_bytes", "dialsort_sort_batched", "dialsort_sort_each",
             "dialsort_batch_prepare", "dialsort_batch_launch", "dialsort_batch_autotune",
@@ -193,6 +195,22 @@ def dialsort_sort_offset(keys: torch.Tensor, lo: int, U: int, H: torch.Tensor, o
         return DIALSORT_EINVAL
     return _lib.dialsort_sort_offset(_ptr(keys), keys.numel(), lo & 0xFFFFFFFF, U, _ptr(H), _ptr(out), _ptr(ws),
                                      ws.numel(), _stream(stream))
+
+
+def dialsort_sort_lut(keys: torch.Tensor, U: int, lut: torch.Tensor, H: torch.Tensor, out: torch.Tensor,
+                      ws: torch.Tensor, stream=None) -> int:
+    """Indices in [0, U); out receives lut[k] for the indices in order."""
+    if out.numel() < keys.numel() or lut.numel() < U or lut.element_size() != 4:
+        return DIALSORT_EINVAL
+    return _lib.dialsort_sort_lut(_ptr(keys), keys.numel(), U, _ptr(lut), _ptr(H), _ptr(out), _ptr(ws), ws.numel(),
+                                  _stream(stream))
+
+
+def dialsort_key_range(keys: torch.Tensor, minmax: torch.Tensor, is_signed: bool = False, stream=None) -> int:
+    """minmax[0] = min, minmax[1] = max of the keys (two 32-bit device words)."""
+    if minmax.numel() * minmax.element_size() < 8:
+        return DIALSORT_EINVAL
+    return _lib.dialsort_key_range(_ptr(keys), keys.numel(), int(bool(is_signed)), _ptr(minmax), _stream(stream))
 
 
 def dialsort_sort(keys: torch.Tensor, U: int, H: torch.Tensor, out: torch.Tensor, ws: torch.Tensor,

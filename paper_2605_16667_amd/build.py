@@ -7,7 +7,8 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRCS = [os.path.join(HERE, "csrc", f) for f in ("dialsort.hip", "batch.hip", "server.hip", "query.hip", "radix.hip")]
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("dialsort.hip", "batch.hip", "server.hip", "query.hip", "radix.hip",
+                                                             "transform.hip")]
 LIB = os.path.join(HERE, "libdialsort.so")
 
 HIPCC_FLAGS = [

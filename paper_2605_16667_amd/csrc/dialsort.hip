@@ -252,17 +252,23 @@ dialsort_status launch_scan(const uint32_t* rows, uint32_t nrows, uint64_t row_s
 }
 
 dialsort_status launch_fill(const uint32_t* H, uint32_t* out, uint32_t lo, char* base, const Layout& L,
-                            hipStream_t s) {
+                            hipStream_t s, const uint32_t* lut = nullptr) {
   Ctl* ctl = (Ctl*)base;
   const FillItem* items = (const FillItem*)(base + L.off_items);
   if (L.limit == 0) return DIALSORT_OK;
   // one resident round of workgroups (7 per CU at 256 threads), or fewer
   const uint32_t grid = (uint32_t)std::min<uint64_t>(cdiv(L.item_cap, FILL_NT / WAVE), 256 * 7);
   const uint32_t icap = (uint32_t)std::min<uint64_t>(L.item_cap, 0xFFFFFFF0ull);
-  if (aligned16(out))
-    DS_LAUNCH((k_fill<FILL_NT, FILL_CL2, true>), dim3(grid), dim3(FILL_NT), s, H, out, ctl, items, icap, lo);
-  else
-    DS_LAUNCH((k_fill<FILL_NT, FILL_CL2, false>), dim3(grid), dim3(FILL_NT), s, H, out, ctl, items, icap, lo);
+  if (lut) {
+    if (aligned16(out))
+      DS_LAUNCH((k_fill<FILL_NT, FILL_CL2, true, true>), dim3(grid), dim3(FILL_NT), s, H, out, ctl, items, icap, 0u, lut);
+    else
+      DS_LAUNCH((k_fill<FILL_NT, FILL_CL2, false, true>), dim3(grid), dim3(FILL_NT), s, H, out, ctl, items, icap, 0u, lut);
+  } else if (aligned16(out)) {
+    DS_LAUNCH((k_fill<FILL_NT, FILL_CL2, true>), dim3(grid), dim3(FILL_NT), s, H, out, ctl, items, icap, lo, nullptr);
+  } else {
+    DS_LAUNCH((k_fill<FILL_NT, FILL_CL2, false>), dim3(grid), dim3(FILL_NT), s, H, out, ctl, items, icap, lo, nullptr);
+  }
   return DIALSORT_OK;
 }
 
@@ -290,7 +296,7 @@ dialsort_status check_common(uint64_t U, const void* ws, size_t ws_bytes, size_t
 
 // histogram or sort, after argument checks
 dialsort_status run_sort(const uint32_t* keys, uint64_t n, uint64_t U, uint32_t lo, uint32_t* H, uint32_t* out, void* ws,
-                         int mode, hipStream_t s) {
+                         int mode, hipStream_t s, const uint32_t* lut = nullptr) {
   const Layout L = plan(n, U, mode);
   char* base = ws_base(ws);
   const bool zeroH = L.kind == K_EMPTY || L.kind == K_GLOBAL;
@@ -305,7 +311,7 @@ dialsort_status run_sort(const uint32_t* keys, uint64_t n, uint64_t U, uint32_t 
   if (L.kind != K_PART)
     DS_TRY(launch_scan(rows, nrows, L.rows_in_ws ? L.row_stride : 0, L.rows_in_ws ? H : nullptr, U, base, L,
                        true, 0, s));
-  DS_TRY(launch_fill(H, out, lo, base, L, s));
+  DS_TRY(launch_fill(H, out, lo, base, L, s, lut));
   return DIALSORT_OK;
 }
 
@@ -409,6 +415,19 @@ dialsort_status dialsort_sort_offset(const uint32_t* keys, uint64_t n, uint32_t 
   DS_TRY(check_common(U, ws, ws_bytes, dialsort_workspace_bytes(n, U, DIALSORT_MODE_SORT)));
   CallScope scope(stream);
   return run_sort(keys, n, U, lo, H, out, ws, DIALSORT_MODE_SORT, stream);
+}
+
+dialsort_status dialsort_sort_lut(const uint32_t* keys, uint64_t n, uint64_t U, const uint32_t* lut, uint32_t* H,
+                                  uint32_t* out, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (U == 0 || U > U_MAX || !H || !lut || (n && (!keys || !out))) return DIALSORT_EINVAL;
+  if (!aligned4(keys) || !aligned4(H) || !aligned4(out) || !aligned4(lut)) return DIALSORT_EINVAL;
+  if (n > N_MAX) return DIALSORT_EOVERFLOW;
+  if (overlap(keys, n * 4, H, U * 4) || overlap(out, n * 4, H, U * 4)) return DIALSORT_EINVAL;
+  if (overlap(lut, U * 4, H, U * 4) || overlap(lut, U * 4, out, n * 4)) return DIALSORT_EINVAL;
+  if (out != keys && overlap(keys, n * 4, out, n * 4)) return DIALSORT_EINVAL;
+  DS_TRY(check_common(U, ws, ws_bytes, dialsort_workspace_bytes(n, U, DIALSORT_MODE_SORT)));
+  CallScope scope(stream);
+  return run_sort(keys, n, U, 0, H, out, ws, DIALSORT_MODE_SORT, stream, lut);
 }
 
 dialsort_status dialsort_sort(const uint32_t* keys, uint64_t n, uint64_t U, uint32_t* H, uint32_t* out, void* ws,

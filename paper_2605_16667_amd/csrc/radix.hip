@@ -35,8 +35,8 @@ using namespace dsh;
 
 namespace {
 
-constexpr int RX_NT = 512;               // threads per pass block
-constexpr int RX_R = 16;                 // keys per thread
+constexpr int RX_NT = 1024;              // threads per pass block
+constexpr int RX_R = 12;                 // keys per thread
 constexpr int RX_TK = RX_NT * RX_R;      // keys per tile
 constexpr int RX_HIST_NT = 512;
 constexpr int RX_HIST_UNROLL = 8;

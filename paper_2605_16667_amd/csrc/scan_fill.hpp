@@ -273,9 +273,11 @@ struct WaveFillSmem {
   uint32_t flag[NFW];
 };
 
-template <int CL2, bool OALIGNED>
+// LUT: bin k's value is lut[k] (a table phi^-1 of Sec. 3.4) instead of lo + k.
+template <int CL2, bool OALIGNED, bool LUT = false>
 __device__ __forceinline__ void wave_fill_item(WaveFillSmem<CL2>& S, const uint32_t* __restrict__ H,
-                                               uint32_t* __restrict__ out, const FillItem& I, uint32_t lo = 0) {
+                                               uint32_t* __restrict__ out, const FillItem& I, uint32_t lo = 0,
+                                               const uint32_t* __restrict__ lut = nullptr) {
   constexpr uint32_t C = 1u << CL2;
   constexpr uint32_t NFW = C / 32;
   static_assert(NFW <= (uint32_t)WAVE, "one flag word per lane at most");
@@ -337,20 +339,31 @@ __device__ __forceinline__ void wave_fill_item(WaveFillSmem<CL2>& S, const uint3
   // at position p is the last mark at or before p in the segment, else the
   // segment's carried key
   const uint32_t nq = (le + 3) >> 2;
-  const uint32_t kf = I.k + lo;  // phi^-1 (Sec. 3.4): bin k holds key lo + k
+  // phi^-1 (Sec. 3.4): bin k holds key lo + k, or lut[k]
+  const uint32_t kf = LUT ? I.k : I.k + lo;
+  const uint32_t* __restrict__ tab = LUT ? lut + I.k : nullptr;
   for (uint32_t q = lane; q < nq; q += WAVE) {
     const uint32_t sg = q >> 3;
     const uint32_t fw = S.flag[sg];
     uint32_t r0, r1, r2, r3;
     if (fw == 0) {
-      r0 = r1 = r2 = r3 = kf + S.val[C + sg];
+      r0 = r1 = r2 = r3 = LUT ? tab[S.val[C + sg]] : kf + S.val[C + sg];
     } else {
       const uint32_t base = sg * 32u + 31u;
       const uint32_t m0 = fw & mk0, m1 = fw & mk1, m2 = fw & mk2, m3 = fw & mk3;
-      r0 = kf + S.val[m0 ? base - __clz(m0) : C + sg];
-      r1 = kf + S.val[m1 ? base - __clz(m1) : C + sg];
-      r2 = kf + S.val[m2 ? base - __clz(m2) : C + sg];
-      r3 = kf + S.val[m3 ? base - __clz(m3) : C + sg];
+      const uint32_t o0 = S.val[m0 ? base - __clz(m0) : C + sg], o1 = S.val[m1 ? base - __clz(m1) : C + sg];
+      const uint32_t o2 = S.val[m2 ? base - __clz(m2) : C + sg], o3 = S.val[m3 ? base - __clz(m3) : C + sg];
+      if (LUT) {
+        r0 = tab[o0];
+        r1 = tab[o1];
+        r2 = tab[o2];
+        r3 = tab[o3];
+      } else {
+        r0 = kf + o0;
+        r1 = kf + o1;
+        r2 = kf + o2;
+        r3 = kf + o3;
+      }
     }
     const uint32_t i0 = q << 2;
     if (OALIGNED && i0 >= lb && i0 + 4 <= le) {
@@ -366,10 +379,10 @@ __device__ __forceinline__ void wave_fill_item(WaveFillSmem<CL2>& S, const uint3
 
 // Persistent fill over the items appended to ctl->nitems: every wave of every
 // workgroup takes items on its own.
-template <int NT, int CL2, bool OALIGNED>
+template <int NT, int CL2, bool OALIGNED, bool LUT = false>
 __global__ __launch_bounds__(NT) void k_fill(const uint32_t* __restrict__ H, uint32_t* __restrict__ out,
                                              Ctl* ctl, const FillItem* __restrict__ items,
-                                             uint32_t item_cap, uint32_t lo) {
+                                             uint32_t item_cap, uint32_t lo, const uint32_t* __restrict__ lut) {
   constexpr uint32_t NW = NT / WAVE;
   __shared__ WaveFillSmem<CL2> S[NW];
   const uint32_t w = threadIdx.x / WAVE;
@@ -383,7 +396,7 @@ __global__ __launch_bounds__(NT) void k_fill(const uint32_t* __restrict__ H, uin
       if (lane_id() == 0) atomicOr(&ctl->status, ST_INT_ITEM);
       continue;
     }
-    wave_fill_item<CL2, OALIGNED>(S[w], H, out, I, lo);
+    wave_fill_item<CL2, OALIGNED, LUT>(S[w], H, out, I, lo, lut);
   }
 }
 

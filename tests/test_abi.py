@@ -63,6 +63,18 @@ def test_host_argument_checks():
     # reconstruct: out_cap at or beyond 2^62, overlap with H
     assert lib.dialsort_reconstruct(FAKE, 8, FAKE + 4096, 1 << 62, FAKE, big, None) == ds.DIALSORT_EINVAL
     assert lib.dialsort_reconstruct(FAKE, 8, FAKE + 16, 4, FAKE + 8192, big, None) == ds.DIALSORT_EINVAL
+    # lookup-table sort: null or misaligned table, table overlapping H or out
+    assert lib.dialsort_sort_lut(FAKE, 4, 8, None, FAKE + 4096, FAKE + 8192, FAKE, big, None) == ds.DIALSORT_EINVAL
+    assert lib.dialsort_sort_lut(FAKE, 4, 8, FAKE + 2, FAKE + 4096, FAKE + 8192, FAKE, big, None) == ds.DIALSORT_EINVAL
+    assert lib.dialsort_sort_lut(FAKE, 4, 8, FAKE + 4100, FAKE + 4096, FAKE + 8192, FAKE, big,
+                                 None) == ds.DIALSORT_EINVAL
+    assert lib.dialsort_sort_lut(FAKE, 4, 8, FAKE + 8200, FAKE + 4096, FAKE + 8192, FAKE, big,
+                                 None) == ds.DIALSORT_EINVAL
+    # key range: null result, keys missing, result overlapping the keys, n too large
+    assert lib.dialsort_key_range(FAKE, 4, 0, None, None) == ds.DIALSORT_EINVAL
+    assert lib.dialsort_key_range(None, 4, 0, FAKE, None) == ds.DIALSORT_EINVAL
+    assert lib.dialsort_key_range(FAKE, 4, 0, FAKE + 8, None) == ds.DIALSORT_EINVAL
+    assert lib.dialsort_key_range(FAKE, 1 << 32, 0, FAKE + 4096, None) == ds.DIALSORT_EOVERFLOW
 
 
 def test_batched_argument_checks():

@@ -336,3 +336,59 @@ def test_radix_is_numpy_sort(n):
     d = (0x11220033 | (rng.integers(0, 256, n).astype(np.uint32) << 8)).astype(np.uint32)
     st, out = oracle.sort_radix(d)
     assert np.array_equal(out, np.sort(d))
+
+
+def test_lut_sort_orders_a_non_integer_domain():
+    """phi^-1 as a table (Sec. 3.4): weekday names indexed by their position in
+    the week come out in week order, whatever order the input holds them in;
+    with an increasing table the output is the comparison sort of the decoded
+    values; with any table it is the table read at the sorted indices."""
+    week = ["Mon", "Tue", "Wed", "Thu", "Fri", "Sat", "Sun"]
+    codes = {name: i for i, name in enumerate(week)}
+    rng = np.random.default_rng(17)
+    days = [week[i] for i in rng.integers(0, 7, 200)]
+    # the table decodes an index into a token of the name (its bytes as an int)
+    token = np.array([int.from_bytes(d.encode(), "little") for d in week], dtype=np.uint32)
+    name_of = {int(t): d for t, d in zip(token, week)}
+    keys = np.array([codes[d] for d in days], dtype=np.uint32)
+    st, H, out = oracle.sort_lut(keys, 7, token)
+    assert st == oracle.OK
+    assert [name_of[int(t)] for t in out] == sorted(days, key=week.index)
+    assert H.tolist() == [days.count(d) for d in week]
+    # an increasing table: the order of the decoded values themselves
+    U = 5000
+    inc = np.cumsum(rng.integers(1, 1000, U)).astype(np.uint32)
+    idx = rng.integers(0, U, 20000).astype(np.uint32)
+    st, _, out = oracle.sort_lut(idx, U, inc)
+    assert st == oracle.OK and np.array_equal(out, np.sort(inc[idx]))
+    # any table (here a permutation): the table at the sorted indices
+    perm = rng.permutation(U).astype(np.uint32)
+    st, _, out = oracle.sort_lut(idx, U, perm)
+    assert st == oracle.OK and np.array_equal(out, perm[np.sort(idx)])
+    st, _, _ = oracle.sort_lut(np.array([U], dtype=np.uint32), U, perm)
+    assert st == oracle.ERANGE
+    st, _, out = oracle.sort_lut(np.array([], dtype=np.uint32), U, perm)
+    assert st == oracle.OK and out.size == 0
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 1000, 100_003])
+def test_key_range_is_numpy_min_max(n):
+    """The key range that fixes the smallest offset map (Sec. 3.4), unsigned
+    and signed, against numpy's min and max; the empty input leaves min above
+    max."""
+    rng = np.random.default_rng(n + 29)
+    u = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+    st, lo, hi = oracle.key_range(u)
+    assert st == oracle.OK
+    if n:
+        assert (lo, hi) == (int(u.min()), int(u.max()))
+        s = u.view(np.int32)
+        st, lo, hi = oracle.key_range(u, is_signed=True)
+        assert (np.uint32(lo).view(np.int32), np.uint32(hi).view(np.int32)) == (s.min(), s.max())
+    else:
+        assert (lo, hi) == (0xFFFFFFFF, 0)
+        assert oracle.key_range(u, is_signed=True)[1:] == (0x7FFFFFFF, 0x80000000)
+    # the extremes themselves
+    ext = np.array([0x80000000, 0x7FFFFFFF, 0, 0xFFFFFFFF], dtype=np.uint32)
+    assert oracle.key_range(ext)[1:] == (0, 0xFFFFFFFF)
+    assert oracle.key_range(ext, is_signed=True)[1:] == (0x80000000, 0x7FFFFFFF)
