@@ -100,15 +100,26 @@ def algo_bytes(name: str, n: int, U: int, mode: str) -> int:
     return 0
 
 
-def source_digest() -> str:
-    """sha256 over the library's kernel and host sources (names and contents)."""
+def source_digest(top: str = "dialsort.hip") -> str:
+    """sha256 over the sources the single-array path's kernels are built from:
+    `top` and every file it includes, transitively (names and contents)."""
     import hashlib
+    import re
 
     d = os.path.join(ROOT, "paper_2605_16667_amd", "csrc")
+    inc = re.compile(r'^\s*#\s*include\s+"([^"]+)"', re.M)
+    seen, todo = set(), [os.path.normpath(os.path.join(d, top))]
+    while todo:
+        f = todo.pop()
+        if f in seen or not os.path.exists(f):
+            continue
+        seen.add(f)
+        with open(f) as fh:
+            todo += [os.path.normpath(os.path.join(os.path.dirname(f), m)) for m in inc.findall(fh.read())]
     h = hashlib.sha256()
-    for f in sorted(os.listdir(d)):
-        h.update(f.encode())
-        with open(os.path.join(d, f), "rb") as fh:
+    for f in sorted(seen):
+        h.update(os.path.relpath(f, ROOT).encode())
+        with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
