@@ -71,12 +71,26 @@ __global__ __launch_bounds__(PF_NT) void k_prefix(const uint32_t* __restrict__ H
   __syncthreads();
   const uint64_t t = s_tile;
   const uint64_t base = t * (uint64_t)TB;
-  // striped loads (coalesced), then thread tid owns bins base + tid*VPT + j
+  // striped loads (coalesced), then thread tid owns bins base + tid*VPT + j;
+  // a whole tile loads without bounds tests, so that all its loads are in
+  // flight together
+  const bool whole = base + TB <= U;
+  if (whole) {
+    uint32_t h[PF_VPT];
 #pragma unroll
-  for (int j = 0; j < PF_VPT; ++j) {
-    const uint64_t k = base + (uint64_t)j * PF_NT + tid;
-    const uint32_t p = j * PF_NT + tid;
-    tr[p + (p >> 5)] = k < U ? H[k] : 0u;
+    for (int j = 0; j < PF_VPT; ++j) h[j] = H[base + (uint64_t)j * PF_NT + tid];
+#pragma unroll
+    for (int j = 0; j < PF_VPT; ++j) {
+      const uint32_t p = j * PF_NT + tid;
+      tr[p + (p >> 5)] = h[j];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < PF_VPT; ++j) {
+      const uint64_t k = base + (uint64_t)j * PF_NT + tid;
+      const uint32_t p = j * PF_NT + tid;
+      tr[p + (p >> 5)] = k < U ? H[k] : 0u;
+    }
   }
   __syncthreads();
   uint32_t v[PF_VPT];
@@ -116,7 +130,7 @@ __global__ __launch_bounds__(PF_NT) void k_prefix(const uint32_t* __restrict__ H
   for (int j = 0; j < PF_VPT; ++j) {
     const uint64_t k = base + (uint64_t)j * PF_NT + tid;
     const uint32_t p = j * PF_NT + tid;
-    if (k < U) P[k] = out64[p + (p >> 5)];
+    if (whole || k < U) P[k] = out64[p + (p >> 5)];
   }
   // the tile holding bin U - 1 also writes P[U], the total
   if (base <= U - 1 && U - 1 < base + TB && tid == 0) P[U] = sat_add(s_prefix, agg_sat);
