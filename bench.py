@@ -624,12 +624,10 @@ def run_radix_workload(ds, K, W, sizes=(10**7, 10**8)):
     return res
 
 
-def cpu_baseline(keys_dev, U, budget_s=12.0, max_runs=5):
+def cpu_baseline(kh, U, budget_s=12.0, max_runs=5):
     """The oracle as it stands, on this host, on the same keys (sequential C)."""
     import oracle
-    import workloads as w
 
-    kh = w.as_u32(keys_dev)
     n = kh.size
     times = []
     t_start = time.perf_counter()
@@ -642,6 +640,46 @@ def cpu_baseline(keys_dev, U, budget_s=12.0, max_runs=5):
     return {"value": n / best, "unit": "keys/s", "cores": 1, "kind": "oracle",
             "sample": f"oracle.sort on the full workload (n={n}, U={U}), best of {len(times)} runs",
             "best_s": best}
+
+
+def cpu_parallel_baseline(kh, U, warmup=1, runs=5):
+    """The CPU-parallel baseline (private per-thread histograms, merge, projection
+    by bin ranges) on all the host threads this process may use, on the same
+    keys: best and median of `runs` after `warmup`, verified against the
+    GPU-independent oracle's histogram."""
+    import platform
+
+    import numpy as np
+
+    import oracle
+    from oracle import cpu_parallel
+
+    T = cpu_parallel.default_threads()
+    times = []
+    for i in range(warmup + runs):
+        t = time.perf_counter()
+        st, H, out = cpu_parallel.sort(kh, U, T)
+        dt = time.perf_counter() - t
+        assert st == 0
+        if i >= warmup:
+            times.append(dt)
+    st, H_ref = oracle.histogram(kh, U)
+    ok = bool(st == oracle.OK and np.array_equal(H, H_ref) and out.size == kh.size
+              and bool(np.all(out[1:] >= out[:-1])))
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    best = min(times)
+    return {"value": kh.size / best, "unit": "keys/s", "cores": T, "nproc": os.cpu_count(), "cpu_model": model,
+            "kind": "cpu-parallel baseline (oracle/cpu_parallel.c)", "best_s": best,
+            "median_s": statistics.median(times), "runs": runs, "verified": ok,
+            "sample": f"full workload (n={kh.size}, U={U}), histogram and sorted output"}
 
 
 def main():
@@ -701,10 +739,15 @@ def main():
     if "query" in todo:
         log("queries on the large workload's histogram")
         extra["queries"] = run_query_workload(ds, keys, U, max(K // 2, 5), 2)
-    cpu = None
+    cpu = cpu_par = None
     if not args.no_cpu:
+        kh = w.as_u32(keys)
         log("cpu baseline (oracle)")
-        cpu = cpu_baseline(keys, U)
+        cpu = cpu_baseline(kh, U)
+        log("cpu-parallel baseline")
+        cpu_par = cpu_parallel_baseline(kh, U)
+        log(f"cpu-parallel: {cpu_par['value'] / 1e6:.0f} M keys/s on {cpu_par['cores']} threads")
+        del kh
     del keys
     torch.cuda.empty_cache()
 
@@ -768,6 +811,7 @@ def main():
                    "keys": "uniform i.i.d. on [0, 2^24)", "mode": "sort"},
         "roofline": main_res["roofline"],
         "cpu_baseline": cpu,
+        "cpu_parallel": cpu_par,
         "path_roofline": main_res["path_roofline"],
         "stats": {"best_ms": main_res["best_ms"], "median_ms": main_res["median_ms"], "cv": main_res["cv"]},
         "verified": main_res["verified"],

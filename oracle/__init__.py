@@ -36,11 +36,15 @@ _lib: Optional[ctypes.CDLL] = None
 
 
 def build() -> str:
-    """Compile the C oracle into oracle/liboracle.so (plain gcc, -O2)."""
+    """Compile the C oracle into oracle/liboracle.so (plain gcc, -O2), and the
+    CPU-parallel benchmark baseline beside it (oracle/cpu_parallel.py)."""
     tmp = _LIB_PATH + ".tmp"
     subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-fPIC", "-shared",
                            _SRC, "-o", tmp])
     os.replace(tmp, _LIB_PATH)
+    from . import cpu_parallel
+
+    cpu_parallel.build()
     return _LIB_PATH
 
 
