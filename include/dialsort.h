@@ -404,13 +404,17 @@ dialsort_status dialsort_query_select(const uint64_t *P, uint64_t U, const uint6
 /* ---- DialSort-Radix: the whole 32-bit range ----------------------------------
  *
  * LSD, base 256, four passes, no order comparison (Sec. 8, "Full int32 range",
- * Table "tab:radix"): each pass counts one 8-bit digit per tile (Eq. (1)),
- * takes the running count over (digit, tile) as positions (Eq. (2)), and
- * places every key stably within its digit.  out[0 .. n) = the keys in
- * ascending order: as uint32, or, with is_signed != 0, as int32 (the sign bit
- * is flipped on the first load and back on the last store, the phi of Sec.
- * 3.4).  No histogram over the 2^32 keys is formed.  out may equal keys;
- * any other overlap is EINVAL.  n > 2^32 - 1 is EOVERFLOW. */
+ * Table "tab:radix").  One read of the keys counts all four 8-bit digits
+ * (Eq. (1) per digit); the running count of each digit histogram gives where
+ * each digit starts (Eq. (2)); each pass then places every key stably at its
+ * digit's start plus the count of that digit among the keys before it.
+ * out[0 .. n) = the keys in ascending order: as uint32, or, with
+ * is_signed != 0, as int32 (the sign bit is flipped on the first load and back
+ * on the last store, the phi of Sec. 3.4).  No histogram over the 2^32 keys is
+ * formed, so no key is out of range.  out may equal keys; any other overlap is
+ * EINVAL.  n > 2^32 - 1 is EOVERFLOW.  The workspace (device memory, at least
+ * dialsort_radix_workspace_bytes(n) bytes, contents not preserved) holds a
+ * second copy of the keys and the per-tile digit counts. */
 size_t dialsort_radix_workspace_bytes(uint64_t n);
 dialsort_status dialsort_sort_radix(const uint32_t *keys, uint64_t n, int is_signed, uint32_t *out, void *ws,
                                     size_t ws_bytes, hipStream_t stream);
