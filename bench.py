@@ -102,7 +102,8 @@ def algo_bytes(name: str, n: int, U: int, mode: str) -> int:
 
 def source_digest(top: str = "dialsort.hip") -> str:
     """sha256 over the sources the single-array path's kernels are built from:
-    `top` and every file it includes, transitively (names and contents)."""
+    `top` and every file under csrc/ it includes, transitively (names and
+    contents).  The public header, which only declares the C ABI, is left out."""
     import hashlib
     import re
 
@@ -111,7 +112,7 @@ def source_digest(top: str = "dialsort.hip") -> str:
     seen, todo = set(), [os.path.normpath(os.path.join(d, top))]
     while todo:
         f = todo.pop()
-        if f in seen or not os.path.exists(f):
+        if f in seen or not os.path.exists(f) or os.path.dirname(f) != d:
             continue
         seen.add(f)
         with open(f) as fh:
