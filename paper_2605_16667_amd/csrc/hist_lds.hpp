@@ -122,21 +122,47 @@ __device__ __forceinline__ void hist_slab(SM& S, const uint32_t* __restrict__ ke
     for (int u = 0; u < UNR; ++u) nv[u] = load_group<ALIGNED>(keys, g0 + ((uint64_t)u * NT + tid) * 4, end, v[u], lo);
     uint32_t cc[UNR][4];
     uint32_t old[UNR][4];
+    // a step whose groups are all whole and whose keys are all in range (every
+    // step but the last and those of a faulty input) needs no per-key masks
+    uint32_t vmax = 0;
 #pragma unroll
-    for (int u = 0; u < UNR; ++u) {
+    for (int u = 0; u < UNR; ++u)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const bool valid = (uint32_t)i < nv[u];
-        const bool ok = valid && v[u][i] <= umax;
-        bad |= valid && !ok;
-        WaveGroups g;
-        const uint32_t c = wave_merge_count<AGG>(v[u][i], ok, st, g);
-        cc[u][i] = c;
-        old[u][i] = 0;
-        if constexpr (!PACKED) {
-          if (c) atomicAdd(&S.s[v[u][i]], c);
-        } else {
-          if (c) old[u][i] = atomicAdd(&S.s[v[u][i] >> 1], c << ((v[u][i] & 1u) << 4));
+      for (int i = 0; i < 4; ++i) vmax = vmax > v[u][i] ? vmax : v[u][i];
+    const bool clean = g0 + (uint64_t)NT * 4 * UNR <= end && !__any(vmax > umax);
+    if (clean) {
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          WaveGroups g;
+          const uint32_t c = wave_merge_count<AGG>(v[u][i], true, st, g);
+          cc[u][i] = c;
+          old[u][i] = 0;
+          if constexpr (!PACKED) {
+            if (c) atomicAdd(&S.s[v[u][i]], c);
+          } else {
+            if (c) old[u][i] = atomicAdd(&S.s[v[u][i] >> 1], c << ((v[u][i] & 1u) << 4));
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const bool valid = (uint32_t)i < nv[u];
+          const bool ok = valid && v[u][i] <= umax;
+          bad |= valid && !ok;
+          WaveGroups g;
+          const uint32_t c = wave_merge_count<AGG>(v[u][i], ok, st, g);
+          cc[u][i] = c;
+          old[u][i] = 0;
+          if constexpr (!PACKED) {
+            if (c) atomicAdd(&S.s[v[u][i]], c);
+          } else {
+            if (c) old[u][i] = atomicAdd(&S.s[v[u][i] >> 1], c << ((v[u][i] & 1u) << 4));
+          }
         }
       }
     }
