@@ -19,6 +19,8 @@ fields of the same line:
            loads, against serial plain sorts; p50/p99 latency and keys/s
   query    queries on the large workload's histogram: the running count over
            2^24 bins, and 2^20 frequency/presence/range-count/select queries
+  windows  64 tumbling windows of 2^20 keys (U = 2^16): ingestion of one window
+           overlapped with the projection of the previous one, vs one stream
   radix    DialSort-Radix over the whole signed int32 range, n = 1e7 and 1e8
 The roofline object is for the kernel that takes the most time per step,
 measured with HIP events recorded on the launch stream around every kernel of
@@ -638,6 +640,48 @@ def run_radix_workload(ds, K, W, sizes=(10**7, 10**8)):
     return res
 
 
+def run_windows_workload(ds, K, W, count=64, wn=1 << 20, U=1 << 16):
+    """A key stream sorted in tumbling windows (count windows of wn uniform
+    keys, U bins): the ingestion of each window overlaps the projection of the
+    previous one on a second stream, against the same calls on one stream."""
+    import torch
+
+    import workloads as w
+
+    keys = w.uniform(count * wn, U, w.BASE_SEED + 70, "cuda")
+    H = torch.empty(2 * U, dtype=torch.int32, device="cuda")
+    out = torch.empty_like(keys)
+    ws = ds.workspace(ds.dialsort_windows_workspace_bytes(wn, U))
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+
+    def timed(two):
+        ing, proj = s1, (s2 if two else s1)
+        times = []
+        for it in range(W + K):
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(proj)
+            ing.wait_event(e0)
+            ds.check(ds.dialsort_sort_windows(keys, wn, count, U, H, out, ws, ing, proj))
+            e1.record(proj)
+            torch.cuda.synchronize()
+            if it >= W:
+                times.append(e0.elapsed_time(e1))
+        ok = ds.dialsort_status_sync(ws, proj) == ds.DIALSORT_OK
+        last = keys[(count - 1) * wn:]
+        ok = ok and verify_sort(last, U, H[((count - 1) % 2) * U:((count - 1) % 2 + 1) * U], out[(count - 1) * wn:])
+        return {"ms": statistics.median(times), "best_ms": min(times),
+                "keys_per_s": count * wn / (statistics.median(times) * 1e-3), "verified": bool(ok)}
+
+    res = {"workload": f"{count} tumbling windows of {wn} uniform keys, U = {U}",
+           "one_stream": timed(False), "two_streams": timed(True)}
+    res["speedup"] = res["one_stream"]["ms"] / res["two_streams"]["ms"]
+    del keys, H, out, ws
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(kh, U, budget_s=12.0, max_runs=5):
     """The oracle as it stands, on this host, on the same keys (sequential C)."""
     import oracle
@@ -701,7 +745,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workloads", default="large,hist,query,plain,skewed,radix,batch,serve")
+    ap.add_argument("--workloads", default="large,hist,query,plain,skewed,windows,radix,batch,serve")
     ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--serve-loads", default="0.7,1.5,3.0",
                     help="arrival rates, as multiples of 1 / (mean serial service time)")
@@ -804,6 +848,11 @@ def main():
         del k3u
         torch.cuda.empty_cache()
 
+    if "windows" in todo:
+        log("windows: tumbling windows, ingestion overlapped with projection")
+        extra["windows"] = run_windows_workload(ds, max(K // 2, 5), 2)
+        log(f"windows: one stream {extra['windows']['one_stream']['ms']:.3f} ms, "
+            f"two streams {extra['windows']['two_streams']['ms']:.3f} ms")
     if "radix" in todo:
         log("radix: whole signed int32 range")
         extra["radix"] = run_radix_workload(ds, max(K // 2, 5), 2)

@@ -127,6 +127,26 @@ dialsort_status dialsort_key_range(const uint32_t *keys, uint64_t n, int is_sign
 dialsort_status dialsort_histogram_accumulate(const uint32_t *keys, uint64_t n, uint64_t U, uint32_t *H,
                                               void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* A stream of keys sorted in tumbling windows, with ingestion and projection
+ * overlapped (the streaming remark after the complexity theorem of Sec. 4):
+ * window w is keys[w*window_n .. (w+1)*window_n), w < count; its histogram
+ * (Eq. (1)) goes to H + (w mod 2)*U and its ordered projection (Eq. (2)) to
+ * out + w*window_n.  Ingestions run in order on `ingest` and projections on
+ * `project`: window w + 1 is ingested while window w is projected, and a
+ * histogram is reused only after its previous window's projection.  H holds
+ * 2U counters; on completion it holds the histograms of the last two windows.
+ * keys, out and H must not overlap (out == keys is EINVAL here).  Passing the
+ * same stream twice gives the serial order.  Work already on `ingest` or
+ * `project` is not ordered against the other stream: order it with an event if
+ * it produces the keys.  Completion of everything is ordered before later work
+ * on `project`.  The workspace (dialsort_windows_workspace_bytes) holds the
+ * combined device status read by dialsort_status_sync(ws, project): a key >= U
+ * in any window is ERANGE. */
+size_t dialsort_windows_workspace_bytes(uint64_t window_n, uint64_t U);
+dialsort_status dialsort_sort_windows(const uint32_t *keys, uint64_t window_n, uint32_t count, uint64_t U,
+                                      uint32_t *H, uint32_t *out, void *ws, size_t ws_bytes, hipStream_t ingest,
+                                      hipStream_t project);
+
 /* Ordered projection only (Sec. 3.3, Eq. (2)): writes k exactly H[k] times for
  * k = 0 .. U-1 into out, in ascending k, stopping after out_cap elements.  The
  * number of elements is min(sum H, out_cap); sum H > out_cap is reported as

@@ -73,6 +73,8 @@ def _load() -> ctypes.CDLL:
         "dialsort_sort_offset": (st, [p, u64, ctypes.c_uint32, u64, p, p, p, sz, p]),
         "dialsort_sort_lut": (st, [p, u64, u64, p, p, p, p, sz, p]),
         "dialsort_key_range": (st, [p, u64, ctypes.c_int, p, p]),
+        "dialsort_windows_workspace_bytes": (sz, [u64, u64]),
+        "dialsort_sort_windows": (st, [p, u64, ctypes.c_uint32, u64, p, p, p, sz, p, p]),
         "dialsort_reconstruct": (st, [p, u64, p, u64, p, sz, p]),
         "dialsort_sort": (st, [p, u64, u64, p, p, p, sz, p]),
         "dialsort_batched_workspace_bytes": (sz, [ctypes.POINTER(dialsort_desc), ctypes.c_uint32]),
@@ -121,6 +123,7 @@ def _load() -> ctypes.CDLL:
 _lib = _load()
 EXPORTED = ("dialsort_workspace_bytes", "dialsort_histogram", "dialsort_histogram_accumulate",
             "dialsort_histogram_offset", "dialsort_sort_offset", "dialsort_sort_lut", "dialsort_key_range",
+            "dialsort_windows_workspace_bytes", "dialsort_sort_windows",
             "dialsort_reconstruct", "dialsort_sort",
             "dialsort_batched_workspace_bytes", "dialsort_sort_batched", "dialsort_sort_each",
             "dialsort_batch_prepare", "dialsort_batch_launch", "dialsort_batch_autotune",
@@ -204,6 +207,20 @@ def dialsort_sort_lut(keys: torch.Tensor, U: int, lut: torch.Tensor, H: torch.Te
         return DIALSORT_EINVAL
     return _lib.dialsort_sort_lut(_ptr(keys), keys.numel(), U, _ptr(lut), _ptr(H), _ptr(out), _ptr(ws), ws.numel(),
                                   _stream(stream))
+
+
+def dialsort_windows_workspace_bytes(window_n: int, U: int) -> int:
+    return _lib.dialsort_windows_workspace_bytes(window_n, U)
+
+
+def dialsort_sort_windows(keys: torch.Tensor, window_n: int, count: int, U: int, H: torch.Tensor, out: torch.Tensor,
+                          ws: torch.Tensor, ingest_stream=None, project_stream=None) -> int:
+    """Tumbling windows of window_n keys: window w's ingestion on ingest_stream
+    overlaps window w - 1's projection on project_stream.  H holds 2U counters."""
+    if keys.numel() < window_n * count or out.numel() < window_n * count or H.numel() < 2 * U:
+        return DIALSORT_EINVAL
+    return _lib.dialsort_sort_windows(_ptr(keys), window_n, count, U, _ptr(H), _ptr(out), _ptr(ws), ws.numel(),
+                                      _stream(ingest_stream), _stream(project_stream))
 
 
 def dialsort_key_range(keys: torch.Tensor, minmax: torch.Tensor, is_signed: bool = False, stream=None) -> int:

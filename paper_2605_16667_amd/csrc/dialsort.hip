@@ -458,6 +458,76 @@ dialsort_status dialsort_reconstruct(const uint32_t* H, uint64_t U, uint32_t* ou
   return DIALSORT_OK;
 }
 
+// Tumbling windows: window w is ingested on `ingest` into H + (w mod 2) U and
+// projected on `project` while window w + 1 is ingested into the other
+// histogram.  Each histogram has its own sub-workspace, used in turn by its
+// window's ingestion and projection; the combined status lives at the front.
+static size_t windows_sub_bytes(uint64_t wn, uint64_t U) {
+  return align_up(std::max(plan(wn, U, DIALSORT_MODE_HISTOGRAM).bytes, plan(wn, U, DIALSORT_MODE_RECONSTRUCT).bytes),
+                  ALIGN);
+}
+
+size_t dialsort_windows_workspace_bytes(uint64_t window_n, uint64_t U) {
+  if (U == 0 || U > U_MAX || window_n > N_MAX) return 0;
+  return 2 * ALIGN + 2 * windows_sub_bytes(window_n, U);
+}
+
+dialsort_status dialsort_sort_windows(const uint32_t* keys, uint64_t window_n, uint32_t count, uint64_t U,
+                                      uint32_t* H, uint32_t* out, void* ws, size_t ws_bytes, hipStream_t ingest,
+                                      hipStream_t project) {
+  const uint64_t n = window_n * count;
+  if (U == 0 || U > U_MAX || !H || (n && (!keys || !out))) return DIALSORT_EINVAL;
+  if (!aligned4(keys) || !aligned4(H) || !aligned4(out)) return DIALSORT_EINVAL;
+  if (window_n > N_MAX) return DIALSORT_EOVERFLOW;
+  if (overlap(keys, n * 4, H, 2 * U * 4) || overlap(out, n * 4, H, 2 * U * 4)) return DIALSORT_EINVAL;
+  if (overlap(keys, n * 4, out, n * 4)) return DIALSORT_EINVAL;
+  if (!ws || ws_bytes < dialsort_windows_workspace_bytes(window_n, U)) return DIALSORT_EWORKSPACE;
+  char* base = ws_base(ws);
+  const size_t sub_bytes = windows_sub_bytes(window_n, U);
+  char* sub[2] = {base + ALIGN, base + ALIGN + sub_bytes};
+  CallScope scope(project);
+  Layout L0;
+  L0.scan = false;
+  DS_TRY(launch_init(base, L0, nullptr, 0, project));
+  if (count == 0) return DIALSORT_OK;
+  hipEvent_t ev[4] = {};  // ingested[0], ingested[1], projected[0], projected[1]
+  dialsort_status st = DIALSORT_OK;
+  for (int i = 0; i < 4 && st == DIALSORT_OK; ++i) {
+    const hipError_t e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+    if (e != hipSuccess) {
+      g_last_hip_error = (int)e;
+      st = DIALSORT_EHIP;
+    }
+  }
+  const Layout LR = plan(window_n, U, DIALSORT_MODE_RECONSTRUCT);
+  auto run = [&]() -> dialsort_status {
+    for (uint32_t w = 0; w < count; ++w) {
+      const int b = (int)(w & 1u);
+      uint32_t* Hb = H + (uint64_t)b * U;
+      char* sb = sub[b];
+      // window w - 2 has been projected out of this histogram and workspace
+      if (w >= 2) DS_HIP(hipStreamWaitEvent(ingest, ev[2 + b], 0));
+      DS_TRY(run_sort(keys + (uint64_t)w * window_n, window_n, U, 0, Hb, nullptr, sb, DIALSORT_MODE_HISTOGRAM,
+                      ingest));
+      DS_HIP(hipEventRecord(ev[b], ingest));
+      DS_HIP(hipStreamWaitEvent(project, ev[b], 0));
+      // the ingestion's status, before the projection clears the workspace
+      DS_LAUNCH(k_or_status, dim3(1), dim3(64), project, (Ctl*)base, (const Ctl*)sb);
+      DS_TRY(launch_init(sb, LR, nullptr, 0, project));
+      DS_TRY(launch_scan(Hb, 1, 0, nullptr, U, sb, LR, true, 1, project));
+      DS_TRY(launch_fill(Hb, out + (uint64_t)w * window_n, 0, sb, LR, project));
+      DS_LAUNCH(k_or_status, dim3(1), dim3(64), project, (Ctl*)base, (const Ctl*)sb);
+      DS_HIP(hipEventRecord(ev[2 + b], project));
+    }
+    // the last ingestion is also ordered before everything that follows on project
+    return DIALSORT_OK;
+  };
+  if (st == DIALSORT_OK) st = run();
+  for (int i = 0; i < 4; ++i)
+    if (ev[i]) (void)hipEventDestroy(ev[i]);
+  return st;
+}
+
 dialsort_status dialsort_set_launch_events(hipEvent_t* events, uint32_t cap, uint32_t* count) {
   if (events && cap < 2) return DIALSORT_EINVAL;
   g_log.ev = events;

@@ -70,6 +70,14 @@ def test_host_argument_checks():
                                  None) == ds.DIALSORT_EINVAL
     assert lib.dialsort_sort_lut(FAKE, 4, 8, FAKE + 8200, FAKE + 4096, FAKE + 8192, FAKE, big,
                                  None) == ds.DIALSORT_EINVAL
+    # tumbling windows: out overlapping keys, H overlapping out, window past 2^32 - 1 keys
+    assert lib.dialsort_sort_windows(FAKE, 4, 2, 8, FAKE + 8192, FAKE + 16, FAKE + 16384, big, None,
+                                     None) == ds.DIALSORT_EINVAL
+    assert lib.dialsort_sort_windows(FAKE, 4, 2, 8, FAKE + 4100, FAKE + 4096, FAKE + 16384, big, None,
+                                     None) == ds.DIALSORT_EINVAL
+    assert lib.dialsort_sort_windows(FAKE, 1 << 32, 1, 8, FAKE + 8192, FAKE + 4096, FAKE + 16384, big, None,
+                                     None) == ds.DIALSORT_EOVERFLOW
+    assert lib.dialsort_windows_workspace_bytes(1 << 32, 8) == 0
     # key range: null result, keys missing, result overlapping the keys, n too large
     assert lib.dialsort_key_range(FAKE, 4, 0, None, None) == ds.DIALSORT_EINVAL
     assert lib.dialsort_key_range(None, 4, 0, FAKE, None) == ds.DIALSORT_EINVAL
