@@ -19,6 +19,8 @@ fields of the same line:
            loads, against serial plain sorts; p50/p99 latency and keys/s
   query    queries on the large workload's histogram: the running count over
            2^24 bins, and 2^20 frequency/presence/range-count/select queries
+  transforms  the key transforms (offset, key range, lookup table) and
+           ingestion in ten pieces at n = 1e8, U = 2^24, beside the plain forms
   windows  64 tumbling windows of 2^20 keys (U = 2^16): ingestion of one window
            overlapped with the projection of the previous one, vs one stream
   radix    DialSort-Radix over the whole signed int32 range, n = 1e7 and 1e8
@@ -640,6 +642,76 @@ def run_radix_workload(ds, K, W, sizes=(10**7, 10**8)):
     return res
 
 
+def _time(call, K, W):
+    import torch
+
+    for _ in range(W):
+        call()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(K):
+        call()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / K
+
+
+def run_transform_workload(ds, K, W, n=10**8, U=1 << 24, pieces=10):
+    """The key transforms phi (Sec. 3.4) and streaming ingestion at the large
+    workload's size, beside the plain sort of the same shape: signed keys in a
+    2^24 range sorted through the offset map, the key range that picks it,
+    indices sorted through a lookup table phi^-1, and the same n keys ingested
+    into one resident H in `pieces` pieces."""
+    import torch
+
+    import workloads as w
+
+    res = {"n": n, "U": U}
+    keys = w.uniform(n, U, w.BASE_SEED + 80, "cuda")
+    H = torch.empty(U, dtype=torch.int32, device="cuda")
+    out = torch.empty_like(keys)
+    ws = ds.workspace(ds.dialsort_workspace_bytes(n, U, ds.DIALSORT_MODE_SORT))
+    lo = -(1 << 23)
+    skeys = keys + lo  # signed keys in [-2^23, 2^23)
+    ms = _time(lambda: ds.check(ds.dialsort_sort_offset(skeys, lo, U, H, out, ws)), K, W)
+    ok = ds.dialsort_status_sync(ws) == ds.DIALSORT_OK and bool((out[1:] >= out[:-1]).all()) and \
+        torch.equal(H, torch.bincount(keys, minlength=U).to(torch.int32))
+    res["offset_sort"] = {"ms": ms, "keys_per_s": n / (ms * 1e-3), "verified": bool(ok)}
+    mm = torch.empty(2, dtype=torch.int32, device="cuda")
+    ms = _time(lambda: ds.check(ds.dialsort_key_range(skeys, mm, True)), K, W)
+    ok = [int(v) for v in mm.cpu()] == [int(skeys.min()), int(skeys.max())]
+    res["key_range"] = {"ms": ms, "GBps": 4 * n / (ms * 1e-3) / 1e9, "verified": bool(ok)}
+    del skeys
+    lut = (torch.arange(U, dtype=torch.int64, device="cuda") * 7 + 3).to(torch.int32)  # increasing
+    ms = _time(lambda: ds.check(ds.dialsort_sort_lut(keys, U, lut, H, out, ws)), K, W)
+    ok = ds.dialsort_status_sync(ws) == ds.DIALSORT_OK and bool((out[1:] >= out[:-1]).all()) and \
+        int(out[0]) == int(lut[int(keys.min())]) and int(out[-1]) == int(lut[int(keys.max())])
+    res["lut_sort"] = {"ms": ms, "keys_per_s": n / (ms * 1e-3), "verified": bool(ok)}
+    ms = _time(lambda: ds.check(ds.dialsort_sort(keys, U, H, out, ws)), K, W)
+    res["plain_sort_same_shape"] = {"ms": ms, "keys_per_s": n / (ms * 1e-3)}
+    del lut, out, ws
+    pn = n // pieces
+    aws = ds.workspace(ds.dialsort_workspace_bytes(pn, U, ds.DIALSORT_MODE_ACCUMULATE))
+
+    def stream():
+        H.zero_()
+        for i in range(pieces):
+            ds.check(ds.dialsort_histogram_accumulate(keys[i * pn:(i + 1) * pn], U, H, aws))
+
+    ms = _time(stream, K, W)
+    ok = ds.dialsort_status_sync(aws) == ds.DIALSORT_OK and \
+        torch.equal(H, torch.bincount(keys[: pieces * pn], minlength=U).to(torch.int32))
+    res["accumulate"] = {"pieces": pieces, "ms": ms, "keys_per_s": pieces * pn / (ms * 1e-3), "verified": bool(ok)}
+    hws = ds.workspace(ds.dialsort_workspace_bytes(n, U, ds.DIALSORT_MODE_HISTOGRAM))
+    ms = _time(lambda: ds.check(ds.dialsort_histogram(keys, U, H, hws)), K, W)
+    res["histogram_same_shape"] = {"ms": ms, "keys_per_s": n / (ms * 1e-3)}
+    del keys, H, aws, hws
+    torch.cuda.empty_cache()
+    return res
+
+
 def run_windows_workload(ds, K, W, count=64, wn=1 << 20, U=1 << 16):
     """A key stream sorted in tumbling windows (count windows of wn uniform
     keys, U bins): the ingestion of each window overlaps the projection of the
@@ -745,7 +817,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workloads", default="large,hist,query,plain,skewed,windows,radix,batch,serve")
+    ap.add_argument("--workloads", default="large,hist,query,plain,skewed,transforms,windows,radix,batch,serve")
     ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--serve-loads", default="0.7,1.5,3.0",
                     help="arrival rates, as multiples of 1 / (mean serial service time)")
@@ -848,6 +920,9 @@ def main():
         del k3u
         torch.cuda.empty_cache()
 
+    if "transforms" in todo:
+        log("transforms: offset, key range, lookup table, accumulation at n=1e8, U=2^24")
+        extra["transforms"] = run_transform_workload(ds, max(K // 2, 5), 2)
     if "windows" in todo:
         log("windows: tumbling windows, ingestion overlapped with projection")
         extra["windows"] = run_windows_workload(ds, max(K // 2, 5), 2)

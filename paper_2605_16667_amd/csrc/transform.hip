@@ -6,9 +6,10 @@
 // Kernels
 //   k_range_init: the running pair (min, max) := (2^32 - 1, 0).
 //   k_range: grid-stride, clamped unconditional loads (eight in flight per
-//     thread), a wave reduction, one atomicMin/atomicMax per wave.  Signed keys
-//     are compared with their sign bit flipped (then unsigned order is signed
-//     order).
+//     thread), a wave reduction, then a workgroup reduction through LDS and one
+//     atomicMin/atomicMax per workgroup (few workgroups, so the two words see
+//     few atomics).  Signed keys are compared with their sign bit flipped (then
+//     unsigned order is signed order).
 //   k_range_fini: flips the pair back.
 #include <hip/hip_runtime.h>
 
@@ -23,8 +24,9 @@ using namespace dsh;
 
 namespace {
 
-constexpr int RG_NT = 256;
+constexpr int RG_NT = 1024;
 constexpr int RG_UNROLL = 8;
+constexpr uint32_t RG_BLOCKS = 512;  // two workgroups per CU
 
 __global__ void k_range_init(uint32_t* mm) {
   if (threadIdx.x == 0) {
@@ -53,7 +55,18 @@ __global__ __launch_bounds__(RG_NT) void k_range(const uint32_t* __restrict__ ke
     lo = std::min(lo, (uint32_t)__shfl_xor(lo, d, WAVE));
     hi = std::max(hi, (uint32_t)__shfl_xor(hi, d, WAVE));
   }
+  __shared__ uint32_t red[2][RG_NT / WAVE];
+  const uint32_t w = threadIdx.x / WAVE;
   if (lane_id() == 0) {
+    red[0][w] = lo;
+    red[1][w] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (uint32_t v = 1; v < RG_NT / WAVE; ++v) {
+      lo = std::min(lo, red[0][v]);
+      hi = std::max(hi, red[1][v]);
+    }
     atomicMin(&mm[0], lo);
     atomicMax(&mm[1], hi);
   }
@@ -80,7 +93,7 @@ dialsort_status dialsort_key_range(const uint32_t* keys, uint64_t n, int is_sign
   const uint32_t flip = is_signed ? 0x80000000u : 0u;
   DS_LAUNCH(k_range_init, dim3(1), dim3(64), stream, minmax);
   if (n) {
-    const uint32_t grid = (uint32_t)std::min<uint64_t>(cdiv(n, (uint64_t)RG_NT * RG_UNROLL), 256 * 8);
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(cdiv(n, (uint64_t)RG_NT * RG_UNROLL), RG_BLOCKS);
     DS_LAUNCH(k_range, dim3(grid), dim3(RG_NT), stream, keys, n, flip, minmax);
   }
   DS_LAUNCH(k_range_fini, dim3(1), dim3(64), stream, minmax, flip);
