@@ -23,6 +23,8 @@ namespace dsb {
 
 constexpr uint32_t UNIT_KEYS = 1u << 18;  // target keys per A or B unit
 constexpr uint32_t FILL_PER = 32;         // item slots per fill unit (shared by its waves)
+constexpr uint64_t CLASS_MIN_COST = 1ull << 22;  // keys plus bins of the first size class, at least
+constexpr uint64_t CLASS_GROWTH = 3;             // a class closes at this many times the cost before it
 constexpr uint64_t BT_PACKED_CHUNK_MAX = 1ull << 22;
 
 bool cfg_valid(const dialsort_batch_config& c) {
@@ -102,40 +104,64 @@ void plan_batch(const dialsort_desc* d, uint32_t count, const Cfg& cfg, char* ba
     }
     A.nf = A.item_cap ? (uint32_t)cdiv(A.item_cap, FILL_PER) : 0;
   }
-  // units: phase by phase, larger arrays first inside a phase
+  // Units in size classes: arrays sorted by cost (keys plus bins), cut into
+  // classes whose cost grows geometrically (a class closes once it holds as
+  // much as all the classes before it, times CLASS_GROWTH), and each class
+  // laid out phase by phase (all its ingestion units, then its counting
+  // units, then its fill units), larger arrays first inside a phase.  Small
+  // arrays then complete early, while every phase of a class still runs wide.
+  // Without classes (cfg.classes false) the whole batch is one class.  A unit
+  // waits only for units of its own array with smaller tickets.
   std::vector<uint32_t> order(count);
   std::iota(order.begin(), order.end(), 0u);
-  std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return d[a].n > d[b].n; });
+  auto cost = [&](uint32_t i) { return d[i].n + d[i].U; };
+  std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return cost(a) < cost(b); });
   auto add = [&](uint32_t a, uint32_t type, uint32_t first, uint32_t cnt) {
     BUnit u;
     u.array = a; u.type = type; u.first = first; u.count = cnt;
     P.units.push_back(u);
   };
+  auto emit_class = [&](std::vector<uint32_t> cls) {
+    std::stable_sort(cls.begin(), cls.end(), [&](uint32_t a, uint32_t b) { return d[a].n > d[b].n; });
+    for (uint32_t i : cls) {
+      const BArray& A = P.arr[i];
+      if (A.kind == BA_LDS) {
+        const uint32_t g = (uint32_t)std::max<uint64_t>(1, UNIT_KEYS / A.per);
+        for (uint32_t c = 0; c < A.na; c += g) add(i, UT_HIST, c, std::min(g, A.na - c));
+      } else if (A.kind == BA_PART) {
+        const uint32_t g = UNIT_KEYS / BT_TK;
+        for (uint32_t t = 0; t < A.na; t += g) add(i, UT_PART, t, std::min(g, A.na - t));
+      }
+    }
+    for (uint32_t i : cls) {
+      const BArray& A = P.arr[i];
+      if (A.kind == BA_PART) {
+        // a bucket costs its keys plus a fixed sweep of its W bins
+        const uint64_t bc = A.n / A.B + W / 4;
+        const uint32_t g = (uint32_t)std::max<uint64_t>(1, UNIT_KEYS / bc);
+        for (uint32_t b = 0; b < A.B; b += g) add(i, UT_BUCKET, b, std::min(g, A.B - b));
+      } else {
+        add(i, UT_ROWS, 0, 1);
+      }
+    }
+    for (uint32_t i : cls) {
+      const BArray& A = P.arr[i];
+      for (uint32_t f = 0; f < A.nf; ++f) add(i, UT_FILL, f, A.nf);
+    }
+  };
+  std::vector<uint32_t> cls;
+  uint64_t done_cost = 0, cls_cost = 0;
   for (uint32_t i : order) {
-    const BArray& A = P.arr[i];
-    if (A.kind == BA_LDS) {
-      const uint32_t g = (uint32_t)std::max<uint64_t>(1, UNIT_KEYS / A.per);
-      for (uint32_t c = 0; c < A.na; c += g) add(i, UT_HIST, c, std::min(g, A.na - c));
-    } else if (A.kind == BA_PART) {
-      const uint32_t g = UNIT_KEYS / BT_TK;
-      for (uint32_t t = 0; t < A.na; t += g) add(i, UT_PART, t, std::min(g, A.na - t));
+    cls.push_back(i);
+    cls_cost += cost(i);
+    if (cfg.classes && cls_cost >= std::max<uint64_t>(CLASS_MIN_COST, CLASS_GROWTH * done_cost)) {
+      emit_class(cls);
+      done_cost += cls_cost;
+      cls_cost = 0;
+      cls.clear();
     }
   }
-  for (uint32_t i : order) {
-    const BArray& A = P.arr[i];
-    if (A.kind == BA_PART) {
-      // a bucket costs its keys plus a fixed sweep of its W bins
-      const uint64_t cost = A.n / A.B + W / 4;
-      const uint32_t g = (uint32_t)std::max<uint64_t>(1, UNIT_KEYS / cost);
-      for (uint32_t b = 0; b < A.B; b += g) add(i, UT_BUCKET, b, std::min(g, A.B - b));
-    } else {
-      add(i, UT_ROWS, 0, 1);
-    }
-  }
-  for (uint32_t i : order) {
-    const BArray& A = P.arr[i];
-    for (uint32_t f = 0; f < A.nf; ++f) add(i, UT_FILL, f, A.nf);
-  }
+  if (!cls.empty()) emit_class(cls);
   // offsets
   size_t off = ALIGN;  // Ctl
   P.off_arrays = off;

@@ -18,6 +18,10 @@ namespace dsb {
 struct Cfg {
   uint32_t nt = 1024, log2w = 16;
   uint64_t chunk = 1ull << 20;
+  // lay the units out in size classes (small arrays complete early); off:
+  // phase by phase over the whole batch, for callers that only wait for the
+  // whole launch
+  bool classes = true;
 };
 
 struct Planned {

@@ -361,6 +361,7 @@ dialsort_status dialsort_server_create(void* arena, size_t arena_bytes, const di
     return DIALSORT_EINVAL;
   dialsort_server* S = new dialsort_server();
   S->cfg = to_cfg(config->batch);
+  S->cfg.classes = false;  // a request completes with its whole launch
   S->max_batch = config->max_batch;
   S->arena = ws_base(arena);
   const size_t lost = (size_t)(S->arena - (char*)arena);
