@@ -22,7 +22,8 @@ struct Ctl {
   uint32_t nitems;       // fill items appended by the scan
   uint32_t pad0;
   uint64_t prof[16];     // batched launch: per unit type, workgroup clock ticks busy / waiting
-  uint32_t pad[22];
+  uint64_t runs;         // long runs of the scan: (count << 40) | their chunks
+  uint32_t pad[20];
 };
 static_assert(sizeof(Ctl) == 256, "control block is 256 bytes");
 

@@ -52,8 +52,8 @@ struct Layout {
   int scan_vpt = 16;
   uint64_t scan_tiles = 0;
   uint64_t limit = 0;
-  uint64_t item_cap = 0;
-  size_t off_tile = 0, off_items = 0, off_rows = 0, off_stage = 0, off_seg = 0, bytes = 0;
+  uint64_t item_cap = 0, run_cap = 0;
+  size_t off_tile = 0, off_items = 0, off_runs = 0, off_rows = 0, off_stage = 0, off_seg = 0, bytes = 0;
   size_t off_z = 0, nz = 0;  // PART: cleared words: bucket-total counters, tile ticket, done counters, scratch
   size_t off_done = 0, off_scratch = 0;
 };
@@ -124,6 +124,10 @@ Layout plan(uint64_t n, uint64_t U, int mode) {
     L.item_cap = (L.kind == K_PART ? 2ull * L.B + cdiv(U, PT_BINS) : L.scan_tiles) +
                  cdiv(L.limit, 1ull << FILL_CL2) + 2;
     L.off_items = off; off = align_up(off + L.item_cap * sizeof(FillItem), ALIGN);
+    // run records of the scan: every recorded run holds more than RUN_MIN of
+    // the chunks of C positions
+    L.run_cap = L.kind == K_PART ? 0 : cdiv(L.limit, RUN_MIN << FILL_CL2) + 1;
+    L.off_runs = off; off = align_up(off + L.run_cap * sizeof(FillRun), ALIGN);
   }
   if (L.rows_in_ws) {
     L.off_rows = off; off = align_up(off + (size_t)L.G * L.row_stride * 4, ALIGN);
@@ -236,17 +240,19 @@ dialsort_status launch_scan(const uint32_t* rows, uint32_t nrows, uint64_t row_s
   uint64_t* tiles = (uint64_t*)(base + L.off_tile);
   FillItem* items = (FillItem*)(base + L.off_items);
   const uint32_t icap = (uint32_t)std::min<uint64_t>(L.item_cap, 0xFFFFFFF0ull);
+  FillRun* runs = (FillRun*)(base + L.off_runs);
+  const uint32_t rcap = (uint32_t)std::min<uint64_t>(L.run_cap, 0xFFFFFFF0ull);
   const dim3 grid((uint32_t)L.scan_tiles);
   if (full) {
     if (L.scan_vpt == 1)
-      DS_LAUNCH((k_scan<SCAN_NT, 1, true>), grid, dim3(SCAN_NT), s, rows, nrows, row_stride, H_out, U, ctl, tiles, items, icap, L.limit, FILL_CL2, report_overflow);
+      DS_LAUNCH((k_scan<SCAN_NT, 1, true>), grid, dim3(SCAN_NT), s, rows, nrows, row_stride, H_out, U, ctl, tiles, items, icap, L.limit, FILL_CL2, report_overflow, runs, rcap);
     else
-      DS_LAUNCH((k_scan<SCAN_NT, 16, true>), grid, dim3(SCAN_NT), s, rows, nrows, row_stride, H_out, U, ctl, tiles, items, icap, L.limit, FILL_CL2, report_overflow);
+      DS_LAUNCH((k_scan<SCAN_NT, 16, true>), grid, dim3(SCAN_NT), s, rows, nrows, row_stride, H_out, U, ctl, tiles, items, icap, L.limit, FILL_CL2, report_overflow, runs, rcap);
   } else {
     if (L.scan_vpt == 1)
-      DS_LAUNCH((k_scan<SCAN_NT, 1, false>), grid, dim3(SCAN_NT), s, rows, nrows, row_stride, H_out, U, ctl, tiles, items, icap, L.limit, FILL_CL2, report_overflow);
+      DS_LAUNCH((k_scan<SCAN_NT, 1, false>), grid, dim3(SCAN_NT), s, rows, nrows, row_stride, H_out, U, ctl, tiles, items, icap, L.limit, FILL_CL2, report_overflow, runs, rcap);
     else
-      DS_LAUNCH((k_scan<SCAN_NT, 16, false>), grid, dim3(SCAN_NT), s, rows, nrows, row_stride, H_out, U, ctl, tiles, items, icap, L.limit, FILL_CL2, report_overflow);
+      DS_LAUNCH((k_scan<SCAN_NT, 16, false>), grid, dim3(SCAN_NT), s, rows, nrows, row_stride, H_out, U, ctl, tiles, items, icap, L.limit, FILL_CL2, report_overflow, runs, rcap);
   }
   return DIALSORT_OK;
 }
@@ -255,19 +261,21 @@ dialsort_status launch_fill(const uint32_t* H, uint32_t* out, uint32_t lo, char*
                             hipStream_t s, const uint32_t* lut = nullptr) {
   Ctl* ctl = (Ctl*)base;
   const FillItem* items = (const FillItem*)(base + L.off_items);
+  const FillRun* runs = (const FillRun*)(base + L.off_runs);
+  const uint32_t rcap = (uint32_t)std::min<uint64_t>(L.run_cap, 0xFFFFFFF0ull);
   if (L.limit == 0) return DIALSORT_OK;
   // one resident round of workgroups (7 per CU at 256 threads), or fewer
   const uint32_t grid = (uint32_t)std::min<uint64_t>(cdiv(L.item_cap, FILL_NT / WAVE), 256 * 7);
   const uint32_t icap = (uint32_t)std::min<uint64_t>(L.item_cap, 0xFFFFFFF0ull);
   if (lut) {
     if (aligned16(out))
-      DS_LAUNCH((k_fill<FILL_NT, FILL_CL2, true, true>), dim3(grid), dim3(FILL_NT), s, H, out, ctl, items, icap, 0u, lut);
+      DS_LAUNCH((k_fill<FILL_NT, FILL_CL2, true, true>), dim3(grid), dim3(FILL_NT), s, H, out, ctl, items, icap, 0u, lut, runs, rcap);
     else
-      DS_LAUNCH((k_fill<FILL_NT, FILL_CL2, false, true>), dim3(grid), dim3(FILL_NT), s, H, out, ctl, items, icap, 0u, lut);
+      DS_LAUNCH((k_fill<FILL_NT, FILL_CL2, false, true>), dim3(grid), dim3(FILL_NT), s, H, out, ctl, items, icap, 0u, lut, runs, rcap);
   } else if (aligned16(out)) {
-    DS_LAUNCH((k_fill<FILL_NT, FILL_CL2, true>), dim3(grid), dim3(FILL_NT), s, H, out, ctl, items, icap, lo, nullptr);
+    DS_LAUNCH((k_fill<FILL_NT, FILL_CL2, true>), dim3(grid), dim3(FILL_NT), s, H, out, ctl, items, icap, lo, nullptr, runs, rcap);
   } else {
-    DS_LAUNCH((k_fill<FILL_NT, FILL_CL2, false>), dim3(grid), dim3(FILL_NT), s, H, out, ctl, items, icap, lo, nullptr);
+    DS_LAUNCH((k_fill<FILL_NT, FILL_CL2, false>), dim3(grid), dim3(FILL_NT), s, H, out, ctl, items, icap, lo, nullptr, runs, rcap);
   }
   return DIALSORT_OK;
 }

@@ -40,6 +40,38 @@ struct FillItem {
 };
 static_assert(sizeof(FillItem) == 32, "fill items are 32 bytes");
 
+// A long run of the scan: bin k's run [o, o + H[k]) holds more than RUN_MIN
+// chunk starts; its items (chunks c0 .. c0 + cnt - 1, each [c C, min((c+1) C,
+// e0)), walking bins k .. klast) are not stored but made by the fill from this
+// record.  Runs are numbered in the order they take their chunks, so `start`
+// (the number of run chunks before this run's first) grows with the index.
+struct FillRun {
+  uint64_t start, c0, o, e0;
+  uint32_t k, klast;
+};
+static_assert(sizeof(FillRun) == 40, "run records are 40 bytes");
+constexpr uint64_t RUN_MIN = 4;              // a run with more chunk starts is recorded, not expanded
+constexpr int RUN_SHIFT = 40;                // Ctl::runs = (runs << RUN_SHIFT) | chunks
+constexpr uint64_t RUN_CHUNKS = (1ull << RUN_SHIFT) - 1;
+
+// The fill item of run chunk j (0 <= j < total run chunks) among `nruns` runs.
+__device__ __forceinline__ FillItem run_item(const FillRun* __restrict__ runs, uint32_t nruns, uint64_t j, int CL2) {
+  uint32_t lo = 0, hi = nruns;  // the last run with start <= j
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (runs[mid].start <= j) lo = mid; else hi = mid;
+  }
+  const FillRun R = runs[lo];
+  const uint64_t c = R.c0 + (j - R.start);
+  FillItem it;
+  it.p0 = c << CL2;
+  it.p1 = ((c + 1) << CL2) < R.e0 ? ((c + 1) << CL2) : R.e0;
+  it.o = R.o;
+  it.k = R.k;
+  it.klast = R.klast;
+  return it;
+}
+
 __device__ __forceinline__ uint64_t wave_sum_sat(uint64_t x) {
 #pragma unroll
   for (int d = WAVE / 2; d >= 1; d >>= 1) x = sat_add(x, __shfl_xor(x, d, WAVE));
@@ -79,17 +111,14 @@ template <int NT, int VPT, bool FULL>
 __global__ __launch_bounds__(NT) void k_scan(const uint32_t* __restrict__ rows, uint32_t nrows, uint64_t row_stride,
                                              uint32_t* __restrict__ H_out, uint64_t U, Ctl* ctl,
                                              uint64_t* tile_state, FillItem* __restrict__ items,
-                                             uint32_t item_cap, uint64_t limit, int CL2, int report_overflow) {
+                                             uint32_t item_cap, uint64_t limit, int CL2, int report_overflow,
+                                             FillRun* __restrict__ runs, uint32_t run_cap) {
   constexpr int TB = NT * VPT;
   constexpr int PADW = TB + TB / 32;
   __shared__ uint32_t tr[VPT > 1 ? PADW : 1];
   __shared__ uint64_t scan_tmp[NT / WAVE + 1];
   __shared__ uint64_t s_prefix;
   __shared__ uint32_t s_tile;
-  // long runs that cross many chunk starts, written cooperatively
-  __shared__ uint32_t lr_bin[NT];
-  __shared__ uint64_t lr_off[NT], lr_c0[NT], lr_cnt[NT];
-  __shared__ uint32_t lr_n;
   __shared__ uint32_t s_item0;
   const uint32_t tid = threadIdx.x;
 
@@ -168,23 +197,10 @@ __global__ __launch_bounds__(NT) void k_scan(const uint32_t* __restrict__ rows, 
   const uint64_t e0 = sat_add(tpre, agg_sat) < limit ? sat_add(tpre, agg_sat) : limit;
   const uint64_t cbase = s0 >> CL2;
   const uint64_t nit = e0 > s0 ? ((e0 + C - 1) >> CL2) - cbase : 0;
-  if (tid == 0) {
-    lr_n = 0;
-    uint32_t i0 = 0;
-    if (nit) {
-      i0 = atomicAdd(&ctl->nitems, (uint32_t)nit);
-      if ((uint64_t)i0 + nit > item_cap) { set_status(ctl, ST_INT_ITEMS); i0 = 0xFFFFFFFFu; }
-    }
-    s_item0 = i0;
-  }
-  __syncthreads();
-  const uint32_t item0 = s_item0;
-  const bool emit = nit > 0 && item0 != 0xFFFFFFFFu;
-  const uint32_t klast = (uint32_t)((base + TB < U ? base + TB : U) - 1);
   // chunk starts c*C strictly inside the span and inside bin's run [o, o+h)
   auto starts = [&](uint64_t o, uint64_t h, uint64_t& c0, uint64_t& cnt) {
     c0 = 0; cnt = 0;
-    if (emit && h > 0 && o < e0) {
+    if (nit > 0 && h > 0 && o < e0) {
       const uint64_t e = sat_add(o, h) < e0 ? sat_add(o, h) : e0;  // run clipped to the span
       uint64_t lo = (o + C - 1) >> CL2;
       if (lo < cbase + 1) lo = cbase + 1;
@@ -193,9 +209,37 @@ __global__ __launch_bounds__(NT) void k_scan(const uint32_t* __restrict__ rows, 
       cnt = hi >= lo ? hi - lo + 1 : 0;
     }
   };
+  // Runs with more than RUN_MIN chunk starts become run records; the other
+  // chunks are stored as items, numbered in position order without the run
+  // chunks (a block scan counts the run chunks before each thread's bins).
   const uint64_t o_first = sat_add(tpre, texcl);
+  uint64_t my_lr = 0;
+  {
+    uint64_t o = o_first;
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      uint64_t c0, cnt;
+      starts(o, v[j], c0, cnt);
+      if (cnt > RUN_MIN) my_lr += cnt;
+      o = sat_add(o, v[j]);
+    }
+  }
+  uint64_t lr_total = 0, lr_seen = 0;
+  if (__syncthreads_or(my_lr != 0)) lr_seen = block_exclusive_sum<NT>(my_lr, scan_tmp, &lr_total);
+  if (tid == 0) {
+    uint32_t i0 = 0;
+    const uint64_t nreg = nit - lr_total;
+    if (nreg) {
+      i0 = atomicAdd(&ctl->nitems, (uint32_t)nreg);
+      if ((uint64_t)i0 + nreg > item_cap) { set_status(ctl, ST_INT_ITEMS); i0 = 0xFFFFFFFFu; }
+    }
+    s_item0 = i0;
+  }
+  __syncthreads();
+  const uint32_t item0 = s_item0;
+  const bool emit = nit > 0 && item0 != 0xFFFFFFFFu;
+  const uint32_t klast = (uint32_t)((base + TB < U ? base + TB : U) - 1);
   uint64_t o = o_first;
-  uint32_t pending = 0;  // bit j: bin j's run crosses more than 4 chunk starts
 #pragma unroll
   for (int j = 0; j < VPT; ++j) {
     const uint64_t h = v[j];
@@ -208,47 +252,28 @@ __global__ __launch_bounds__(NT) void k_scan(const uint32_t* __restrict__ rows, 
       it.o = o; it.k = (uint32_t)bin; it.klast = klast;
       items[item0] = it;
     }
-    if (cnt > 0 && cnt <= 4) {
+    if (emit && cnt > 0 && cnt <= RUN_MIN) {
       for (uint64_t i = 0; i < cnt; ++i) {
         const uint64_t c = c0 + i;
         FillItem it;
         it.p0 = c << CL2; it.p1 = ((c + 1) << CL2) < e0 ? ((c + 1) << CL2) : e0;
         it.o = o; it.k = (uint32_t)bin; it.klast = klast;
-        items[item0 + (c - cbase)] = it;
+        items[item0 + (c - cbase) - lr_seen] = it;
       }
     }
-    if (cnt > 4) pending |= 1u << j;
+    if (emit && cnt > RUN_MIN) {
+      const uint64_t old = atomicAdd((unsigned long long*)&ctl->runs, (1ull << RUN_SHIFT) | cnt);
+      const uint64_t slot = old >> RUN_SHIFT;
+      if (slot < run_cap) {
+        FillRun r;
+        r.start = old & RUN_CHUNKS; r.c0 = c0; r.o = o; r.e0 = e0; r.k = (uint32_t)bin; r.klast = klast;
+        runs[slot] = r;
+      } else {
+        set_status(ctl, ST_INT_ITEMS);
+      }
+      lr_seen += cnt;
+    }
     o = sat_add(o, h);
-  }
-  // runs that cross many chunk starts: their items are written by the whole block
-  if (__syncthreads_or(pending != 0)) {
-    o = o_first;
-    for (int j = 0; j < VPT; ++j) {
-      if ((pending >> j) & 1u) {
-        uint64_t c0, cnt;
-        starts(o, v[j], c0, cnt);
-        const uint32_t slot = atomicAdd(&lr_n, 1u);
-        lr_bin[slot] = (uint32_t)(base + (uint64_t)tid * VPT + j);
-        lr_off[slot] = o; lr_c0[slot] = c0; lr_cnt[slot] = cnt;
-      }
-      o = sat_add(o, v[j]);
-      __syncthreads();
-      const uint32_t nl = lr_n;
-      for (uint32_t e = 0; e < nl; ++e) {
-        const uint32_t b = lr_bin[e];
-        const uint64_t oo = lr_off[e], cc = lr_c0[e], nn = lr_cnt[e];
-        for (uint64_t i = tid; i < nn; i += NT) {
-          const uint64_t c = cc + i;
-          FillItem it;
-          it.p0 = c << CL2; it.p1 = ((c + 1) << CL2) < e0 ? ((c + 1) << CL2) : e0;
-          it.o = oo; it.k = b; it.klast = klast;
-          items[item0 + (c - cbase)] = it;
-        }
-      }
-      __syncthreads();
-      if (tid == 0) lr_n = 0;
-      __syncthreads();
-    }
   }
 }
 
@@ -382,14 +407,20 @@ __device__ __forceinline__ void wave_fill_item(WaveFillSmem<CL2>& S, const uint3
 template <int NT, int CL2, bool OALIGNED, bool LUT = false>
 __global__ __launch_bounds__(NT) void k_fill(const uint32_t* __restrict__ H, uint32_t* __restrict__ out,
                                              Ctl* ctl, const FillItem* __restrict__ items,
-                                             uint32_t item_cap, uint32_t lo, const uint32_t* __restrict__ lut) {
+                                             uint32_t item_cap, uint32_t lo, const uint32_t* __restrict__ lut,
+                                             const FillRun* __restrict__ runs, uint32_t run_cap) {
   constexpr uint32_t NW = NT / WAVE;
   __shared__ WaveFillSmem<CL2> S[NW];
   const uint32_t w = threadIdx.x / WAVE;
   // a failed invariant (reported as ST_INTERNAL) leaves items unwritten: fill nothing
-  const uint32_t nitems = (ctl->status & ST_INTERNAL) ? 0u : (ctl->nitems < item_cap ? ctl->nitems : item_cap);
-  for (uint32_t it = blockIdx.x * NW + w; it < nitems; it += gridDim.x * NW) {
-    const FillItem I = items[it];
+  const bool failed = (ctl->status & ST_INTERNAL) != 0;
+  const uint32_t nitems = failed ? 0u : (ctl->nitems < item_cap ? ctl->nitems : item_cap);
+  // the stored items, then the chunks of the recorded runs
+  const uint64_t rr = failed ? 0ull : ctl->runs;
+  const uint32_t nruns = (uint32_t)(rr >> RUN_SHIFT) < run_cap ? (uint32_t)(rr >> RUN_SHIFT) : run_cap;
+  const uint64_t ntotal = nitems + (nruns ? (rr & RUN_CHUNKS) : 0ull);
+  for (uint64_t it = blockIdx.x * NW + w; it < ntotal; it += (uint64_t)gridDim.x * NW) {
+    const FillItem I = it < nitems ? items[it] : run_item(runs, nruns, it - nitems, CL2);
     // every producer cuts items well inside the 16-bit key offsets; anything
     // else is a broken invariant, reported instead of written
     if (I.klast < I.k || I.klast - I.k >= FILL_SPAN_MAX || I.p1 < I.p0 || I.p1 - (I.p0 & ~3ull) > (1ull << CL2)) {
