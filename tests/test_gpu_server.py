@@ -205,3 +205,55 @@ def test_release_rules_and_held_arena(ds):
         assert ds.dialsort_server_info(srv, ids[0])[0] == ds.DIALSORT_EINVAL  # released
     finally:
         ds.check(ds.dialsort_server_destroy(srv))
+
+
+def test_queries_on_resident_histograms(ds):
+    """Served requests keep H in the arena until they are released; the queries
+    of the canonical ordered state (Sec. 3.3) run on it there, through a view of
+    the arena (nothing is copied), and match the oracle on the request's keys."""
+    reqs = small_stream(12, seed_shift=3)
+    dev_keys = [torch.from_numpy(k.view(np.int32)).to(DEV) for k, _ in reqs]
+    arena, srv = make_server(ds, 1 << 30)
+    try:
+        ids = []
+        for kd, (_, U) in zip(dev_keys, reqs):
+            st, rid = ds.dialsort_server_submit(srv, kd, U)
+            ds.check(st)
+            ids.append(rid)
+        ds.check(ds.dialsort_server_drain(srv))
+        rng = np.random.default_rng(17)
+        for rid, (kh, U) in zip(ids, reqs):
+            st, info = ds.dialsort_server_info(srv, rid)
+            ds.check(st)
+            assert info.state == ds.DIALSORT_REQ_DONE and info.status == ds.DIALSORT_OK
+            say(f"queries on the resident H of request {rid}: n={info.n} U={U}")
+            H = ds.arena_view(arena, info.H, info.U)
+            st_o, H_ref = oracle.histogram(kh, U)
+            assert st_o == oracle.OK
+            q = np.concatenate([rng.integers(0, U, 500), kh[:100], [U - 1, U]]).astype(np.uint32)
+            qd = torch.from_numpy(q.view(np.int32)).to(DEV)
+            f = torch.empty(q.size, dtype=torch.int32, device=DEV)
+            ds.check(ds.dialsort_query_frequency(H, U, qd, f))
+            assert np.array_equal(w.as_u32(f), oracle.frequency(H_ref, q))
+            pres = torch.empty(q.size, dtype=torch.uint8, device=DEV)
+            ds.check(ds.dialsort_query_presence(H, U, qd, pres))
+            assert np.array_equal(pres.cpu().numpy(), oracle.presence(H_ref, q))
+            P = torch.empty(U + 1, dtype=torch.int64, device=DEV)
+            ws = ds.workspace(ds.dialsort_prefix_workspace_bytes(U))
+            ds.check(ds.dialsort_prefix(H, U, P, ws))
+            assert np.array_equal(P.cpu().numpy().view(np.uint64), oracle.prefix(H_ref))
+            a = rng.integers(0, U + 1, 200).astype(np.uint64)
+            b = np.minimum(a + rng.integers(0, U + 1, 200).astype(np.uint64), np.uint64(U))
+            rc = torch.empty(a.size, dtype=torch.int64, device=DEV)
+            ds.check(ds.dialsort_query_range_count(P, U, torch.from_numpy(a.view(np.int64)).to(DEV),
+                                                   torch.from_numpy(b.view(np.int64)).to(DEV), rc))
+            assert np.array_equal(rc.cpu().numpy().view(np.uint64), oracle.range_count(H_ref, a, b))
+            r = np.concatenate([rng.integers(0, kh.size, 200), [0, kh.size - 1, kh.size]]).astype(np.uint64)
+            sel = torch.empty(r.size, dtype=torch.int32, device=DEV)
+            ds.check(ds.dialsort_query_select(P, U, torch.from_numpy(r.view(np.int64)).to(DEV), sel))
+            assert np.array_equal(w.as_u32(sel), oracle.select(H_ref, r))
+            # the queries left the request's H as the server wrote it
+            assert np.array_equal(w.as_u32(H), H_ref)
+            ds.check(ds.dialsort_server_release(srv, rid))
+    finally:
+        ds.check(ds.dialsort_server_destroy(srv))
