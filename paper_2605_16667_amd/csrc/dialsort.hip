@@ -264,8 +264,8 @@ dialsort_status launch_fill(const uint32_t* H, uint32_t* out, uint32_t lo, char*
   const FillRun* runs = (const FillRun*)(base + L.off_runs);
   const uint32_t rcap = (uint32_t)std::min<uint64_t>(L.run_cap, 0xFFFFFFF0ull);
   if (L.limit == 0) return DIALSORT_OK;
-  // one resident round of workgroups (7 per CU at 256 threads), or fewer
-  const uint32_t grid = (uint32_t)std::min<uint64_t>(cdiv(L.item_cap, FILL_NT / WAVE), 256 * 7);
+  // one resident round of workgroups (8 per CU at 256 threads), or fewer
+  const uint32_t grid = (uint32_t)std::min<uint64_t>(cdiv(L.item_cap, FILL_NT / WAVE), 256 * 8);
   const uint32_t icap = (uint32_t)std::min<uint64_t>(L.item_cap, 0xFFFFFFF0ull);
   if (lut) {
     if (aligned16(out))

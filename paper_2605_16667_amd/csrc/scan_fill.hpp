@@ -411,7 +411,7 @@ __global__ __launch_bounds__(NT) void k_fill(const uint32_t* __restrict__ H, uin
                                              const FillRun* __restrict__ runs, uint32_t run_cap) {
   constexpr uint32_t NW = NT / WAVE;
   __shared__ WaveFillSmem<CL2> S[NW];
-  const uint32_t w = threadIdx.x / WAVE;
+  const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   // a failed invariant (reported as ST_INTERNAL) leaves items unwritten: fill nothing
   const bool failed = (ctl->status & ST_INTERNAL) != 0;
   const uint32_t nitems = failed ? 0u : (ctl->nitems < item_cap ? ctl->nitems : item_cap);
@@ -419,8 +419,14 @@ __global__ __launch_bounds__(NT) void k_fill(const uint32_t* __restrict__ H, uin
   const uint64_t rr = failed ? 0ull : ctl->runs;
   const uint32_t nruns = (uint32_t)(rr >> RUN_SHIFT) < run_cap ? (uint32_t)(rr >> RUN_SHIFT) : run_cap;
   const uint64_t ntotal = nitems + (nruns ? (rr & RUN_CHUNKS) : 0ull);
-  for (uint64_t it = blockIdx.x * NW + w; it < ntotal; it += (uint64_t)gridDim.x * NW) {
-    const FillItem I = it < nitems ? items[it] : run_item(runs, nruns, it - nitems, CL2);
+  const uint64_t stride = (uint64_t)gridDim.x * NW;
+  uint64_t it = blockIdx.x * NW + w;
+  // the wave's next stored item is loaded while the current one is filled
+  FillItem next{};
+  if (it < nitems) next = items[it];
+  for (; it < ntotal; it += stride) {
+    const FillItem I = it < nitems ? next : run_item(runs, nruns, it - nitems, CL2);
+    if (it + stride < nitems) next = items[it + stride];
     // every producer cuts items well inside the 16-bit key offsets; anything
     // else is a broken invariant, reported instead of written
     if (I.klast < I.k || I.klast - I.k >= FILL_SPAN_MAX || I.p1 < I.p0 || I.p1 - (I.p0 & ~3ull) > (1ull << CL2)) {
