@@ -224,9 +224,15 @@ __device__ __forceinline__ uint64_t unit_fill(BatchSmem<NT, LOG2W>& S, const BAr
   if (!failed) {
     // wave w takes slots first + stride * (w + NW m)
     constexpr uint32_t NW = NT / WAVE;
-    const uint32_t w = threadIdx.x / WAVE;
-    for (uint64_t j = first + (uint64_t)stride * w; j < ni; j += (uint64_t)stride * NW) {
-      const FillItem I = A.items[j];
+    const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const uint64_t step = (uint64_t)stride * NW;
+    uint64_t j = first + (uint64_t)stride * w;
+    // the wave's next item is loaded while the current one is filled
+    FillItem next{};
+    if (j < ni) next = A.items[j];
+    for (; j < ni; j += step) {
+      const FillItem I = next;
+      if (j + step < ni) next = A.items[j + step];
       // an item always lies inside its array; anything else is a broken
       // invariant, reported instead of written
       const bool valid = I.k <= I.klast && I.klast < A.U && I.klast - I.k < FILL_SPAN_MAX && I.o <= I.p0 &&
