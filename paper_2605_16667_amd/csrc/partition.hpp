@@ -428,28 +428,41 @@ __device__ __forceinline__ void emit_items(SM& S, FillItem* __restrict__ items, 
     mine = (len > 0) && (o0 == sp0 || cntc > 0);
   }
   if (mine) {
+    // pn: the first chunk start c*C (c > cb) at or after o.  A bin [o, o + h)
+    // has items to write only if it opens the span (o == sp0) or reaches pn;
+    // every other bin just advances o.
+    auto next_start = [&](uint64_t x) -> uint64_t {
+      const uint64_t c = (x + C - 1) >> CL2;
+      return (c > cb + 1 ? c : cb + 1) << CL2;
+    };
+    uint64_t pn = next_start(o);
     for (uint32_t j = 0; j < NB; ++j) {
       const uint32_t i = j0 + j;
       const uint64_t h = i < nb_valid ? count(i) : 0u;
-      if (h > 0 && o == sp0) {  // the span's first nonzero bin opens item 0
-        FillItem it;
-        it.p0 = sp0; it.p1 = ((cb + 1) << CL2) < sp1 ? ((cb + 1) << CL2) : sp1;
-        it.o = o; it.k = (uint32_t)(hb + i); it.klast = klast;
-        items[item0] = it;
-      }
-      uint64_t lo, cntc;
-      starts(o, h, lo, cntc);
-      if (cntc > 4) {
-        anylong = true;  // written below by the whole block
-      } else {
-        for (uint64_t c = lo; c < lo + cntc; ++c) {
+      if (h > 0 && (o == sp0 || o + h > pn)) {
+        if (o == sp0) {  // the span's first nonzero bin opens item 0
           FillItem it;
-          it.p0 = c << CL2; it.p1 = ((c + 1) << CL2) < sp1 ? ((c + 1) << CL2) : sp1;
+          it.p0 = sp0; it.p1 = ((cb + 1) << CL2) < sp1 ? ((cb + 1) << CL2) : sp1;
           it.o = o; it.k = (uint32_t)(hb + i); it.klast = klast;
-          items[item0 + (c - cb)] = it;
+          items[item0] = it;
         }
+        uint64_t lo, cntc;
+        starts(o, h, lo, cntc);
+        if (cntc > 4) {
+          anylong = true;  // written below by the whole block
+        } else {
+          for (uint64_t c = lo; c < lo + cntc; ++c) {
+            FillItem it;
+            it.p0 = c << CL2; it.p1 = ((c + 1) << CL2) < sp1 ? ((c + 1) << CL2) : sp1;
+            it.o = o; it.k = (uint32_t)(hb + i); it.klast = klast;
+            items[item0 + (c - cb)] = it;
+          }
+        }
+        o += h;
+        pn = next_start(o);
+      } else {
+        o += h;
       }
-      o += h;
     }
   }
   // runs that cross more than 4 chunk starts (rare): one bin per thread per
