@@ -399,8 +399,9 @@ __device__ __forceinline__ uint32_t packed_count(const SM& S, uint32_t k) {
 // o0 is the absolute position where its stretch starts.  The thread's bins lie
 // in a span of output positions [sp0, sp1) (the run of a group of bins ending
 // at bin klast) whose items start at index item0; threads may belong to
-// different spans.
-template <int NT, uint32_t NB, typename SM, typename CountF>
+// different spans.  PAIRS: the counts are packed 16-bit pairs (bin i in word
+// i / 2) and j0, NB are even, so the walk reads one word per two bins.
+template <int NT, uint32_t NB, bool PAIRS, typename SM, typename CountF>
 __device__ __forceinline__ void emit_items(SM& S, FillItem* __restrict__ items, uint32_t item0, int CL2,
                                            uint64_t sp0, uint64_t sp1, uint64_t hb, uint32_t j0, uint32_t nb_valid,
                                            uint64_t o0, uint64_t len, uint32_t klast, CountF count) {
@@ -436,9 +437,8 @@ __device__ __forceinline__ void emit_items(SM& S, FillItem* __restrict__ items, 
       return (c > cb + 1 ? c : cb + 1) << CL2;
     };
     uint64_t pn = next_start(o);
-    for (uint32_t j = 0; j < NB; ++j) {
-      const uint32_t i = j0 + j;
-      const uint64_t h = i < nb_valid ? count(i) : 0u;
+    // bin i with count h: write its items if it has any, and advance o
+    auto visit = [&](uint32_t i, uint64_t h) {
       if (h > 0 && (o == sp0 || o + h > pn)) {
         if (o == sp0) {  // the span's first nonzero bin opens item 0
           FillItem it;
@@ -462,6 +462,26 @@ __device__ __forceinline__ void emit_items(SM& S, FillItem* __restrict__ items, 
         pn = next_start(o);
       } else {
         o += h;
+      }
+    };
+    if constexpr (PAIRS) {
+      // o >= sp0 throughout (the stretch starts inside its span), so a pair
+      // with neither o == sp0 nor o + h0 + h1 > pn holds no item start
+      for (uint32_t j = 0; j < NB; j += 2) {
+        const uint32_t i = j0 + j;
+        const uint32_t word = i < nb_valid ? S.s[i >> 1] : 0u;
+        const uint64_t h0 = word & 0xFFFFu, h1 = i + 1 < nb_valid ? (word >> 16) : 0u;
+        if (h0 + h1 > 0 && (o == sp0 || o + h0 + h1 > pn)) {
+          visit(i, h0);
+          visit(i + 1, h1);
+        } else {
+          o += h0 + h1;
+        }
+      }
+    } else {
+      for (uint32_t j = 0; j < NB; ++j) {
+        const uint32_t i = j0 + j;
+        visit(i, i < nb_valid ? count(i) : 0u);
       }
     }
   }
@@ -593,10 +613,10 @@ __device__ __forceinline__ uint64_t project_piece(SM& S, uint32_t* status, uint3
   const uint32_t my0 = item0 + (uint32_t)tile_off;
   if constexpr (PACKED) {
     auto count = [&](uint32_t i) -> uint32_t { return packed_count(S, i); };
-    emit_items<NT, NB>(S, items, my0, CL2, ts, te, hb, j0, pcnt, base + pre, sum, tklast, count);
+    emit_items<NT, NB, (NB % 2 == 0)>(S, items, my0, CL2, ts, te, hb, j0, pcnt, base + pre, sum, tklast, count);
   } else {
     auto count = [&](uint32_t i) -> uint32_t { return S.s[i]; };
-    emit_items<NT, NB>(S, items, my0, CL2, ts, te, hb, j0, pcnt, base + pre, sum, tklast, count);
+    emit_items<NT, NB, false>(S, items, my0, CL2, ts, te, hb, j0, pcnt, base + pre, sum, tklast, count);
   }
   return tot;
 }
