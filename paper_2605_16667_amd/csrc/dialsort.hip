@@ -34,6 +34,7 @@ namespace {
 
 constexpr int FILL_NT = 256;
 constexpr int FILL_CL2 = 11;  // fill items of at most 2048 positions (one wave each)
+constexpr uint64_t FILL_NTS_BYTES = uint64_t(64) << 20;  // outputs from 64 MiB on use non-temporal stores
 constexpr int SCAN_NT = 256;
 constexpr uint64_t PART_NCU = 256;  // compute units of the target (MI355X)
 
@@ -267,11 +268,18 @@ dialsort_status launch_fill(const uint32_t* H, uint32_t* out, uint32_t lo, char*
   // one resident round of workgroups (8 per CU at 256 threads), or fewer
   const uint32_t grid = (uint32_t)std::min<uint64_t>(cdiv(L.item_cap, FILL_NT / WAVE), 256 * 8);
   const uint32_t icap = (uint32_t)std::min<uint64_t>(L.item_cap, 0xFFFFFFF0ull);
+  // an output larger than the L2 caches together is streamed past them: its
+  // dirty lines then do not drain into the next kernel's HBM traffic
+  const bool nts = L.limit * 4 >= FILL_NTS_BYTES;
   if (lut) {
-    if (aligned16(out))
+    if (aligned16(out) && nts)
+      DS_LAUNCH((k_fill<FILL_NT, FILL_CL2, true, true, true>), dim3(grid), dim3(FILL_NT), s, H, out, ctl, items, icap, 0u, lut, runs, rcap);
+    else if (aligned16(out))
       DS_LAUNCH((k_fill<FILL_NT, FILL_CL2, true, true>), dim3(grid), dim3(FILL_NT), s, H, out, ctl, items, icap, 0u, lut, runs, rcap);
     else
       DS_LAUNCH((k_fill<FILL_NT, FILL_CL2, false, true>), dim3(grid), dim3(FILL_NT), s, H, out, ctl, items, icap, 0u, lut, runs, rcap);
+  } else if (aligned16(out) && nts) {
+    DS_LAUNCH((k_fill<FILL_NT, FILL_CL2, true, false, true>), dim3(grid), dim3(FILL_NT), s, H, out, ctl, items, icap, lo, nullptr, runs, rcap);
   } else if (aligned16(out)) {
     DS_LAUNCH((k_fill<FILL_NT, FILL_CL2, true>), dim3(grid), dim3(FILL_NT), s, H, out, ctl, items, icap, lo, nullptr, runs, rcap);
   } else {

@@ -299,7 +299,8 @@ struct WaveFillSmem {
 };
 
 // LUT: bin k's value is lut[k] (a table phi^-1 of Sec. 3.4) instead of lo + k.
-template <int CL2, bool OALIGNED, bool LUT = false>
+// NTS: the 16-byte stores are non-temporal (streamed past the caches).
+template <int CL2, bool OALIGNED, bool LUT = false, bool NTS = false>
 __device__ __forceinline__ void wave_fill_item(WaveFillSmem<CL2>& S, const uint32_t* __restrict__ H,
                                                uint32_t* __restrict__ out, const FillItem& I, uint32_t lo = 0,
                                                const uint32_t* __restrict__ lut = nullptr) {
@@ -392,7 +393,13 @@ __device__ __forceinline__ void wave_fill_item(WaveFillSmem<CL2>& S, const uint3
     }
     const uint32_t i0 = q << 2;
     if (OALIGNED && i0 >= lb && i0 + 4 <= le) {
-      *reinterpret_cast<uint4*>(out + a0 + i0) = make_uint4(r0, r1, r2, r3);
+      if constexpr (NTS) {
+        typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+        const u32x4_t v = {r0, r1, r2, r3};
+        __builtin_nontemporal_store(v, reinterpret_cast<u32x4_t*>(out + a0 + i0));
+      } else {
+        *reinterpret_cast<uint4*>(out + a0 + i0) = make_uint4(r0, r1, r2, r3);
+      }
     } else {
       if (i0 >= lb && i0 < le) out[a0 + i0] = r0;
       if (i0 + 1 >= lb && i0 + 1 < le) out[a0 + i0 + 1] = r1;
@@ -404,7 +411,7 @@ __device__ __forceinline__ void wave_fill_item(WaveFillSmem<CL2>& S, const uint3
 
 // Persistent fill over the items appended to ctl->nitems: every wave of every
 // workgroup takes items on its own.
-template <int NT, int CL2, bool OALIGNED, bool LUT = false>
+template <int NT, int CL2, bool OALIGNED, bool LUT = false, bool NTS = false>
 __global__ __launch_bounds__(NT) void k_fill(const uint32_t* __restrict__ H, uint32_t* __restrict__ out,
                                              Ctl* ctl, const FillItem* __restrict__ items,
                                              uint32_t item_cap, uint32_t lo, const uint32_t* __restrict__ lut,
@@ -433,7 +440,7 @@ __global__ __launch_bounds__(NT) void k_fill(const uint32_t* __restrict__ H, uin
       if (lane_id() == 0) atomicOr(&ctl->status, ST_INT_ITEM);
       continue;
     }
-    wave_fill_item<CL2, OALIGNED, LUT>(S[w], H, out, I, lo, lut);
+    wave_fill_item<CL2, OALIGNED, LUT, NTS>(S[w], H, out, I, lo, lut);
   }
 }
 
