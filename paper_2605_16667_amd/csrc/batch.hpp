@@ -241,7 +241,7 @@ __device__ __forceinline__ uint64_t unit_fill(BatchSmem<NT, LOG2W>& S, const BAr
         if (lane_id() == 0) atomicOr(status, ST_INT_ITEM);
         continue;
       }
-      wave_fill_item<BT_CL2, true>(S.fill[w], A.H, A.out, I);
+      wave_fill_item<BT_CL2, true, false, true>(S.fill[w], A.H, A.out, I);
     }
   }
   const uint32_t old = unit_signal(&st->c_done, 1);
