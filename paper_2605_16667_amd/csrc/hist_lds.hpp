@@ -36,7 +36,10 @@ __device__ __forceinline__ uint32_t load_group(const uint32_t* __restrict__ keys
   uint32_t c = 0;
   if (e0 + 4 <= end) {
     if constexpr (ALIGNED) {
-      const uint4 q = *reinterpret_cast<const uint4*>(keys + e0);
+      // keys are read once: non-temporal loads keep them from displacing
+      // what the next passes read back (the staging, H)
+      typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+      const u32x4_t q = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t*>(keys + e0));
       v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
     } else {
       v[0] = keys[e0]; v[1] = keys[e0 + 1]; v[2] = keys[e0 + 2]; v[3] = keys[e0 + 3];
