@@ -44,6 +44,7 @@ def sort_lut(ds, keys_u32, U, lut_u32, in_place=False):
     (2001, 50000),          # LDS path
     (1 << 16, 1 << 20),     # packed LDS path
     (1 << 24, 5_000_000),   # partitioned path
+    (1 << 24, 20_000_000),  # partitioned path, an 80 MB output (non-temporal fill stores from 64 MiB)
     (1 << 20, 3000),        # global-atomics path (few keys, large U)
     (70001, 200_003),
 ])
