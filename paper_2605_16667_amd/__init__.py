@@ -62,7 +62,7 @@ DIALSORT_REQ_QUEUED, DIALSORT_REQ_ADMITTED, DIALSORT_REQ_RUNNING, DIALSORT_REQ_D
 
 def _load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2605_16667_amd.build.build()")
+        raise ImportError(f"{LIB_PATH} is missing: build it with python paper_2605_16667_amd/build.py")
     lib = ctypes.CDLL(LIB_PATH)
     u64, p, sz, st = ctypes.c_uint64, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
     sig = {
