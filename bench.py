@@ -437,13 +437,18 @@ def run_batch_workload(ds, hip, count, K, W):
     return res
 
 
-def run_serve_workload(ds, hip, num, loads, batch_cfg, arena_gib=8):
+def run_serve_workload(ds, hip, num, loads, batch_cfg):
     """The served stream: `num` requests with Poisson arrivals, n log-uniform
     in [2^12, 2^24], U uniform over {2^12, 2^16, 2^20, 2^24}, uniform or
     Zipf(1.2) keys (p = 1/2), all keys already in device memory.  For every
     load L the arrival rate is L / (mean serial service time).  Baseline: serial
     plain sorts, first in first out, one dialsort_sort at a time; served: the
-    continuous-batching server.  Latency = arrival to completion."""
+    continuous-batching server.  Latency = arrival to the moment the host sees
+    the request complete, on the host clock for both: the serial loop after its
+    synchronisation, the server when a poll first finds the request's batch
+    finished (seen_ms, on the server clock, against arrivals placed on that
+    clock).  Served results stay resident until the replay ends; every request's
+    H and output are then checked (torch bincount and order) before release."""
     import torch
 
     import workloads as w
@@ -469,13 +474,18 @@ def run_serve_workload(ds, hip, num, loads, batch_cfg, arena_gib=8):
         torch.cuda.synchronize()
         svc.append(time.perf_counter() - t)
     mean_svc = statistics.mean(svc)
-    arena = torch.empty(arena_gib << 30, dtype=torch.uint8, device=dev)
+    # every result stays resident until the replay ends: the arena holds all
+    # footprints plus room for the batches' workspaces
+    foot = sum(ds.dialsort_server_footprint(r.spec.n, r.spec.U) for r in probe)
+    arena_bytes = foot + (16 << 30)
+    arena = torch.empty(arena_bytes, dtype=torch.uint8, device=dev)
     res = {"workload": f"{num} requests, Poisson arrivals at L x (1 / mean serial service time), "
                        "n log-uniform in [2^12, 2^24], U in {2^12, 2^16, 2^20, 2^24}, uniform or Zipf(1.2)",
            "requests": num, "keys": nkeys, "mean_serial_service_ms": mean_svc * 1e3,
+           "latency": "arrival to host-observed completion, host clock for both forms",
            "server_config": {"block": batch_cfg.block, "log2_width": batch_cfg.log2_width,
                              "chunk_keys": batch_cfg.chunk_keys, "max_inflight": SERVE_SLOTS, "max_batch": 256,
-                             "arena_gib": arena_gib},
+                             "arena_bytes": arena_bytes},
            "loads": {}}
     for load in loads:
         rate = load / mean_svc
@@ -511,12 +521,13 @@ def run_serve_workload(ds, hip, num, loads, batch_cfg, arena_gib=8):
                     break
                 if info.status != ds.DIALSORT_OK:
                     raise RuntimeError(f"request status {info.status}")
-                infos[outstanding[0]] = (info.submit_ms, info.launch_ms, info.done_ms)
-                ds.check(ds.dialsort_server_release(srv, outstanding[0]))
+                infos[outstanding[0]] = (info.launch_ms, info.seen_ms, info.H, info.out)
                 outstanding.pop(0)
 
+        ok = True
         try:
             t0 = time.perf_counter()
+            t0s = ds.dialsort_server_now_ms(srv)
             for k, r, a in zip(keys, reqs, arrivals):
                 while time.perf_counter() - t0 < a:
                     ds.check(ds.dialsort_server_poll(srv)[0])
@@ -529,20 +540,24 @@ def run_serve_workload(ds, hip, num, loads, batch_cfg, arena_gib=8):
             while outstanding:
                 ds.check(ds.dialsort_server_poll(srv)[0])
                 retire_front()
-                if outstanding:
-                    ds.check(ds.dialsort_server_drain(srv))
+            # after the replay: every served request's H and output
+            for rid, k, r in zip(ids, keys, reqs):
+                _, _, hp, op = infos[rid]
+                ok = ok and verify_sort(k, r.spec.U, ds.arena_view(arena, hp, r.spec.U),
+                                        ds.arena_view(arena, op, r.spec.n))
+                ds.check(ds.dialsort_server_release(srv, rid))
         finally:
             ds.check(ds.dialsort_server_destroy(srv))
-        slat = [infos[i][2] - infos[i][0] for i in ids]
-        launches = sorted(set(round(infos[i][1], 6) for i in ids))
-        first_sub = min(infos[i][0] for i in ids)
-        last_done = max(infos[i][2] for i in ids)
-        served = {"keys_per_s": nkeys / ((last_done - first_sub) * 1e-3), "p50_ms": percentile(slat, 50),
-                  "p99_ms": percentile(slat, 99), "mean_ms": statistics.mean(slat), "launches": len(launches),
-                  "mean_requests_per_launch": num / max(len(launches), 1)}
+        slat = [infos[i][1] - (t0s + a * 1e3) for i, a in zip(ids, arrivals)]
+        launches = sorted(set(round(infos[i][0], 6) for i in ids))
+        last_seen = max(infos[i][1] for i in ids)
+        served = {"keys_per_s": nkeys / ((last_seen - t0s) * 1e-3), "p50_ms": percentile(slat, 50),
+                  "p99_ms": percentile(slat, 99), "mean_ms": statistics.mean(slat),
+                  "span_s": (last_seen - t0s) * 1e-3, "launches": len(launches),
+                  "mean_requests_per_launch": num / max(len(launches), 1), "verified": bool(ok)}
         log(f"serve L={load}: serial p50 {serial['p50_ms']:.3f} p99 {serial['p99_ms']:.3f} ms "
             f"{serial['keys_per_s'] / 1e9:.1f} Gkeys/s; served p50 {served['p50_ms']:.3f} p99 {served['p99_ms']:.3f} ms "
-            f"{served['keys_per_s'] / 1e9:.1f} Gkeys/s, {len(launches)} launches")
+            f"{served['keys_per_s'] / 1e9:.1f} Gkeys/s, {len(launches)} launches, verified={ok}")
         res["loads"][str(load)] = {"rate_per_s": rate, "serial_plain": serial, "served": served}
     del H, out, ws, arena, keys
     torch.cuda.empty_cache()
@@ -754,31 +769,47 @@ def run_windows_workload(ds, K, W, count=64, wn=1 << 20, U=1 << 16):
     return res
 
 
-def cpu_baseline(kh, U, budget_s=12.0, max_runs=5):
-    """The oracle as it stands, on this host, on the same keys (sequential C)."""
+def cpu_model():
+    import platform
+
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return model
+
+
+def cpu_baseline(kh, U, warmup=3, runs=7):
+    """The oracle as it stands, on this host, on the same keys (sequential C,
+    one thread): the paper's protocol (Sec. 8.1) -- `warmup` untimed runs, then
+    `runs` timed ones; best (the value), median and coefficient of variation."""
     import oracle
 
     n = kh.size
     times = []
-    t_start = time.perf_counter()
-    while len(times) < max_runs and (not times or time.perf_counter() - t_start < budget_s):
+    for i in range(warmup + runs):
         t = time.perf_counter()
         st, H, out = oracle.sort(kh, U)
-        times.append(time.perf_counter() - t)
+        dt = time.perf_counter() - t
         assert st == oracle.OK
-    best = min(times)
+        if i >= warmup:
+            times.append(dt)
+    best, med = min(times), statistics.median(times)
+    cv = statistics.pstdev(times) / statistics.mean(times)
     return {"value": n / best, "unit": "keys/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle.sort on the full workload (n={n}, U={U}), best of {len(times)} runs",
-            "best_s": best}
+            "sample": f"oracle.sort on the full workload (n={n}, U={U}): {warmup} warmups, best of {runs}",
+            "best_s": best, "median_s": med, "cv": cv, "cpu_model": cpu_model(), "nproc": os.cpu_count()}
 
 
-def cpu_parallel_baseline(kh, U, warmup=1, runs=5):
+def cpu_parallel_baseline(kh, U, warmup=3, runs=7):
     """The CPU-parallel baseline (private per-thread histograms, merge, projection
     by bin ranges) on all the host threads this process may use, on the same
-    keys: best and median of `runs` after `warmup`, verified against the
-    GPU-independent oracle's histogram."""
-    import platform
-
+    keys: best, median and CV of `runs` after `warmup` (Sec. 8.1's protocol),
+    verified against the GPU-independent oracle's histogram."""
     import numpy as np
 
     import oracle
@@ -796,19 +827,11 @@ def cpu_parallel_baseline(kh, U, warmup=1, runs=5):
     st, H_ref = oracle.histogram(kh, U)
     ok = bool(st == oracle.OK and np.array_equal(H, H_ref) and out.size == kh.size
               and bool(np.all(out[1:] >= out[:-1])))
-    model = platform.processor() or ""
-    try:
-        with open("/proc/cpuinfo") as f:
-            for line in f:
-                if line.startswith("model name"):
-                    model = line.split(":", 1)[1].strip()
-                    break
-    except OSError:
-        pass
     best = min(times)
-    return {"value": kh.size / best, "unit": "keys/s", "cores": T, "nproc": os.cpu_count(), "cpu_model": model,
+    return {"value": kh.size / best, "unit": "keys/s", "cores": T, "nproc": os.cpu_count(), "cpu_model": cpu_model(),
             "kind": "cpu-parallel baseline (oracle/cpu_parallel.c)", "best_s": best,
-            "median_s": statistics.median(times), "runs": runs, "verified": ok,
+            "median_s": statistics.median(times), "cv": statistics.pstdev(times) / statistics.mean(times),
+            "warmup": warmup, "runs": runs, "verified": ok,
             "sample": f"full workload (n={kh.size}, U={U}), histogram and sorted output"}
 
 
@@ -818,8 +841,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workloads", default="large,hist,query,plain,skewed,transforms,windows,radix,batch,serve")
-    ap.add_argument("--serve-requests", type=int, default=400)
-    ap.add_argument("--serve-loads", default="0.7,1.5,3.0",
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-loads", default="0.5,0.7,0.9,1.2",
                     help="arrival rates, as multiples of 1 / (mean serial service time)")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")

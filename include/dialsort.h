@@ -136,10 +136,11 @@ dialsort_status dialsort_histogram_accumulate(const uint32_t *keys, uint64_t n, 
  * histogram is reused only after its previous window's projection.  H holds
  * 2U counters; on completion it holds the histograms of the last two windows.
  * keys, out and H must not overlap (out == keys is EINVAL here).  Passing the
- * same stream twice gives the serial order.  Work already on `ingest` or
- * `project` is not ordered against the other stream: order it with an event if
- * it produces the keys.  Completion of everything is ordered before later work
- * on `project`.  The workspace (dialsort_windows_workspace_bytes) holds the
+ * same stream twice gives the serial order.  The first ingestion waits for
+ * the work already on `project` (so a previous call's projections, which read
+ * the same H and workspace, finish first); work already on `ingest` is not
+ * ordered against `project`: order it with an event if it produces the keys.
+ * Completion of everything is ordered before later work on `project`.  The workspace (dialsort_windows_workspace_bytes) holds the
  * combined device status read by dialsort_status_sync(ws, project): a key >= U
  * in any window is ERANGE. */
 size_t dialsort_windows_workspace_bytes(uint64_t window_n, uint64_t U);
@@ -311,7 +312,14 @@ typedef struct dialsort_request_info {
     double submit_ms;        /* times in ms since dialsort_server_create: submission, */
     double launch_ms;        /* launch of its batch (host clock) and end of its batch */
     double done_ms;          /* on the device (event clock) */
+    double seen_ms;          /* host clock: when a poll or drain first found its batch
+                                finished (the time a caller can observe completion;
+                                comparable with submit_ms and dialsort_server_now_ms) */
 } dialsort_request_info;
+
+/* The server's host clock: ms since dialsort_server_create, the clock of
+ * submit_ms, launch_ms and seen_ms.  Returns -1 for a null server. */
+double dialsort_server_now_ms(const dialsort_server *server);
 
 /* Arena bytes a request of this size holds from admission to release. */
 size_t dialsort_server_footprint(uint64_t n, uint64_t U);

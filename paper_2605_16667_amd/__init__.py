@@ -54,7 +54,7 @@ class dialsort_server_config(ctypes.Structure):
 class dialsort_request_info(ctypes.Structure):
     _fields_ = [("state", ctypes.c_uint32), ("status", ctypes.c_int), ("H", ctypes.c_void_p), ("out", ctypes.c_void_p),
                 ("n", ctypes.c_uint64), ("U", ctypes.c_uint64), ("submit_ms", ctypes.c_double),
-                ("launch_ms", ctypes.c_double), ("done_ms", ctypes.c_double)]
+                ("launch_ms", ctypes.c_double), ("done_ms", ctypes.c_double), ("seen_ms", ctypes.c_double)]
 
 
 DIALSORT_REQ_QUEUED, DIALSORT_REQ_ADMITTED, DIALSORT_REQ_RUNNING, DIALSORT_REQ_DONE = range(4)
@@ -92,6 +92,7 @@ def _load() -> ctypes.CDLL:
                                       ctypes.c_uint32, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_double)]),
         "dialsort_server_footprint": (sz, [u64, u64]),
+        "dialsort_server_now_ms": (ctypes.c_double, [p]),
         "dialsort_server_create": (st, [p, sz, ctypes.POINTER(dialsort_server_config), ctypes.POINTER(p)]),
         "dialsort_server_destroy": (st, [p]),
         "dialsort_server_submit": (st, [p, p, u64, u64, ctypes.POINTER(u64)]),
@@ -127,7 +128,7 @@ EXPORTED = ("dialsort_workspace_bytes", "dialsort_histogram", "dialsort_histogra
             "dialsort_reconstruct", "dialsort_sort",
             "dialsort_batched_workspace_bytes", "dialsort_sort_batched", "dialsort_sort_each",
             "dialsort_batch_prepare", "dialsort_batch_launch", "dialsort_batch_autotune",
-            "dialsort_batch_default_config", "dialsort_batch_times", "dialsort_server_footprint",
+            "dialsort_batch_default_config", "dialsort_batch_times", "dialsort_server_footprint", "dialsort_server_now_ms",
             "dialsort_server_create", "dialsort_server_destroy", "dialsort_server_submit", "dialsort_server_poll",
             "dialsort_server_drain", "dialsort_server_info", "dialsort_server_release", "dialsort_status_sync",
             "dialsort_result_total", "dialsort_strerror", "dialsort_last_hip_error",
@@ -145,6 +146,11 @@ def _ptr(t: Optional[torch.Tensor]):
     if t.numel() and not t.is_contiguous():
         raise ValueError("dialsort tensors must be contiguous")
     return t.data_ptr() if t.numel() else None
+
+
+def _w(size: int, *ts) -> bool:
+    """True when every given tensor (None skipped) has elements of `size` bytes."""
+    return all(t is None or t.element_size() == size for t in ts)
 
 
 def _stream(stream) -> Optional[int]:
@@ -176,17 +182,23 @@ def workspace(nbytes: int, device="cuda") -> torch.Tensor:
 
 
 def dialsort_histogram(keys: torch.Tensor, U: int, H: torch.Tensor, ws: torch.Tensor, stream=None) -> int:
+    if not _w(4, keys, H) or H.numel() < U:
+        return DIALSORT_EINVAL
     return _lib.dialsort_histogram(_ptr(keys), keys.numel(), U, _ptr(H), _ptr(ws), ws.numel(), _stream(stream))
 
 
 def dialsort_histogram_accumulate(keys: torch.Tensor, U: int, H: torch.Tensor, ws: torch.Tensor,
                                   stream=None) -> int:
+    if not _w(4, keys, H) or H.numel() < U:
+        return DIALSORT_EINVAL
     return _lib.dialsort_histogram_accumulate(_ptr(keys), keys.numel(), U, _ptr(H), _ptr(ws), ws.numel(),
                                               _stream(stream))
 
 
 def dialsort_histogram_offset(keys: torch.Tensor, lo: int, U: int, H: torch.Tensor, ws: torch.Tensor,
                               stream=None) -> int:
+    if not _w(4, keys, H) or H.numel() < U:
+        return DIALSORT_EINVAL
     return _lib.dialsort_histogram_offset(_ptr(keys), keys.numel(), lo & 0xFFFFFFFF, U, _ptr(H), _ptr(ws),
                                           ws.numel(), _stream(stream))
 
@@ -194,7 +206,7 @@ def dialsort_histogram_offset(keys: torch.Tensor, lo: int, U: int, H: torch.Tens
 def dialsort_sort_offset(keys: torch.Tensor, lo: int, U: int, H: torch.Tensor, out: torch.Tensor,
                          ws: torch.Tensor, stream=None) -> int:
     """Keys in [lo, lo + U) (mod 2^32); lo may be given as a signed int32."""
-    if out.numel() < keys.numel():
+    if not _w(4, keys, H, out) or out.numel() < keys.numel() or H.numel() < U:
         return DIALSORT_EINVAL
     return _lib.dialsort_sort_offset(_ptr(keys), keys.numel(), lo & 0xFFFFFFFF, U, _ptr(H), _ptr(out), _ptr(ws),
                                      ws.numel(), _stream(stream))
@@ -203,7 +215,7 @@ def dialsort_sort_offset(keys: torch.Tensor, lo: int, U: int, H: torch.Tensor, o
 def dialsort_sort_lut(keys: torch.Tensor, U: int, lut: torch.Tensor, H: torch.Tensor, out: torch.Tensor,
                       ws: torch.Tensor, stream=None) -> int:
     """Indices in [0, U); out receives lut[k] for the indices in order."""
-    if out.numel() < keys.numel() or lut.numel() < U or lut.element_size() != 4:
+    if not _w(4, keys, H, out, lut) or out.numel() < keys.numel() or lut.numel() < U or H.numel() < U:
         return DIALSORT_EINVAL
     return _lib.dialsort_sort_lut(_ptr(keys), keys.numel(), U, _ptr(lut), _ptr(H), _ptr(out), _ptr(ws), ws.numel(),
                                   _stream(stream))
@@ -217,7 +229,8 @@ def dialsort_sort_windows(keys: torch.Tensor, window_n: int, count: int, U: int,
                           ws: torch.Tensor, ingest_stream=None, project_stream=None) -> int:
     """Tumbling windows of window_n keys: window w's ingestion on ingest_stream
     overlaps window w - 1's projection on project_stream.  H holds 2U counters."""
-    if keys.numel() < window_n * count or out.numel() < window_n * count or H.numel() < 2 * U:
+    if not _w(4, keys, H, out) or keys.numel() < window_n * count or out.numel() < window_n * count \
+            or H.numel() < 2 * U:
         return DIALSORT_EINVAL
     return _lib.dialsort_sort_windows(_ptr(keys), window_n, count, U, _ptr(H), _ptr(out), _ptr(ws), ws.numel(),
                                       _stream(ingest_stream), _stream(project_stream))
@@ -225,14 +238,14 @@ def dialsort_sort_windows(keys: torch.Tensor, window_n: int, count: int, U: int,
 
 def dialsort_key_range(keys: torch.Tensor, minmax: torch.Tensor, is_signed: bool = False, stream=None) -> int:
     """minmax[0] = min, minmax[1] = max of the keys (two 32-bit device words)."""
-    if minmax.numel() * minmax.element_size() < 8:
+    if not _w(4, keys) or minmax.numel() * minmax.element_size() < 8:
         return DIALSORT_EINVAL
     return _lib.dialsort_key_range(_ptr(keys), keys.numel(), int(bool(is_signed)), _ptr(minmax), _stream(stream))
 
 
 def dialsort_sort(keys: torch.Tensor, U: int, H: torch.Tensor, out: torch.Tensor, ws: torch.Tensor,
                   stream=None) -> int:
-    if out.numel() < keys.numel():
+    if not _w(4, keys, H, out) or out.numel() < keys.numel() or H.numel() < U:
         return DIALSORT_EINVAL
     return _lib.dialsort_sort(_ptr(keys), keys.numel(), U, _ptr(H), _ptr(out), _ptr(ws), ws.numel(),
                               _stream(stream))
@@ -241,15 +254,19 @@ def dialsort_sort(keys: torch.Tensor, U: int, H: torch.Tensor, out: torch.Tensor
 def dialsort_reconstruct(H: torch.Tensor, out: torch.Tensor, ws: torch.Tensor, out_cap: Optional[int] = None,
                          stream=None) -> int:
     cap = out.numel() if out_cap is None else int(out_cap)
-    if cap > out.numel():
+    if not _w(4, H, out) or cap > out.numel():
         return DIALSORT_EINVAL
     return _lib.dialsort_reconstruct(_ptr(H), H.numel(), _ptr(out), cap, _ptr(ws), ws.numel(), _stream(stream))
 
 
 def make_descs(arrays: Sequence[Tuple[torch.Tensor, int, torch.Tensor, torch.Tensor]]):
-    """(keys, U, H, out) tuples -> a ctypes array of dialsort_desc."""
+    """(keys, U, H, out) tuples -> a ctypes array of dialsort_desc.  Raises
+    DialSortError(DIALSORT_EINVAL) for keys, H or out without 4-byte elements,
+    an H shorter than U or an out shorter than the keys."""
     descs = (dialsort_desc * max(len(arrays), 1))()
     for i, (k, U, H, o) in enumerate(arrays):
+        if not _w(4, k, H, o) or H.numel() < U or o.numel() < k.numel():
+            raise DialSortError(DIALSORT_EINVAL)
         descs[i] = dialsort_desc(_ptr(k), k.numel(), U, _ptr(H), _ptr(o))
     return descs
 
@@ -325,12 +342,18 @@ def dialsort_server_create(arena: torch.Tensor, config: dialsort_server_config) 
     return st, h.value
 
 
+def dialsort_server_now_ms(server: int) -> float:
+    return _lib.dialsort_server_now_ms(server)
+
+
 def dialsort_server_destroy(server: int) -> int:
     return _lib.dialsort_server_destroy(server)
 
 
 def dialsort_server_submit(server: int, keys: torch.Tensor, U: int) -> Tuple[int, int]:
     rid = ctypes.c_uint64(0)
+    if not _w(4, keys):
+        return DIALSORT_EINVAL, 0
     st = _lib.dialsort_server_submit(server, _ptr(keys), keys.numel(), U, ctypes.byref(rid))
     return st, rid.value
 
@@ -391,13 +414,13 @@ def dialsort_launch_name(i: int) -> Optional[str]:
 
 
 def dialsort_query_frequency(H: torch.Tensor, U: int, q: torch.Tensor, out: torch.Tensor, stream=None) -> int:
-    if out.numel() < q.numel():
+    if not _w(4, H, q, out) or H.numel() < U or out.numel() < q.numel():
         return DIALSORT_EINVAL
     return _lib.dialsort_query_frequency(_ptr(H), U, _ptr(q), q.numel(), _ptr(out), _stream(stream))
 
 
 def dialsort_query_presence(H: torch.Tensor, U: int, q: torch.Tensor, out: torch.Tensor, stream=None) -> int:
-    if out.numel() < q.numel() or out.element_size() != 1:
+    if not _w(4, H, q) or H.numel() < U or out.numel() < q.numel() or out.element_size() != 1:
         return DIALSORT_EINVAL
     return _lib.dialsort_query_presence(_ptr(H), U, _ptr(q), q.numel(), _ptr(out), _stream(stream))
 
@@ -407,20 +430,20 @@ def dialsort_prefix_workspace_bytes(U: int) -> int:
 
 
 def dialsort_prefix(H: torch.Tensor, U: int, P: torch.Tensor, ws: torch.Tensor, stream=None) -> int:
-    if P.numel() < U + 1 or P.element_size() != 8:
+    if not _w(4, H) or H.numel() < U or P.numel() < U + 1 or P.element_size() != 8:
         return DIALSORT_EINVAL
     return _lib.dialsort_prefix(_ptr(H), U, _ptr(P), _ptr(ws), ws.numel(), _stream(stream))
 
 
 def dialsort_query_range_count(P: torch.Tensor, U: int, a: torch.Tensor, b: torch.Tensor, out: torch.Tensor,
                                stream=None) -> int:
-    if b.numel() != a.numel() or out.numel() < a.numel():
+    if not _w(8, P, a, b, out) or P.numel() < U + 1 or b.numel() != a.numel() or out.numel() < a.numel():
         return DIALSORT_EINVAL
     return _lib.dialsort_query_range_count(_ptr(P), U, _ptr(a), _ptr(b), a.numel(), _ptr(out), _stream(stream))
 
 
 def dialsort_query_select(P: torch.Tensor, U: int, r: torch.Tensor, out: torch.Tensor, stream=None) -> int:
-    if out.numel() < r.numel():
+    if not _w(8, P, r) or not _w(4, out) or P.numel() < U + 1 or out.numel() < r.numel():
         return DIALSORT_EINVAL
     return _lib.dialsort_query_select(_ptr(P), U, _ptr(r), r.numel(), _ptr(out), _stream(stream))
 
@@ -434,7 +457,7 @@ def dialsort_radix_workspace_bytes(n: int) -> int:
 
 def dialsort_sort_radix(keys: torch.Tensor, out: torch.Tensor, ws: torch.Tensor, is_signed: bool = False,
                         stream=None) -> int:
-    if out.numel() < keys.numel():
+    if not _w(4, keys, out) or out.numel() < keys.numel():
         return DIALSORT_EINVAL
     return _lib.dialsort_sort_radix(_ptr(keys), keys.numel(), 1 if is_signed else 0, _ptr(out), _ptr(ws),
                                     ws.numel(), _stream(stream))

@@ -506,9 +506,13 @@ dialsort_status dialsort_sort_windows(const uint32_t* keys, uint64_t window_n, u
   L0.scan = false;
   DS_TRY(launch_init(base, L0, nullptr, 0, project));
   if (count == 0) return DIALSORT_OK;
-  hipEvent_t ev[4] = {};  // ingested[0], ingested[1], projected[0], projected[1]
+  // ingested[0], ingested[1], projected[0], projected[1], and the point on
+  // `project` where this call starts: the first two ingestions reuse the
+  // sub-workspaces and histograms that work enqueued earlier on `project` (a
+  // previous call's last projections) may still read
+  hipEvent_t ev[5] = {};
   dialsort_status st = DIALSORT_OK;
-  for (int i = 0; i < 4 && st == DIALSORT_OK; ++i) {
+  for (int i = 0; i < 5 && st == DIALSORT_OK; ++i) {
     const hipError_t e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
     if (e != hipSuccess) {
       g_last_hip_error = (int)e;
@@ -517,6 +521,8 @@ dialsort_status dialsort_sort_windows(const uint32_t* keys, uint64_t window_n, u
   }
   const Layout LR = plan(window_n, U, DIALSORT_MODE_RECONSTRUCT);
   auto run = [&]() -> dialsort_status {
+    DS_HIP(hipEventRecord(ev[4], project));
+    DS_HIP(hipStreamWaitEvent(ingest, ev[4], 0));
     for (uint32_t w = 0; w < count; ++w) {
       const int b = (int)(w & 1u);
       uint32_t* Hb = H + (uint64_t)b * U;
@@ -539,7 +545,7 @@ dialsort_status dialsort_sort_windows(const uint32_t* keys, uint64_t window_n, u
     return DIALSORT_OK;
   };
   if (st == DIALSORT_OK) st = run();
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 5; ++i)
     if (ev[i]) (void)hipEventDestroy(ev[i]);
   return st;
 }

@@ -100,7 +100,7 @@ struct Request {
   size_t h_off = 0, o_off = 0;
   uint32_t state = RQ_QUEUED;
   dialsort_status status = DIALSORT_OK;
-  double submit_ms = 0, launch_ms = 0, done_ms = 0;
+  double submit_ms = 0, launch_ms = 0, done_ms = 0, seen_ms = 0;
 };
 
 struct Slot {
@@ -142,6 +142,7 @@ struct dialsort_server {
 namespace {
 
 dialsort_status retire(dialsort_server* S) {
+  const double seen = S->now_ms();
   for (Slot& sl : S->slots) {
     if (!sl.busy) continue;
     const hipError_t q = hipEventQuery(sl.done);
@@ -164,6 +165,7 @@ dialsort_status retire(dialsort_server* S) {
       r.state = RQ_DONE;
       r.status = rs;
       r.done_ms = ms;
+      r.seen_ms = seen;
       --S->not_done;
     }
     sl.reqs.clear();
@@ -353,6 +355,8 @@ extern "C" {
 
 size_t dialsort_server_footprint(uint64_t n, uint64_t U) { return footprint(n, U); }
 
+double dialsort_server_now_ms(const dialsort_server* S) { return S ? S->now_ms() : -1.0; }
+
 dialsort_status dialsort_server_create(void* arena, size_t arena_bytes, const dialsort_server_config* config,
                                        dialsort_server** server) {
   if (!server || !arena || !config) return DIALSORT_EINVAL;
@@ -484,6 +488,7 @@ dialsort_status dialsort_server_info(dialsort_server* S, uint64_t id, dialsort_r
   info->submit_ms = r.submit_ms;
   info->launch_ms = r.launch_ms;
   info->done_ms = r.done_ms;
+  info->seen_ms = r.seen_ms;
   return DIALSORT_OK;
 }
 

@@ -150,3 +150,56 @@ def test_server_host_checks():
 def test_strerror():
     for s in range(6):
         assert ds.dialsort_strerror(s)
+
+
+def test_binding_rejects_short_or_narrow_tensors():
+    """The binding returns EINVAL before any call for H shorter than U, keys,
+    H or out without 4-byte elements, and P / query arguments of the wrong
+    width (CPU tensors: nothing reaches the library or the device)."""
+    import torch
+
+    k32 = torch.zeros(16, dtype=torch.int32)
+    k16 = torch.zeros(16, dtype=torch.int16)
+    k64 = torch.zeros(16, dtype=torch.int64)
+    H = torch.zeros(64, dtype=torch.int32)
+    ws = torch.zeros(16, dtype=torch.uint8)
+    E = ds.DIALSORT_EINVAL
+    U = 64
+    for f in (ds.dialsort_histogram, ds.dialsort_histogram_accumulate):
+        assert f(k32, U + 1, H, ws) == E            # H shorter than U
+        assert f(k16, U, H, ws) == E                # 2-byte keys
+        assert f(k32, U, H.view(torch.int16), ws) == E
+    assert ds.dialsort_histogram_offset(k32, 0, U + 1, H, ws) == E
+    assert ds.dialsort_histogram_offset(k64, 0, U, H, ws) == E
+    out = torch.zeros(16, dtype=torch.int32)
+    assert ds.dialsort_sort(k32, U + 1, H, out, ws) == E
+    assert ds.dialsort_sort(k16, U, H, out, ws) == E
+    assert ds.dialsort_sort(k32, U, H, out.view(torch.int16)[:16], ws) == E
+    assert ds.dialsort_sort(k32, U, H, torch.zeros(8, dtype=torch.int32), ws) == E
+    assert ds.dialsort_sort_offset(k32, 0, U + 1, H, out, ws) == E
+    assert ds.dialsort_sort_offset(k64, 0, U, H, out, ws) == E
+    lut = torch.zeros(U, dtype=torch.int32)
+    assert ds.dialsort_sort_lut(k32, U, lut, torch.zeros(U - 1, dtype=torch.int32), out, ws) == E
+    assert ds.dialsort_sort_lut(k32, U, lut.to(torch.int64), H, out, ws) == E
+    assert ds.dialsort_sort_windows(k16, 8, 2, U, torch.zeros(2 * U, dtype=torch.int32), out, ws) == E
+    assert ds.dialsort_key_range(k16, torch.zeros(2, dtype=torch.int32)) == E
+    assert ds.dialsort_reconstruct(H.view(torch.int16), out, ws) == E
+    assert ds.dialsort_reconstruct(H, out.to(torch.int64), ws) == E
+    assert ds.dialsort_sort_radix(k16, out, ws) == E
+    # queries: H width and length, P / a / b / r as 8-byte words
+    q = torch.zeros(4, dtype=torch.int32)
+    assert ds.dialsort_query_frequency(H, U + 1, q, q.clone()) == E
+    assert ds.dialsort_query_frequency(H, U, q.to(torch.int16), q.clone()) == E
+    assert ds.dialsort_query_presence(H[:U - 1], U, q, torch.zeros(4, dtype=torch.uint8)) == E
+    P = torch.zeros(U + 1, dtype=torch.int64)
+    assert ds.dialsort_prefix(H[:U - 1], U, P, ws) == E
+    a = torch.zeros(4, dtype=torch.int64)
+    assert ds.dialsort_query_range_count(P, U, a.to(torch.int32), a, a.clone()) == E
+    assert ds.dialsort_query_range_count(P[:U], U, a, a, a.clone()) == E
+    assert ds.dialsort_query_select(P, U, a.to(torch.int32), q) == E
+    assert ds.dialsort_query_select(P, U, a, a.clone()) == E
+    # the batched descriptor table refuses the same
+    with pytest.raises(ds.DialSortError):
+        ds.make_descs([(k32, U + 1, H, out)])
+    with pytest.raises(ds.DialSortError):
+        ds.make_descs([(k16, U, H, out)])

@@ -257,3 +257,58 @@ def test_queries_on_resident_histograms(ds):
             ds.check(ds.dialsort_server_release(srv, rid))
     finally:
         ds.check(ds.dialsort_server_destroy(srv))
+
+
+def test_served_upper_sizes_match_the_oracle(ds):
+    """The served workload's upper request sizes through one server: eight
+    requests of n = 2^24 keys (U in {2^20, 2^24}, uniform and Zipf(1.2)) mixed
+    with 24 small ones, submitted in two waves so that the second arrives while
+    the first is on the device.  Every request's H and output must equal the
+    oracle's (Sec. 3.3, Eqs. (1) and (2)), element by element."""
+    big = []
+    for j, (U, dist) in enumerate([(1 << 20, "uniform"), (1 << 24, "uniform"), (1 << 20, "zipf"), (1 << 24, "zipf")] * 2):
+        spec = w.ArraySpec(1 << 24, U, dist, 1.2, w.BASE_SEED + 900 + j)
+        big.append((w.as_u32(spec.keys()), U))
+    small = small_stream(24, seed_shift=5)
+    mix = []
+    for i in range(len(small)):
+        mix.append(small[i])
+        if i % 3 == 1:
+            mix.append(big[i // 3])
+    assert sum(1 for k, _ in mix if k.size == 1 << 24) == 8
+    dev_keys = [torch.from_numpy(k.view(np.int32)).to(DEV) for k, _ in mix]
+    torch.cuda.synchronize()
+    arena, srv = make_server(ds, 6 << 30, max_inflight=2, max_batch=64)
+    try:
+        ids = []
+        half = len(mix) // 2
+        say(f"served mix: {len(mix)} requests, 8 of n=2^24, first wave of {half}")
+        for i in range(half):
+            st, rid = ds.dialsort_server_submit(srv, dev_keys[i], mix[i][1])
+            ds.check(st)
+            ids.append(rid)
+        ds.check(ds.dialsort_server_poll(srv)[0])
+        say("second wave, submitted while the first runs")
+        for i in range(half, len(mix)):
+            st, rid = ds.dialsort_server_submit(srv, dev_keys[i], mix[i][1])
+            ds.check(st)
+            ids.append(rid)
+            if i % 4 == 0:
+                ds.check(ds.dialsort_server_poll(srv)[0])
+        ds.check(ds.dialsort_server_drain(srv))
+        per_launch = {}
+        for (kh, U), rid in zip(mix, ids):
+            info, H, out = result(ds, arena, srv, rid)
+            say(f"request {rid}: n={kh.size} U={U}")
+            assert info.status == ds.DIALSORT_OK
+            per_launch.setdefault(round(info.launch_ms, 6), []).append(kh.size)
+            st_o, Hr, outr = oracle.sort(kh, U)
+            assert st_o == oracle.OK
+            assert np.array_equal(w.as_u32(H), Hr), f"H of request {rid}"
+            assert np.array_equal(w.as_u32(out), outr), f"output of request {rid}"
+            assert info.seen_ms >= info.submit_ms
+            ds.check(ds.dialsort_server_release(srv, rid))
+        # some fused launch carried a request of 2^24 keys together with others
+        assert any(len(v) > 1 and max(v) == 1 << 24 for v in per_launch.values())
+    finally:
+        ds.check(ds.dialsort_server_destroy(srv))

@@ -85,3 +85,38 @@ def test_windows_argument_errors(ds):
     out = torch.empty_like(kd)
     assert ds.dialsort_sort_windows(kd, wn, 3, U, H, out, small) == ds.DIALSORT_EWORKSPACE
     assert ds.dialsort_sort_windows(kd, wn, 3, U, H[:U], out, ws) == ds.DIALSORT_EINVAL  # H holds 2U
+
+
+def test_back_to_back_calls_without_sync(ds):
+    """Two calls on the same H and workspace, issued one after the other with
+    no host synchronisation: the second call's first ingestions wait for the
+    first call's last projections, so both calls' outputs are the oracle's."""
+    U, wn, count = 1 << 16, 400_003, 3
+    rng = np.random.default_rng(29)
+    k1 = rng.integers(0, U, wn * count).astype(np.uint32)
+    k2 = rng.integers(0, U, wn * count).astype(np.uint32)
+    k2[:wn // 2] = 5  # a hot key in the second call's first window
+    d1 = torch.from_numpy(k1.view(np.int32).copy()).to(DEV)
+    d2 = torch.from_numpy(k2.view(np.int32).copy()).to(DEV)
+    H = torch.full((2 * U,), -1, dtype=torch.int32, device=DEV)
+    o1 = torch.full((wn * count,), -1, dtype=torch.int32, device=DEV)
+    o2 = torch.full((wn * count,), -1, dtype=torch.int32, device=DEV)
+    ws = ds.workspace(ds.dialsort_windows_workspace_bytes(wn, U))
+    torch.cuda.synchronize()
+    ingest = torch.cuda.Stream(device=DEV)
+    project = torch.cuda.Stream(device=DEV)
+    say(f"two window calls back to back U={U} window_n={wn} count={count}")
+    ds.check(ds.dialsort_sort_windows(d1, wn, count, U, H, o1, ws, ingest, project))
+    ds.check(ds.dialsort_sort_windows(d2, wn, count, U, H, o2, ws, ingest, project))
+    assert ds.dialsort_status_sync(ws, project) == ds.DIALSORT_OK
+    torch.cuda.synchronize()
+    out1, out2, Hh = w.as_u32(o1), w.as_u32(o2), w.as_u32(H)
+    for keys, out in ((k1, out1), (k2, out2)):
+        for k in range(count):
+            st_o, _, out_ref = oracle.sort(keys[k * wn:(k + 1) * wn], U)
+            assert st_o == oracle.OK
+            assert np.array_equal(out[k * wn:(k + 1) * wn], out_ref), f"window {k}"
+    for k in (count - 2, count - 1):
+        _, H_ref, _ = oracle.sort(k2[k * wn:(k + 1) * wn], U)
+        b = k % 2
+        assert np.array_equal(Hh[b * U:(b + 1) * U], H_ref), f"histogram of window {k}"
