@@ -326,8 +326,8 @@ size_t dialsort_server_footprint(uint64_t n, uint64_t U);
 
 /* Creates a server on the current device.  arena: device memory owned by the
  * caller, kept allocated until dialsort_server_destroy returns.  Creates
- * max_inflight streams and events; pinned host staging is allocated on first
- * use and grown when a batch's tables need more. */
+ * max_inflight streams and events, and 4 MiB of pinned host staging per
+ * stream (grown, while its stream is idle, when a batch's tables need more). */
 dialsort_status dialsort_server_create(void *arena, size_t arena_bytes, const dialsort_server_config *config,
                                        dialsort_server **server);
 

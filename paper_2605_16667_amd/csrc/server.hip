@@ -375,6 +375,9 @@ dialsort_status dialsort_server_create(void* arena, size_t arena_bytes, const di
   for (Slot& sl : S->slots) {
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreate(&sl.done);
+    // pinned staging now: a first allocation inside a launch would stall the
+    // requests queued behind it
+    if (e == hipSuccess && ensure_pinned(sl, 1) != DIALSORT_OK) e = hipErrorOutOfMemory;
   }
   if (e == hipSuccess) e = hipEventCreate(&S->t0);
   if (e == hipSuccess) e = hipEventRecord(S->t0, S->slots[0].stream);

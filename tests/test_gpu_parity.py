@@ -246,3 +246,21 @@ def test_batched_equals_single(ds):
         assert st == oracle.OK
         assert np.array_equal(w.as_u32(H), H_ref)
         assert np.array_equal(w.as_u32(o), out_ref)
+
+
+@pytest.mark.parametrize("U", [1000, 4096, 40001, 65536])
+def test_changing_hot_keys(ds, U):
+    """Runs of different hot keys one after another, three hot keys shuffled
+    together, and an alternating pair: the wave's candidate counts are replaced
+    (flushed) many times and reach the flush threshold, on every LDS path."""
+    rng = np.random.default_rng(U + 31)
+    blocks = []
+    for j in range(12):  # 12 runs of ~350K keys, each mostly one key
+        b = rng.integers(0, U, 350_001).astype(np.uint32)
+        b[rng.random(b.size) < 0.8] = (j * 7919) % U
+        blocks.append(b)
+    three = np.array([3 % U, (U // 2) | 1, U - 1], dtype=np.uint32)[rng.integers(0, 3, 1_500_000)]
+    alt = np.tile(np.array([1 % U, (U - 2) % U], dtype=np.uint32), 400_000)
+    keys = np.concatenate(blocks + [three, alt])
+    assert_parity(ds, keys, U, label="changing hot keys")
+    assert_parity(ds, keys, U, mode="hist", label="changing hot keys")
