@@ -447,6 +447,24 @@ size_t dialsort_radix_workspace_bytes(uint64_t n);
 dialsort_status dialsort_sort_radix(const uint32_t *keys, uint64_t n, int is_signed, uint32_t *out, void *ws,
                                     size_t ws_bytes, hipStream_t stream);
 
+/* ---- Sorting without any allocation -----------------------------------------
+ *
+ * For callers that cannot allocate device memory or pass a workspace (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * dialsort_sort with the workspace taken from a 64 MiB array that the library
+ * holds on each device from its load until the process ends.  Same arguments,
+ * results and in-place rule as dialsort_sort, without ws; a sort whose
+ * dialsort_workspace_bytes(n, U, DIALSORT_MODE_SORT) exceeds 64 MiB returns
+ * EWORKSPACE before anything is enqueued.  status (device memory, 4-byte aligned,
+ * may be null): receives the call's device status word once the sort has run
+ * (0 = OK; bit 0 set = a key >= U, as ERANGE from dialsort_status_sync).
+ * Nothing is allocated: no hipMalloc or hipFree, no allocating library routine.
+ * Every call on a device shares that device's array and clears what must start
+ * at zero; calls that overlap on one device (different streams, or threads
+ * without ordering between their streams) race and give undefined results. */
+dialsort_status dialsort_sort_noalloc(const uint32_t *keys, uint64_t n, uint64_t U, uint32_t *H, uint32_t *out,
+                                      uint32_t *status, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -112,6 +112,7 @@ def _load() -> ctypes.CDLL:
         "dialsort_prefix": (st, [p, u64, p, p, sz, p]),
         "dialsort_query_range_count": (st, [p, u64, p, p, u64, p, p]),
         "dialsort_query_select": (st, [p, u64, p, u64, p, p]),
+        "dialsort_sort_noalloc": (st, [p, u64, u64, p, p, p, p]),
         "dialsort_radix_workspace_bytes": (sz, [u64]),
         "dialsort_sort_radix": (st, [p, u64, ctypes.c_int, p, p, sz, p]),
     }
@@ -135,7 +136,7 @@ EXPORTED = ("dialsort_workspace_bytes", "dialsort_histogram", "dialsort_histogra
             "dialsort_set_launch_events", "dialsort_launch_name", "dialsort_query_frequency",
             "dialsort_query_presence", "dialsort_prefix_workspace_bytes", "dialsort_prefix",
             "dialsort_query_range_count", "dialsort_query_select", "dialsort_radix_workspace_bytes",
-            "dialsort_sort_radix")
+            "dialsort_sort_radix", "dialsort_sort_noalloc")
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -249,6 +250,18 @@ def dialsort_sort(keys: torch.Tensor, U: int, H: torch.Tensor, out: torch.Tensor
         return DIALSORT_EINVAL
     return _lib.dialsort_sort(_ptr(keys), keys.numel(), U, _ptr(H), _ptr(out), _ptr(ws), ws.numel(),
                               _stream(stream))
+
+
+def dialsort_sort_noalloc(keys: torch.Tensor, U: int, H: torch.Tensor, out: torch.Tensor,
+                          status: Optional[torch.Tensor] = None, stream=None) -> int:
+    """dialsort_sort with the library's own per-device workspace (nothing is
+    allocated); status: an optional one-word device tensor for the status word."""
+    if not _w(4, keys, H, out, status) or out.numel() < keys.numel() or H.numel() < U:
+        return DIALSORT_EINVAL
+    if status is not None and status.numel() < 1:
+        return DIALSORT_EINVAL
+    return _lib.dialsort_sort_noalloc(_ptr(keys), keys.numel(), U, _ptr(H), _ptr(out), _ptr(status),
+                                      _stream(stream))
 
 
 def dialsort_reconstruct(H: torch.Tensor, out: torch.Tensor, ws: torch.Tensor, out_cap: Optional[int] = None,

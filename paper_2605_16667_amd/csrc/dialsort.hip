@@ -14,6 +14,8 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
+#include <vector>
 
 #include "../../include/dialsort.h"
 #include "common.hpp"
@@ -588,6 +590,63 @@ dialsort_status dialsort_result_total(const void* ws, hipStream_t stream, uint64
     g_last_hip_error = (int)e;
     return DIALSORT_EHIP;
   }
+  return DIALSORT_OK;
+}
+
+}  // extern "C"
+
+// ---- the allocation-free sort -----------------------------------------------
+// dialsort_sort_noalloc runs dialsort_sort's kernels with their workspace in
+// `scratch`, a device array of this library: each device holds its own copy
+// from module load until the process ends.  In host code the array's name is
+// only a stand-in; its device address comes from hipGetSymbolAddress, taken
+// once per device (with that device current) and kept.
+namespace {
+
+constexpr size_t NOALLOC_BYTES = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;  // per device ordinal
+
+dialsort_status scratch_of_current_device(void** p) {
+  int dev = 0;
+  DS_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((size_t)dev >= g_scratch_ptr.size()) g_scratch_ptr.resize((size_t)dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* q = nullptr;
+    DS_HIP(hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)));
+    if (!q) return DIALSORT_EHIP;
+    g_scratch_ptr[dev] = q;
+  }
+  *p = g_scratch_ptr[dev];
+  return DIALSORT_OK;
+}
+
+__global__ void k_copy_status(uint32_t* dst, const Ctl* src) {
+  if (threadIdx.x == 0) *dst = src->status;
+}
+
+}  // namespace
+
+extern "C" {
+
+dialsort_status dialsort_sort_noalloc(const uint32_t* keys, uint64_t n, uint64_t U, uint32_t* H, uint32_t* out,
+                                      uint32_t* status, hipStream_t stream) {
+  if (U == 0 || U > U_MAX || !H || (n && (!keys || !out))) return DIALSORT_EINVAL;
+  if (!aligned4(keys) || !aligned4(H) || !aligned4(out) || !aligned4(status)) return DIALSORT_EINVAL;
+  if (n > N_MAX) return DIALSORT_EOVERFLOW;
+  if (overlap(keys, n * 4, H, U * 4) || overlap(out, n * 4, H, U * 4)) return DIALSORT_EINVAL;
+  if (out != keys && overlap(keys, n * 4, out, n * 4)) return DIALSORT_EINVAL;
+  if (status && (overlap(status, 4, keys, n * 4) || overlap(status, 4, H, U * 4) || overlap(status, 4, out, n * 4)))
+    return DIALSORT_EINVAL;
+  if (dialsort_workspace_bytes(n, U, DIALSORT_MODE_SORT) > NOALLOC_BYTES) return DIALSORT_EWORKSPACE;
+  void* ws = nullptr;
+  DS_TRY(scratch_of_current_device(&ws));
+  CallScope scope(stream);
+  DS_TRY(run_sort(keys, n, U, 0, H, out, ws, DIALSORT_MODE_SORT, stream));
+  if (status) DS_LAUNCH(k_copy_status, dim3(1), dim3(64), stream, status, (const Ctl*)ws_base(ws));
   return DIALSORT_OK;
 }
 
