@@ -39,6 +39,8 @@ constexpr int FILL_CL2 = 11;  // fill items of at most 2048 positions (one wave 
 constexpr uint64_t FILL_NTS_BYTES = uint64_t(64) << 20;  // outputs from 64 MiB on use non-temporal stores
 constexpr int SCAN_NT = 256;
 constexpr uint64_t PART_NCU = 256;  // compute units of the target (MI355X)
+constexpr uint64_t DIRECT_NMAX = 1ull << 24;     // direct projection from the scan: at most this many keys,
+constexpr uint64_t DIRECT_PER_TILE = 1ull << 14;  // and at most this many per scan tile on average
 
 enum Kind { K_EMPTY, K_LDS32S, K_LDS32, K_LDS16, K_PART, K_GLOBAL, K_NONE };
 
@@ -52,6 +54,7 @@ struct Layout {
   bool rows_in_ws = false;
   uint64_t row_stride = 0;
   bool scan = false;     // full projection
+  bool direct = false;   // LDS paths, sort: the scan tiles write the output (no fill items)
   int scan_vpt = 16;
   uint64_t scan_tiles = 0;
   uint64_t limit = 0;
@@ -118,8 +121,14 @@ Layout plan(uint64_t n, uint64_t U, int mode) {
   // partitioned path projects bucket by bucket and needs no scan
   L.scan_vpt = (L.rows_in_ws && L.G >= 8) ? 1 : 16;
   L.scan_tiles = L.kind == K_PART ? 0 : cdiv(U, (uint64_t)SCAN_NT * L.scan_vpt);
+  // a sort whose scan tiles each hold few output positions writes the output
+  // from the scan itself: one launch and the fill items fewer
+  L.direct = mode == DIALSORT_MODE_SORT && (L.kind == K_LDS32S || L.kind == K_LDS32 || L.kind == K_LDS16) &&
+             n <= DIRECT_NMAX && n <= DIRECT_PER_TILE * L.scan_tiles;
   if (L.scan) {
     L.off_tile = off; off = align_up(off + L.scan_tiles * 8, ALIGN);
+  }
+  if (L.scan && !L.direct) {
     // one item per chunk of output positions, plus one per span boundary that
     // splits a chunk: spans are the scan tiles, or on the partitioned path the
     // projection tiles of PT_BINS bins and the buckets (two pieces for a bucket
@@ -235,10 +244,11 @@ dialsort_status launch_ingest(const uint32_t* keys, uint64_t n, uint64_t U, uint
   return DIALSORT_OK;
 }
 
-// k_scan over `rows` (nrows rows), writing H when H_out is set.
+// k_scan over `rows` (nrows rows), writing H when H_out is set.  With
+// L.direct (and full) the scan tiles write the sorted output themselves.
 dialsort_status launch_scan(const uint32_t* rows, uint32_t nrows, uint64_t row_stride, uint32_t* H_out,
                             uint64_t U, char* base, const Layout& L, bool full, int report_overflow,
-                            hipStream_t s) {
+                            hipStream_t s, uint32_t* out = nullptr, FillCfg fc = FillCfg{}) {
   Ctl* ctl = (Ctl*)base;
   uint64_t* tiles = (uint64_t*)(base + L.off_tile);
   FillItem* items = (FillItem*)(base + L.off_items);
@@ -246,17 +256,17 @@ dialsort_status launch_scan(const uint32_t* rows, uint32_t nrows, uint64_t row_s
   FillRun* runs = (FillRun*)(base + L.off_runs);
   const uint32_t rcap = (uint32_t)std::min<uint64_t>(L.run_cap, 0xFFFFFFF0ull);
   const dim3 grid((uint32_t)L.scan_tiles);
-  if (full) {
-    if (L.scan_vpt == 1)
-      DS_LAUNCH((k_scan<SCAN_NT, 1, true>), grid, dim3(SCAN_NT), s, rows, nrows, row_stride, H_out, U, ctl, tiles, items, icap, L.limit, FILL_CL2, report_overflow, runs, rcap);
-    else
-      DS_LAUNCH((k_scan<SCAN_NT, 16, true>), grid, dim3(SCAN_NT), s, rows, nrows, row_stride, H_out, U, ctl, tiles, items, icap, L.limit, FILL_CL2, report_overflow, runs, rcap);
+#define DS_SCAN(VPT, FULL, DIRECT)                                                                                  \
+  DS_LAUNCH((k_scan<SCAN_NT, VPT, FULL, DIRECT>), grid, dim3(SCAN_NT), s, rows, nrows, row_stride, H_out, U, ctl, \
+            tiles, items, icap, L.limit, FILL_CL2, report_overflow, runs, rcap, out, fc)
+  if (full && L.direct) {
+    if (L.scan_vpt == 1) DS_SCAN(1, true, true); else DS_SCAN(16, true, true);
+  } else if (full) {
+    if (L.scan_vpt == 1) DS_SCAN(1, true, false); else DS_SCAN(16, true, false);
   } else {
-    if (L.scan_vpt == 1)
-      DS_LAUNCH((k_scan<SCAN_NT, 1, false>), grid, dim3(SCAN_NT), s, rows, nrows, row_stride, H_out, U, ctl, tiles, items, icap, L.limit, FILL_CL2, report_overflow, runs, rcap);
-    else
-      DS_LAUNCH((k_scan<SCAN_NT, 16, false>), grid, dim3(SCAN_NT), s, rows, nrows, row_stride, H_out, U, ctl, tiles, items, icap, L.limit, FILL_CL2, report_overflow, runs, rcap);
+    if (L.scan_vpt == 1) DS_SCAN(1, false, false); else DS_SCAN(16, false, false);
   }
+#undef DS_SCAN
   return DIALSORT_OK;
 }
 
@@ -325,6 +335,16 @@ dialsort_status run_sort(const uint32_t* keys, uint64_t n, uint64_t U, uint32_t 
   if (mode == DIALSORT_MODE_HISTOGRAM) {
     if (L.rows_in_ws) DS_TRY(launch_scan(rows, nrows, L.row_stride, H, U, base, L, false, 0, s));
     return DIALSORT_OK;
+  }
+  if (L.direct) {
+    FillCfg fc;
+    fc.lo = lo;
+    fc.lut = lut;
+    fc.limit = n;
+    fc.oal = aligned16(out);
+    fc.nts = fc.oal && n * 4 >= FILL_NTS_BYTES;
+    return launch_scan(rows, nrows, L.rows_in_ws ? L.row_stride : 0, L.rows_in_ws ? H : nullptr, U, base, L, true, 0,
+                       s, out, fc);
   }
   if (L.kind != K_PART)
     DS_TRY(launch_scan(rows, nrows, L.rows_in_ws ? L.row_stride : 0, L.rows_in_ws ? H : nullptr, U, base, L,

@@ -24,6 +24,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "fill_window.hpp"
 
 namespace ds {
 
@@ -106,16 +107,21 @@ __device__ __forceinline__ uint64_t lookback(uint64_t* state, uint64_t t) {
 // NT threads, VPT bins per thread (tile = NT*VPT bins).
 // rows: nrows partial rows (row r at rows + r*row_stride); H_out receives their
 // sum when non-null.  FULL: also scan and build the chunk map (chunk = 2^CL2).
+// DIRECT (with FULL): instead of fill items, every tile writes its own runs
+// into out once its prefix is known (wave_fill; the counts must come from keys,
+// so that any sum of them fits 32 bits).
 // limit: number of output positions that may be written (n, or out_cap).
-template <int NT, int VPT, bool FULL>
+template <int NT, int VPT, bool FULL, bool DIRECT = false>
 __global__ __launch_bounds__(NT) void k_scan(const uint32_t* __restrict__ rows, uint32_t nrows, uint64_t row_stride,
                                              uint32_t* __restrict__ H_out, uint64_t U, Ctl* ctl,
                                              uint64_t* tile_state, FillItem* __restrict__ items,
                                              uint32_t item_cap, uint64_t limit, int CL2, int report_overflow,
-                                             FillRun* __restrict__ runs, uint32_t run_cap) {
+                                             FillRun* __restrict__ runs, uint32_t run_cap, uint32_t* __restrict__ out,
+                                             FillCfg fc) {
   constexpr int TB = NT * VPT;
   constexpr int PADW = TB + TB / 32;
   __shared__ uint32_t tr[VPT > 1 ? PADW : 1];
+  __shared__ __align__(16) uint32_t wbuf[DIRECT ? NT / WAVE : 1][DIRECT ? WIN_POS : 1];
   __shared__ uint64_t scan_tmp[NT / WAVE + 1];
   __shared__ uint64_t s_prefix;
   __shared__ uint32_t s_tile;
@@ -188,6 +194,25 @@ __global__ __launch_bounds__(NT) void k_scan(const uint32_t* __restrict__ rows, 
     ctl->total = total;
     ctl->limit = lim;
     if (report_overflow && total > limit) set_status(ctl, ST_OVERFLOW);
+  }
+
+  if constexpr (DIRECT) {
+    // 4'. the tile's runs, written by its waves: wave w owns the tile's bins
+    //     [64 VPT w, 64 VPT (w + 1)), whose run starts where its lane 0's
+    //     stretch starts (blocked layout)
+    const uint32_t lane = lane_id(), w = tid / WAVE;
+    const uint64_t wstart = sat_add(tpre, (uint64_t)__shfl((long long)texcl, 0, WAVE));
+    const uint64_t wtot = wave_sum(tsum);
+    auto count = [&](uint32_t j) -> uint32_t {
+      if constexpr (VPT == 1) {
+        return v[0];
+      } else {
+        const uint32_t p = w * (WAVE * VPT) + j * WAVE + lane;  // bin - base
+        return tr[p + (p >> 5)];
+      }
+    };
+    wave_fill(wbuf[w], out, wstart, wtot, base + (uint64_t)w * WAVE * VPT, VPT, count, fc);
+    return;
   }
 
   // 4. fill items of this tile: its span [s, e), clipped at limit, cut at the

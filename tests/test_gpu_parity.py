@@ -264,3 +264,18 @@ def test_changing_hot_keys(ds, U):
     keys = np.concatenate(blocks + [three, alt])
     assert_parity(ds, keys, U, label="changing hot keys")
     assert_parity(ds, keys, U, mode="hist", label="changing hot keys")
+
+
+@pytest.mark.parametrize("U", [300, 4096, 32768, 65536])
+def test_runs_near_window_sizes(ds, U):
+    """Sorts small enough for the scan tiles to write the output themselves:
+    runs of 63..70000 copies next to short ones, so that steps with only short
+    runs, steps with a long one and runs across several windows all occur."""
+    rng = np.random.default_rng(U + 41)
+    base = rng.integers(0, U, 400_000).astype(np.uint32)
+    extra = [np.full(c, (97 * i + 5) % U, dtype=np.uint32)
+             for i, c in enumerate([63, 64, 65, 66, 255, 256, 257, 1000, 4099, 70000])]
+    keys = np.concatenate([base] + extra)
+    rng.shuffle(keys)
+    assert_parity(ds, keys, U, label="runs near window sizes")
+    assert_parity(ds, keys, U, in_place=True, label="runs near window sizes")
