@@ -206,8 +206,10 @@ typedef struct dialsort_batch_plan {
     dialsort_batch_config config;
     uint32_t count;         /* arrays */
     uint32_t units;         /* work units of one launch */
-    uint32_t grid;          /* persistent workgroups */
-    uint32_t reserved;
+    uint32_t grid;          /* persistent workgroups of the fused kernel */
+    uint32_t fill_units;    /* the last fill_units of the units: fill units of
+                               the late size classes, run by a second kernel
+                               of small workgroups right after the fused one */
     uint64_t units_offset;  /* where the unit table sits in the workspace */
     void *ws;
     size_t ws_bytes;
@@ -228,7 +230,8 @@ dialsort_status dialsort_batch_prepare(const dialsort_desc *descs, uint32_t coun
                                        size_t ws_bytes, hipStream_t stream,
                                        dialsort_batch_plan *plan);
 
-/* Enqueues the prepared batch on `stream`: two kernel launches, no host
+/* Enqueues the prepared batch on `stream`: three kernel launches at most
+ * (clear, fused, late fills), no host
  * synchronisation, no allocation and no copy, so the call may be captured into
  * a HIP graph (hipStreamBeginCapture) and replayed; each launch recomputes
  * every H and output from the keys.  One plan (one workspace) must not be

@@ -43,7 +43,7 @@ class dialsort_batch_config(ctypes.Structure):
 
 class dialsort_batch_plan(ctypes.Structure):
     _fields_ = [("config", dialsort_batch_config), ("count", ctypes.c_uint32), ("units", ctypes.c_uint32),
-                ("grid", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("units_offset", ctypes.c_uint64),
+                ("grid", ctypes.c_uint32), ("fill_units", ctypes.c_uint32), ("units_offset", ctypes.c_uint64),
                 ("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t)]
 
 

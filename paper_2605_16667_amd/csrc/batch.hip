@@ -26,6 +26,9 @@ constexpr uint32_t FILL_PER = 32;         // item slots per fill unit (shared by
 constexpr uint64_t CLASS_MIN_COST = 1ull << 22;  // keys plus bins of the first size class, at least
 constexpr uint64_t CLASS_GROWTH = 3;             // a class closes at this many times the cost before it
 constexpr uint64_t BT_PACKED_CHUNK_MAX = 1ull << 22;
+constexpr uint64_t LATE_FILL_NUM = 1, LATE_FILL_DEN = 4;  // classes ending past this share of the cost
+                                                           // fill in k_batch_fill
+constexpr int FILL_K_NT = 256;                             // k_batch_fill workgroup
 
 bool cfg_valid(const dialsort_batch_config& c) {
   const bool nt = c.block == 512 || c.block == 1024;
@@ -121,7 +124,8 @@ void plan_batch(const dialsort_desc* d, uint32_t count, const Cfg& cfg, char* ba
     u.array = a; u.type = type; u.first = first; u.count = cnt;
     P.units.push_back(u);
   };
-  auto emit_class = [&](std::vector<uint32_t> cls) {
+  std::vector<BUnit> late;  // fill units of the late classes, listed last
+  auto emit_class = [&](std::vector<uint32_t> cls, bool late_fill) {
     std::stable_sort(cls.begin(), cls.end(), [&](uint32_t a, uint32_t b) { return d[a].n > d[b].n; });
     for (uint32_t i : cls) {
       const BArray& A = P.arr[i];
@@ -146,22 +150,35 @@ void plan_batch(const dialsort_desc* d, uint32_t count, const Cfg& cfg, char* ba
     }
     for (uint32_t i : cls) {
       const BArray& A = P.arr[i];
-      for (uint32_t f = 0; f < A.nf; ++f) add(i, UT_FILL, f, A.nf);
+      for (uint32_t f = 0; f < A.nf; ++f) {
+        add(i, UT_FILL, f, A.nf);
+        if (late_fill) {
+          late.push_back(P.units.back());
+          P.units.pop_back();
+        }
+      }
     }
   };
+  // a class whose cost ends past LATE_FILL of the batch's leaves its fills to
+  // k_batch_fill (a single class always does)
+  uint64_t all_cost = 0;
+  for (uint32_t i = 0; i < count; ++i) all_cost += cost(i);
+  auto late_end = [&](uint64_t end_cost) { return end_cost * LATE_FILL_DEN > all_cost * LATE_FILL_NUM; };
   std::vector<uint32_t> cls;
   uint64_t done_cost = 0, cls_cost = 0;
   for (uint32_t i : order) {
     cls.push_back(i);
     cls_cost += cost(i);
     if (cfg.classes && cls_cost >= std::max<uint64_t>(CLASS_MIN_COST, CLASS_GROWTH * done_cost)) {
-      emit_class(cls);
+      emit_class(cls, late_end(done_cost + cls_cost));
       done_cost += cls_cost;
       cls_cost = 0;
       cls.clear();
     }
   }
-  if (!cls.empty()) emit_class(cls);
+  if (!cls.empty()) emit_class(cls, true);
+  P.fill_units = (uint32_t)late.size();
+  P.units.insert(P.units.end(), late.begin(), late.end());
   // offsets
   size_t off = ALIGN;  // Ctl
   P.off_arrays = off;
@@ -207,6 +224,32 @@ std::vector<Cfg> candidates() {
   return v;
 }
 
+// Persistent grid of k_batch_fill: every workgroup the device holds at once,
+// at most one per unit.  The occupancy is queried once per device.
+std::mutex g_fill_occ_mu;
+std::map<int, uint32_t> g_fill_occ;
+
+uint32_t fill_grid(uint32_t units) {
+  int dev = 0, cus = 0;
+  (void)hipGetDevice(&dev);
+  uint32_t resident = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_fill_occ_mu);
+    auto it = g_fill_occ.find(dev);
+    if (it != g_fill_occ.end()) {
+      resident = it->second;
+    } else {
+      int nb = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_fill<FILL_K_NT>, FILL_K_NT, 0) != hipSuccess)
+        nb = 1;
+      if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 1;
+      resident = (uint32_t)(std::max(nb, 1) * std::max(cus, 1));
+      g_fill_occ[dev] = resident;
+    }
+  }
+  return std::max<uint32_t>(1, std::min(resident, units));
+}
+
 template <int NT, int LOG2W>
 dialsort_status launch_fused_t(const dialsort_batch_plan& p, hipStream_t s) {
   char* base = ws_base(p.ws);
@@ -216,8 +259,14 @@ dialsort_status launch_fused_t(const dialsort_batch_plan& p, hipStream_t s) {
   const uint32_t ig = (uint32_t)cdiv(std::max<uint64_t>(64, (uint64_t)p.count * 8), 256);
   DS_LAUNCH(k_batch_init, dim3(std::min<uint32_t>(ig, 1024)), dim3(256), s, (Ctl*)base, (BState*)(base + off_states),
             p.count);
-  DS_LAUNCH((k_batch<NT, LOG2W>), dim3(p.grid), dim3(NT), s, (const BArray*)(base + off_arrays),
-            (BState*)(base + off_states), (const BUnit*)(base + off_units), p.units, (Ctl*)base);
+  const uint32_t nmain = p.units - p.fill_units;
+  if (nmain)
+    DS_LAUNCH((k_batch<NT, LOG2W>), dim3(p.grid), dim3(NT), s, (const BArray*)(base + off_arrays),
+              (BState*)(base + off_states), (const BUnit*)(base + off_units), nmain, (Ctl*)base);
+  if (p.fill_units)
+    DS_LAUNCH((k_batch_fill<FILL_K_NT>), dim3(fill_grid(p.fill_units)), dim3(FILL_K_NT), s,
+              (const BArray*)(base + off_arrays), (BState*)(base + off_states),
+              (const BUnit*)(base + off_units) + nmain, p.fill_units, (Ctl*)base);
   return DIALSORT_OK;
 }
 
@@ -311,7 +360,9 @@ dialsort_status make_plan(const Planned& P, uint32_t count, const Cfg& cfg, void
   plan->config = from_cfg(cfg);
   plan->count = count;
   plan->units = (uint32_t)P.units.size();
-  plan->grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(resident, P.units.size()));
+  plan->fill_units = P.fill_units;
+  plan->grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(resident, P.units.size() - P.fill_units));
+  if (P.fill_units) (void)fill_grid(P.fill_units);  // the occupancy query happens here, not in a capture
   plan->units_offset = P.off_units;
   plan->ws = ws;
   plan->ws_bytes = ws_bytes;

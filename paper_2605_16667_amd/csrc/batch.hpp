@@ -14,7 +14,11 @@
 //   C  projection  -- fill units, each taking every F-th item slot of its array.
 // The host lists the units phase by phase (all A units of the batch, then all B
 // units, then all C units; inside a phase, larger arrays first).  Workgroups take
-// units in that order from one ticket counter.  A unit that depends on others
+// units in that order from one ticket counter.  The fill units of the size
+// classes that end late in the batch (most of its output) are listed apart and
+// run in a second kernel, k_batch_fill, right after this one: fill work needs
+// little LDS, and there it runs at many more waves per CU than the fused
+// kernel, whose workgroup is sized for the counting units' histograms.  A unit that depends on others
 // (B on its array's A units, C on its array's B units) spins on its array's
 // completion counter until they are done.  The units it waits for hold smaller
 // tickets, so they were taken by workgroups that are already running, and the
@@ -213,37 +217,46 @@ __device__ __forceinline__ uint64_t unit_bucket(BatchSmem<NT, LOG2W>& S, const B
   return waited;
 }
 
+// The fill items of one fill unit: wave w of the NT / WAVE takes the item
+// slots first + stride * (w + NW m).  fill: one LDS window per wave.
+template <int NT>
+__device__ __forceinline__ void fill_unit_items(WaveFillSmem<BT_CL2>* fill, const BArray& A, const BState* st,
+                                                uint32_t first, uint32_t stride, uint32_t* status, Ctl* ctl) {
+  const uint32_t ni = st->nitems < A.item_cap ? st->nitems : A.item_cap;
+  // a failed invariant (ST_INTERNAL) may leave items unwritten: fill nothing
+  const bool failed = (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ST_INTERNAL) != 0;
+  if (failed) return;
+  constexpr uint32_t NW = NT / WAVE;
+  const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  const uint64_t step = (uint64_t)stride * NW;
+  uint64_t j = first + (uint64_t)stride * w;
+  // the wave's next item is loaded while the current one is filled
+  FillItem next{};
+  if (j < ni) next = A.items[j];
+  for (; j < ni; j += step) {
+    const FillItem I = next;
+    if (j + step < ni) next = A.items[j + step];
+    // an item always lies inside its array; anything else is a broken
+    // invariant, reported (to the array and to the launch) instead of written
+    const bool valid = I.k <= I.klast && I.klast < A.U && I.klast - I.k < FILL_SPAN_MAX && I.o <= I.p0 &&
+                       I.p0 < I.p1 && I.p1 <= A.n && I.p1 - (I.p0 & ~3ull) <= (1ull << BT_CL2);
+    if (!valid) {
+      if (lane_id() == 0) {
+        atomicOr(status, ST_INT_ITEM);
+        atomicOr(&ctl->status, ST_INT_ITEM);
+      }
+      continue;
+    }
+    wave_fill_item<BT_CL2, true, false, true>(fill[w], A.H, A.out, I);
+  }
+}
+
 template <int NT, int LOG2W>
 __device__ __forceinline__ uint64_t unit_fill(BatchSmem<NT, LOG2W>& S, const BArray* __restrict__ Ap, BState* st,
                                        uint32_t first, uint32_t stride, uint32_t* status, Ctl* ctl) {
   const BArray& A = *Ap;
   const uint64_t waited = unit_wait(&st->b_done, A.nb);
-  const uint32_t ni = st->nitems < A.item_cap ? st->nitems : A.item_cap;
-  // a failed invariant (ST_INTERNAL) may leave items unwritten: fill nothing
-  const bool failed = (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ST_INTERNAL) != 0;
-  if (!failed) {
-    // wave w takes slots first + stride * (w + NW m)
-    constexpr uint32_t NW = NT / WAVE;
-    const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-    const uint64_t step = (uint64_t)stride * NW;
-    uint64_t j = first + (uint64_t)stride * w;
-    // the wave's next item is loaded while the current one is filled
-    FillItem next{};
-    if (j < ni) next = A.items[j];
-    for (; j < ni; j += step) {
-      const FillItem I = next;
-      if (j + step < ni) next = A.items[j + step];
-      // an item always lies inside its array; anything else is a broken
-      // invariant, reported instead of written
-      const bool valid = I.k <= I.klast && I.klast < A.U && I.klast - I.k < FILL_SPAN_MAX && I.o <= I.p0 &&
-                         I.p0 < I.p1 && I.p1 <= A.n && I.p1 - (I.p0 & ~3ull) <= (1ull << BT_CL2);
-      if (!valid) {
-        if (lane_id() == 0) atomicOr(status, ST_INT_ITEM);
-        continue;
-      }
-      wave_fill_item<BT_CL2, true, false, true>(S.fill[w], A.H, A.out, I);
-    }
-  }
+  fill_unit_items<NT>(S.fill, A, st, first, stride, status, ctl);
   const uint32_t old = unit_signal(&st->c_done, 1);
   if (threadIdx.x == 0 && old + 1 == A.nf) mark_done(st, ctl);
   return waited;
@@ -285,6 +298,47 @@ __global__ __launch_bounds__(NT) void k_batch(const BArray* __restrict__ arrays,
       const uint64_t busy = wall_clock64() - t0 - waited;
       __hip_atomic_fetch_add(&ctl->prof[2 * u.type], busy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_fetch_add(&ctl->prof[2 * u.type + 1], waited, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// The fill units listed after the fused kernel's own: launched on the same
+// stream right after k_batch, so every array's counting units have finished
+// and their H, items and item counts are visible (kernel boundary); nothing
+// here waits.  Small workgroups (NTF threads, one LDS window per wave) keep
+// many waves per CU in flight, as the single-array fill does.  A unit's
+// completion is counted without release semantics: nothing in the launch reads
+// the output, the count only stamps the array's completion time (after the
+// unit's stores are acknowledged) and folds its status, whose fill bits also
+// go straight to the launch status.
+template <int NTF>
+__global__ __launch_bounds__(NTF) void k_batch_fill(const BArray* __restrict__ arrays, BState* __restrict__ states,
+                                                    const BUnit* __restrict__ units, uint32_t nunits, Ctl* ctl) {
+  __shared__ WaveFillSmem<BT_CL2> S[NTF / WAVE];
+  __shared__ uint32_t s_ticket;
+  const uint32_t tid = threadIdx.x;
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) s_ticket = atomicAdd(&ctl->fill_ticket, 1u);
+    __syncthreads();
+    const uint32_t t = __builtin_amdgcn_readfirstlane(s_ticket);
+    if (t >= nunits) break;
+    const BUnit u = units[t];
+    const uint64_t t0 = wall_clock64();
+    if (u.type != UT_FILL) {
+      if (tid == 0) atomicOr(&ctl->status, ST_INT_UNIT);
+      continue;
+    }
+    const BArray& A = arrays[u.array];
+    BState* st = states + u.array;
+    fill_unit_items<NTF>(S, A, st, u.first, u.count, &st->status, ctl);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (tid == 0) {
+      const uint32_t old = __hip_atomic_fetch_add(&st->c_done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (old + 1 == A.nf) mark_done(st, ctl);
+      __hip_atomic_fetch_add(&ctl->prof[2 * UT_FILL], wall_clock64() - t0, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }

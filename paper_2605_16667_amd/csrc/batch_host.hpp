@@ -26,7 +26,8 @@ struct Cfg {
 
 struct Planned {
   std::vector<ds::BArray> arr;
-  std::vector<ds::BUnit> units;
+  std::vector<ds::BUnit> units;  // the fused kernel's units, then fill_units for k_batch_fill
+  uint32_t fill_units = 0;
   size_t off_arrays = 0, off_states = 0, off_units = 0, bytes = 0;
 };
 
