@@ -55,6 +55,18 @@ HBM_PEAK = 8.0e12  # MI355X HBM3E, bytes/s
 SERVE_SLOTS = 4    # batches (or lone requests) the server keeps on the device at once
 
 
+# Where the Zipf and hot-key inputs are generated before they are placed in
+# device memory: "cuda" by default; "cpu" with --host-inputs (the same
+# distributions from the host generator's stream; keeps the device sorts behind
+# torch.randperm out of profiled runs).
+GEN_DEVICE = "cuda"
+
+
+def gen(t):
+    """A generated input tensor, moved to the GPU if it was made on the host."""
+    return t if t.is_cuda else t.to("cuda")
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -338,7 +350,7 @@ def run_batch_workload(ds, hip, count, K, W):
     specs = w.batch_spec(count=count)
     arrays = []
     for s in specs:
-        k = s.keys("cuda")
+        k = gen(s.keys(GEN_DEVICE))
         arrays.append((k, s.U, torch.empty(s.U, dtype=torch.int32, device=dev),
                        torch.empty(s.n, dtype=torch.int32, device=dev)))
     torch.cuda.synchronize()
@@ -437,6 +449,59 @@ def run_batch_workload(ds, hip, count, K, W):
     return res
 
 
+PROFILE_CASES = ("large-sort", "large-hist", "plain", "skewed-sort", "skewed-hist", "uniform28-sort",
+                 "uniform28-hist", "batch", "zipf24-sort", "global-hist")
+
+
+def run_profile_case(ds, hip, name, K, W, batch_count):
+    """One workload alone (--profile NAME), for profiler runs: every dispatch of
+    the process then belongs to that one input.  No autotuning, no graph and no
+    per-array baseline for the batch (it launches the plan prepared with the
+    configuration the autotuner picks on this batch, 1024 threads, W = 2^16,
+    chunks of 2^22 keys).  Prints one JSON line with the per-kernel times."""
+    import torch
+
+    import workloads as w
+
+    if name == "batch":
+        specs = w.batch_spec(count=batch_count)
+        dev = torch.device("cuda:0")
+        arrays = []
+        for sp in specs:
+            k = gen(sp.keys(GEN_DEVICE))
+            arrays.append((k, sp.U, torch.empty(sp.U, dtype=torch.int32, device=dev),
+                           torch.empty(sp.n, dtype=torch.int32, device=dev)))
+        descs = ds.make_descs(arrays)
+        ws = ds.workspace(ds.dialsort_batched_workspace_bytes(descs, batch_count), dev)
+        st, plan = ds.dialsort_batch_prepare(descs, batch_count, ds.batch_config(1024, 16, 1 << 22), ws)
+        ds.check(st)
+        call = lambda: ds.check(ds.dialsort_batch_launch(plan))  # noqa: E731
+        res = time_calls(ds, hip, call, K, W, 0, 0)
+        st = ds.dialsort_status_sync(ws)
+        ok = st == ds.DIALSORT_OK and verify_batch(arrays)
+        print(json.dumps({"profile": name, "arrays": batch_count, "ms_per_step": res["ms_per_step"],
+                          "kernels": res["kernels"], "verified": ok}), flush=True)
+        return
+    if name.startswith("large"):
+        keys, U = w.uniform(10**8, 1 << 24, w.BASE_SEED + 1, "cuda"), 1 << 24
+    elif name == "plain":
+        keys, U = w.uniform(1 << 20, 1 << 16, w.BASE_SEED, "cuda"), 1 << 16
+    elif name.startswith("skewed"):
+        keys, U = gen(w.hot_zipf(1 << 28, 1 << 16, w.BASE_SEED + 2, GEN_DEVICE)), 1 << 16
+    elif name == "zipf24-sort":
+        # heavy buckets split between workgroups (global atomics into scratch rows)
+        keys, U = gen(w.zipf(10**8, 1 << 24, 1.2, w.BASE_SEED + 5, GEN_DEVICE)), 1 << 24
+    elif name == "global-hist":
+        # a universe beyond the partitioned path: direct global atomics into H
+        keys, U = w.uniform(1 << 24, 1 << 30, w.BASE_SEED + 6, "cuda"), 1 << 30
+    else:
+        keys, U = w.uniform(1 << 28, 1 << 16, w.BASE_SEED + 2, "cuda"), 1 << 16
+    torch.cuda.synchronize()
+    r = run_sort_workload(ds, hip, keys, U, K, W, "hist" if name.endswith("-hist") else "sort")
+    print(json.dumps({"profile": name, "n": keys.numel(), "U": U, "ms_per_step": r["ms_per_step"],
+                      "kernels": r["kernels"], "verified": r["verified"]}), flush=True)
+
+
 def run_serve_workload(ds, hip, num, loads, batch_cfg):
     """The served stream: `num` requests with Poisson arrivals, n log-uniform
     in [2^12, 2^24], U uniform over {2^12, 2^16, 2^20, 2^24}, uniform or
@@ -455,7 +520,7 @@ def run_serve_workload(ds, hip, num, loads, batch_cfg):
 
     dev = torch.device("cuda:0")
     probe = w.request_stream(num, 1.0)
-    keys = [r.spec.keys("cuda") for r in probe]
+    keys = [gen(r.spec.keys(GEN_DEVICE)) for r in probe]
     torch.cuda.synchronize()
     nkeys = sum(r.spec.n for r in probe)
     nmax = max(r.spec.n for r in probe)
@@ -846,12 +911,19 @@ def main():
                     help="arrival rates, as multiples of 1 / (mean serial service time)")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile", choices=PROFILE_CASES,
+                    help="run this one workload alone (for profiler runs) instead of the benchmark")
+    ap.add_argument("--host-inputs", action="store_true",
+                    help="generate the Zipf and hot-key inputs on the host and copy them to the GPU")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 256 MiB device copy (reference for profiler byte counters)")
     args = ap.parse_args()
+    if args.host_inputs:
+        global GEN_DEVICE
+        GEN_DEVICE = "cpu"
     if args.gpus != 1:
-        print("bench.py measures the single-GPU hot path: this build runs on one GPU only "
-              "(see DESIGN.md for how the path would shard); use --gpus 1", file=sys.stderr)
+        print("bench.py measures the single-GPU hot path and runs on one GPU only; use --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -871,6 +943,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    if args.profile:
+        run_profile_case(ds, hip, args.profile, K, W, args.batch_count)
+        return
     extra = {}
 
     copy_bps = copy_bandwidth()
@@ -916,7 +991,7 @@ def main():
     if "skewed" in todo:
         n3, U3 = 1 << 28, 1 << 16
         log("skewed: generating n=2^28 hot+Zipf(1.2)")
-        k3 = w.hot_zipf(n3, U3, w.BASE_SEED + 2, "cuda")
+        k3 = gen(w.hot_zipf(n3, U3, w.BASE_SEED + 2, GEN_DEVICE))
         r = run_sort_workload(ds, hip, k3, U3, max(K // 2, 3), W, "sort")
         extra["skewed"] = {"n": n3, "U": U3, "ms_per_step": r["ms_per_step"], "keys_per_s": r["keys_per_s"],
                            "path_roofline": r["path_roofline"], "roofline": r["roofline"], "cv": r["cv"],

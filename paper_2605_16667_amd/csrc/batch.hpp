@@ -41,7 +41,7 @@ namespace ds {
 
 constexpr uint32_t BT_BMAX = 1024;  // buckets per array on the fused path
 constexpr int BT_CL2 = 11;          // fill item span: 2048 positions (one wave)
-constexpr int BT_TK = 8192;         // keys per partition tile
+constexpr int BT_TK = 16384;        // keys per partition tile
 
 enum BatchKind : uint32_t { BA_EMPTY = 0, BA_LDS = 1, BA_PART = 2 };
 enum UnitType : uint32_t { UT_HIST = 0, UT_PART = 1, UT_ROWS = 2, UT_BUCKET = 3, UT_FILL = 4 };
@@ -158,9 +158,9 @@ __device__ __forceinline__ void unit_hist(BatchSmem<NT, LOG2W>& S, const BArray*
     if constexpr (LOG2W == 16) packed = A.U > 32768u;  // two 16-bit counters per word
     if (packed) {
       if constexpr (LOG2W == 16)
-        hist_slab<NT, true, 3, true, 4>(S.bin, A.keys, beg, end, umax, (uint32_t)A.U, row, status);
+        hist_slab<NT, true, 6, true, 4>(S.bin, A.keys, beg, end, umax, (uint32_t)A.U, row, status);
     } else {
-      hist_slab<NT, false, 3, true, 4>(S.bin, A.keys, beg, end, umax, (uint32_t)A.U, row, status);
+      hist_slab<NT, false, 6, true, 4>(S.bin, A.keys, beg, end, umax, (uint32_t)A.U, row, status);
     }
     __syncthreads();
   }
@@ -312,7 +312,7 @@ __global__ __launch_bounds__(NT) void k_batch(const BArray* __restrict__ arrays,
 // unit's stores are acknowledged) and folds its status, whose fill bits also
 // go straight to the launch status.
 template <int NTF>
-__global__ __launch_bounds__(NTF) void k_batch_fill(const BArray* __restrict__ arrays, BState* __restrict__ states,
+__global__ __launch_bounds__(NTF, 8) void k_batch_fill(const BArray* __restrict__ arrays, BState* __restrict__ states,
                                                     const BUnit* __restrict__ units, uint32_t nunits, Ctl* ctl) {
   __shared__ WaveFillSmem<BT_CL2> S[NTF / WAVE];
   __shared__ uint32_t s_ticket;

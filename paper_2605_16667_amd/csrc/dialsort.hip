@@ -190,16 +190,16 @@ dialsort_status launch_ingest(const uint32_t* keys, uint64_t n, uint64_t U, uint
   uint32_t* rows = L.rows_in_ws ? (uint32_t*)(base + L.off_rows) : H;
   switch (L.kind) {
     case K_LDS32S:
-      if (ka) DS_LAUNCH((k_hist_lds<1024, 4096, false, 3, true, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo);
-      else DS_LAUNCH((k_hist_lds<1024, 4096, false, 3, false, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo);
+      if (ka) DS_LAUNCH((k_hist_lds<1024, 4096, false, 6, true, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo);
+      else DS_LAUNCH((k_hist_lds<1024, 4096, false, 6, false, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo);
       break;
     case K_LDS32:
-      if (ka) DS_LAUNCH((k_hist_lds<1024, 32768, false, 3, true, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo);
-      else DS_LAUNCH((k_hist_lds<1024, 32768, false, 3, false, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo);
+      if (ka) DS_LAUNCH((k_hist_lds<1024, 32768, false, 6, true, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo);
+      else DS_LAUNCH((k_hist_lds<1024, 32768, false, 6, false, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo);
       break;
     case K_LDS16:
-      if (ka) DS_LAUNCH((k_hist_lds<1024, 32768, true, 3, true, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo);
-      else DS_LAUNCH((k_hist_lds<1024, 32768, true, 3, false, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo);
+      if (ka) DS_LAUNCH((k_hist_lds<1024, 32768, true, 6, true, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo);
+      else DS_LAUNCH((k_hist_lds<1024, 32768, true, 6, false, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo);
       break;
     case K_PART: {
       uint16_t* stg = (uint16_t*)(base + L.off_stage);

@@ -117,8 +117,62 @@ __device__ __forceinline__ void hist_slab(SM& S, const uint32_t* __restrict__ ke
 
   bool bad = false;
   WaveAgg st;
+  // AGG 6: the wave's candidate key hk is counted in registers -- each lane
+  // adds its matches to acc, no LDS atomic -- and the sum goes to LDS in one
+  // add when the candidate changes, when the slab ends and (packed counters)
+  // every HOT_FLUSH_ITERS iterations, so that a flush adds less than 2^16
+  // (at most 33 iterations of 64 * 4 * UNR keys) and crosses a field boundary
+  // at most once.
+  constexpr uint32_t HOT_FLUSH_ITERS = (1u << 15) / (WAVE * 4 * UNR);
+  uint32_t hk = 0xFFFFFFFFu;  // wave-uniform; no index <= umax < 2^32 - 1 equals it
+  uint32_t acc = 0, since = 0;
+  auto flush = [&]() {
+    const uint32_t c = __builtin_amdgcn_readfirstlane(wave_sum(acc));
+    acc = 0;
+    since = 0;
+    if (c == 0) return;
+    if (lane_id() == 0) {
+      if constexpr (!PACKED) {
+        atomicAdd(&S.s[hk], c);
+      } else {
+        const uint32_t old = atomicAdd(&S.s[hk >> 1], c << ((hk & 1u) << 4));
+        if (__builtin_amdgcn_ubfe(old, (hk & 1u) << 4, 16) + c >= 0x10000u)
+          lds16_crossing(S.s, hk >> 1, hk, c, old, S.evflag, S.ev, &S.nev);
+      }
+    }
+  };
+  // One slot of AGG 6: returns the count this lane adds to its key's bin
+  // (0 or 1), after counting a match of the candidate in registers.  The
+  // first slot of every iteration (probe) also looks for a group of
+  // AGG_HOT_MIN or more lanes on one key other than the candidate; a group
+  // larger than the candidate's in that slot takes its place, so the
+  // candidate settles on the key most lanes share.
+  auto slot_count6 = [&](uint32_t x, bool ok, bool probe) -> uint32_t {
+    const bool eq = ok && x == hk;
+    acc += eq ? 1u : 0u;
+    bool act = ok && !eq;
+    if (probe) {
+      const uint64_t am = __ballot(act);
+      if (am) {
+        const uint32_t ll = (uint32_t)__ffsll((unsigned long long)am) - 1;
+        const uint32_t lk = (uint32_t)__builtin_amdgcn_readlane((int)x, (int)ll);
+        const bool eq2 = act && x == lk;
+        const uint32_t c2 = (uint32_t)__popcll(__ballot(eq2));
+        if (c2 >= AGG_HOT_MIN && c2 > (uint32_t)__popcll(__ballot(eq))) {
+          flush();
+          hk = lk;
+          acc = eq2 ? 1u : 0u;
+          act = act && !eq2;
+        }
+      }
+    }
+    return act ? 1u : 0u;
+  };
   // uniform trip count across the workgroup: every lane takes part in the ballots
   for (uint64_t g0 = beg; g0 < end; g0 += (uint64_t)NT * 4 * UNR) {
+    if constexpr (AGG == 6 && PACKED) {
+      if (++since > HOT_FLUSH_ITERS) flush();
+    }
     uint32_t v[UNR][4];
     uint32_t nv[UNR];
 #pragma unroll
@@ -138,8 +192,13 @@ __device__ __forceinline__ void hist_slab(SM& S, const uint32_t* __restrict__ ke
       for (int u = 0; u < UNR; ++u) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          WaveGroups g;
-          const uint32_t c = wave_merge_count<AGG>(v[u][i], true, st, g);
+          uint32_t c;
+          if constexpr (AGG == 6) {
+            c = slot_count6(v[u][i], true, u == 0 && i == 0);
+          } else {
+            WaveGroups g;
+            c = wave_merge_count<AGG>(v[u][i], true, st, g);
+          }
           cc[u][i] = c;
           old[u][i] = 0;
           if constexpr (!PACKED) {
@@ -157,8 +216,13 @@ __device__ __forceinline__ void hist_slab(SM& S, const uint32_t* __restrict__ ke
           const bool valid = (uint32_t)i < nv[u];
           const bool ok = valid && v[u][i] <= umax;
           bad |= valid && !ok;
-          WaveGroups g;
-          const uint32_t c = wave_merge_count<AGG>(v[u][i], ok, st, g);
+          uint32_t c;
+          if constexpr (AGG == 6) {
+            c = slot_count6(v[u][i], ok, u == 0 && i == 0);
+          } else {
+            WaveGroups g;
+            c = wave_merge_count<AGG>(v[u][i], ok, st, g);
+          }
           cc[u][i] = c;
           old[u][i] = 0;
           if constexpr (!PACKED) {
@@ -192,6 +256,7 @@ __device__ __forceinline__ void hist_slab(SM& S, const uint32_t* __restrict__ ke
       }
     }
   }
+  if constexpr (AGG == 6) flush();
   if (__syncthreads_or(bad) && tid == 0) atomicOr(status, ST_RANGE);
 
   if constexpr (!PACKED) {

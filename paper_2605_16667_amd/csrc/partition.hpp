@@ -7,7 +7,9 @@
 //
 // Pass 1 (k_partition): workgroup t takes tile t of TK = 8192 keys, counts them
 // per bucket, scans the counts and places every key at a cursor of its bucket
-// (LDS atomics, after the wavefront equality merge).  It writes the tile's keys
+// (LDS atomics: with few buckets into per-lane copies of each bucket's counter,
+// and where many lanes share a counter after the wavefront equality merge).
+// It writes the tile's keys
 // grouped by bucket as uint16 bucket-relative keys (x & 0xFFFF) into its own
 // slice of the staging buffer, plus the tile's B+1 segment starts seg[t][0..B]
 // (seg[t][B] = number of valid keys of the tile).  Staging stays tile-major, so
@@ -72,6 +74,17 @@ struct SplitPlan {
 // ---------------------------------------------------------------------------
 // Pass 1
 // ---------------------------------------------------------------------------
+// Copies of each bucket's counter a tile keeps when it has few buckets: with
+// C = 2^lc copies, lane l counts into copy l mod C, so the 64 lanes of a slot
+// spread over up to 64 counters instead of B.  The copies of bucket b are
+// counters b*C .. b*C + C - 1, consecutive, so the exclusive scan over all of
+// them still places every bucket's keys together (a copy's cursor starts
+// where the previous copy's keys end), and bucket b starts at counter b*C.
+__device__ __forceinline__ uint32_t part_copies_log2(uint32_t B) {
+  const uint32_t lb = B > 1 ? 32u - (uint32_t)__clz(B - 1) : 0u;  // ceil(log2 B)
+  return lb < 6 ? 6 - lb : 0;
+}
+
 template <int NT, int BMAXT, int TK>
 struct PartSmem {
   uint32_t cnt[BMAXT + 1];
@@ -96,7 +109,9 @@ __device__ __forceinline__ void partition_tile(PartSmem<NT, BMAXT, TK>& S, const
   const uint64_t tb = (uint64_t)tile * TK;
   const uint64_t te = tb + TK < n ? tb + TK : n;
 
-  for (uint32_t i = tid; i <= B; i += NT) S.cnt[i] = 0;
+  // counters: B buckets, times 2^lc copies on a tile without merging
+  const uint32_t lc = part_copies_log2(B);
+  for (uint32_t i = tid; i <= (B << lc); i += NT) S.cnt[i] = 0;
 
   uint32_t v[GPT][4];
   bool bad = false;
@@ -111,17 +126,22 @@ __device__ __forceinline__ void partition_tile(PartSmem<NT, BMAXT, TK>& S, const
       if (!ok) v[u][i] = 0xFFFFFFFFu;
     }
   }
-  // Equality merging pays only where many lanes share a bucket: a tile takes
-  // it when some wave finds 8 or more of its first 64 keys (one per lane) in
-  // the bucket of its lowest lane's key.  Either way every count is exact.
+  // Equality merging pays only where many lanes share a counter: a tile takes
+  // it when some wave finds 8 or more of its first 64 keys (one per lane) on
+  // the counter (bucket and copy) of its lowest lane's key.  Merging tiles
+  // count each bucket in one counter, the others in 2^lc copies.  Either way
+  // every count is exact.
+  const uint32_t cmask = (1u << lc) - 1;
   bool crowd = false;
   if constexpr (AGG != 0) {
     const uint32_t x0 = v[0][0];
-    const uint32_t bk = x0 != 0xFFFFFFFFu ? x0 >> LOG2W : 0xFFFFFFFFu;
-    const uint32_t lead = __builtin_amdgcn_readfirstlane(bk);
-    crowd = lead != 0xFFFFFFFFu && __popcll(__ballot(bk == lead)) >= 8;
+    const uint32_t ci = x0 != 0xFFFFFFFFu ? ((x0 >> LOG2W) << lc) | (lane_id() & cmask) : 0xFFFFFFFFu;
+    const uint32_t lead = __builtin_amdgcn_readfirstlane(ci);
+    crowd = lead != 0xFFFFFFFFu && __popcll(__ballot(ci == lead)) >= 8;
   }
   const bool merge = __syncthreads_or(crowd);
+  const uint32_t cl = merge ? 0u : lc;  // copies of this tile: 2^cl
+  const uint32_t cm = (1u << cl) - 1, nc = B << cl;
   WaveAgg st;
   if (merge) {
 #pragma unroll
@@ -137,24 +157,33 @@ __device__ __forceinline__ void partition_tile(PartSmem<NT, BMAXT, TK>& S, const
     for (int u = 0; u < GPT; ++u) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const bool ok = v[u][i] != 0xFFFFFFFFu;
-        wave_count<0>(S.cnt, ok ? (v[u][i] >> LOG2W) : 0u, ok, st);
+        const uint32_t x = v[u][i];
+        if (x != 0xFFFFFFFFu) atomicAdd(&S.cnt[((x >> LOG2W) << cl) | (lane_id() & cm)], 1u);
       }
     }
   }
   if (__syncthreads_or(bad) && tid == 0) atomicOr(status, ST_RANGE);
 
-  // exclusive scan of the B+1 counters (counter B stays 0, so the total is the
-  // number of valid keys); each thread owns a run of CPT counters
+  // exclusive scan of the nc+1 counters (counter nc stays 0, so the total is
+  // the number of valid keys); each thread owns a run of CPT counters.
+  // Bucket b starts at counter b << cl; counter nc gives seg[B].
+  static_assert(BMAXT >= 64, "the copies of a few buckets fit the counters");
+  if (plan != nullptr) {
+    // bucket totals: one global add per nonzero bucket (its copies summed here)
+    for (uint32_t b = tid; b < B; b += NT) {
+      uint32_t t = 0;
+      for (uint32_t c = 0; c <= cm; ++c) t += S.cnt[(b << cl) + c];
+      if (t) atomicAdd(&plan->colsum[(tile & (plan->rows - 1)) * B + b], t);
+    }
+  }
   constexpr int CPT = (BMAXT + 1 + NT - 1) / NT;
   uint32_t loc[CPT];
   uint32_t sum = 0;
 #pragma unroll
   for (int j = 0; j < CPT; ++j) {
     const uint32_t i = tid * CPT + j;
-    loc[j] = i <= B ? S.cnt[i] : 0;
+    loc[j] = i <= nc ? S.cnt[i] : 0;
     sum += loc[j];
-    if (plan != nullptr && i < B && loc[j]) atomicAdd(&plan->colsum[(tile & (plan->rows - 1)) * B + i], loc[j]);
   }
   uint32_t total;
   uint32_t pre = block_exclusive_sum<NT>(sum, S.scan_tmp, &total);
@@ -162,7 +191,10 @@ __device__ __forceinline__ void partition_tile(PartSmem<NT, BMAXT, TK>& S, const
 #pragma unroll
   for (int j = 0; j < CPT; ++j) {
     const uint32_t i = tid * CPT + j;
-    if (i <= B) { S.cnt[i] = pre; srow[i] = (uint16_t)pre; }
+    if (i <= nc) {
+      S.cnt[i] = pre;
+      if ((i & cm) == 0) srow[i >> cl] = (uint16_t)pre;
+    }
     pre += loc[j];
   }
   __syncthreads();
@@ -205,7 +237,7 @@ __device__ __forceinline__ void partition_tile(PartSmem<NT, BMAXT, TK>& S, const
         for (int i = 0; i < 4; ++i) {
           const uint32_t x = v[u0 + u][i];
           pos[u][i] = 0;
-          if (x != 0xFFFFFFFFu) pos[u][i] = atomicAdd(&S.cnt[x >> LOG2W], 1u);
+          if (x != 0xFFFFFFFFu) pos[u][i] = atomicAdd(&S.cnt[((x >> LOG2W) << cl) | (lane_id() & cm)], 1u);
         }
       }
 #pragma unroll
