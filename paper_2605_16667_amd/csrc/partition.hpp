@@ -336,6 +336,82 @@ enum GatherMode { GM_PACKED, GM_HALF, GM_DIRECT };
 // The bounds of a wave's next group are loaded before its current group is
 // counted.  Only tiles [t0, t1) are visited; returns the number of keys in the
 // segments this thread owned (each segment belongs to one lane of one wave).
+// Count the 8 keys of quad d (tile-local key indices [8q, 8q + 8)) that lie in
+// [s, e) (and, GM_HALF, in half `half`) into S, after the wave merge.
+template <int NT, int LOG2W, int AGG, GatherMode GM>
+__device__ __forceinline__ void count_quad(BinSmem<NT, LOG2W>& S, const uint4& d, int32_t q8, uint32_t s, uint32_t e,
+                                           uint32_t half, WaveAgg& st) {
+  const int32_t lob = max((int32_t)s - q8, 0), hib = min((int32_t)e - q8, 8);
+  const uint32_t qm = hib > lob ? ((1u << hib) - 1u) & ~((1u << lob) - 1u) : 0u;
+  const uint32_t wds[4] = {d.x, d.y, d.z, d.w};
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const uint32_t x = (m & 1) ? (wds[m >> 1] >> 16) : (wds[m >> 1] & 0xFFFFu);
+    bool ok = (qm >> m) & 1u;
+    if (GM == GM_HALF) ok = ok && (x >> 15) == half;
+    WaveGroups grp;
+    const uint32_t n = wave_merge_count<AGG>(x, ok, st, grp);
+    // lanes without a count issue nothing: as no-ops they would all hit
+    // one word (masked keys, merged group members) and serialise
+    if (n) {
+      if (GM == GM_PACKED) {
+        atomicAdd(&S.s[x >> 1], n << ((x & 1u) << 4));
+      } else if (GM == GM_HALF) {
+        atomicAdd(&S.s[x & 0x7FFFu], n);
+      } else {
+        atomicAdd(&S.s[x], n);
+      }
+    }
+  }
+}
+
+// Bucket b's segments of fewer than 64 tiles: the waves take the tiles (NW / T
+// waves per tile when there are fewer tiles than waves) and all 64 lanes of a
+// wave walk one segment, BK_SQ 16-byte quads per lane per step, the step count
+// uniform over the wave (lanes past the segment's end reread its last quad,
+// masked out).  With one lane per tile, as below, such a bucket would keep at
+// most T lanes of each wave busy.
+template <int NT, int LOG2W, int AGG, GatherMode GM, int TK>
+__device__ __forceinline__ uint32_t bucket_gather_few(BinSmem<NT, LOG2W>& S, const uint16_t* __restrict__ staging,
+                                                      const uint16_t* __restrict__ seg, uint32_t bstride, uint32_t t0,
+                                                      uint32_t T, uint32_t b, uint32_t half) {
+  constexpr uint32_t NW = NT / WAVE;
+  WaveAgg st;
+  const uint32_t lane = lane_id(), w = threadIdx.x / WAVE;
+  const uint4* sq = reinterpret_cast<const uint4*>(staging);
+  const uint32_t wpt = T < NW ? NW / T : 1;  // waves per tile
+  const uint32_t tstep = NW / wpt;           // tiles between a wave's tiles
+  const uint32_t sub = w % wpt;
+  if (w >= tstep * wpt) return 0;  // spare waves when NW is not a multiple of T
+  uint32_t counted = 0;
+  for (uint32_t i = w / wpt; i < T; i += tstep) {  // wave-uniform
+    const uint32_t t = t0 + i;
+    const uint16_t* row = seg + (uint64_t)t * bstride;
+    const uint32_t e = row[b + 1] < (uint32_t)TK ? row[b + 1] : (uint32_t)TK;
+    const uint32_t s = row[b] < e ? row[b] : e;
+    if (sub == 0 && lane == 0) counted += e - s;
+    if (e <= s) continue;
+    const uint32_t q0 = s >> 3, q1 = (e + 7) >> 3;  // quads [q0, q1) of the tile
+    const uint64_t tq = (uint64_t)t * (TK / 8);
+    constexpr uint32_t CH = WAVE * BK_SQ;  // quads per wave step
+    for (uint32_t c0 = q0 + sub * CH; c0 < q1; c0 += wpt * CH) {  // wave-uniform
+      uint4 d[BK_SQ];
+#pragma unroll
+      for (int j = 0; j < BK_SQ; ++j) {
+        const uint32_t q = c0 + j * WAVE + lane;
+        d[j] = sq[tq + (q < q1 ? q : q1 - 1)];
+      }
+#pragma unroll
+      for (int j = 0; j < BK_SQ; ++j) {
+        const uint32_t q = c0 + j * WAVE + lane;
+        // a reread quad counts nothing: its window [8q, 8q + 8) lies past e
+        count_quad<NT, LOG2W, AGG, GM>(S, d[j], (int32_t)(q * 8), s, e, half, st);
+      }
+    }
+  }
+  return counted;
+}
+
 template <int NT, int LOG2W, int AGG, GatherMode GM, int TK>
 __device__ __forceinline__ uint32_t bucket_gather(BinSmem<NT, LOG2W>& S, const uint16_t* __restrict__ staging,
                                                   const uint16_t* __restrict__ seg, uint32_t bstride, uint32_t t0,
@@ -348,6 +424,7 @@ __device__ __forceinline__ uint32_t bucket_gather(BinSmem<NT, LOG2W>& S, const u
   uint32_t counted = 0;
   if (t1 <= t0) return 0;
   const uint32_t T = t1 - t0;               // tiles t0 + i, i < T
+  if (T < WAVE) return bucket_gather_few<NT, LOG2W, AGG, GM, TK>(S, staging, seg, bstride, t0, T, b, half);
   const uint32_t G = (T + WAVE - 1) / WAVE;  // groups of 64 tiles
   const uint32_t wpg = G < NW ? NW / G : 1;  // waves per group
   const uint32_t gstep = NW / wpg;           // groups between a wave's groups
@@ -388,29 +465,7 @@ __device__ __forceinline__ uint32_t bucket_gather(BinSmem<NT, LOG2W>& S, const u
 #pragma unroll
       for (int j = 0; j < BK_SQ; ++j) {
         // valid keys of this quad: tile-local indices [s, e) within [q, q + 8)
-        const int32_t q = (int32_t)((q0 + k0 + j) * 8);
-        const int32_t lob = max((int32_t)s - q, 0), hib = min((int32_t)e - q, 8);
-        const uint32_t qm = hib > lob ? ((1u << hib) - 1u) & ~((1u << lob) - 1u) : 0u;
-        const uint32_t wds[4] = {d[j].x, d[j].y, d[j].z, d[j].w};
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-          const uint32_t x = (m & 1) ? (wds[m >> 1] >> 16) : (wds[m >> 1] & 0xFFFFu);
-          bool ok = (qm >> m) & 1u;
-          if (GM == GM_HALF) ok = ok && (x >> 15) == half;
-          WaveGroups grp;
-          const uint32_t n = wave_merge_count<AGG>(x, ok, st, grp);
-          // lanes without a count issue nothing: as no-ops they would all hit
-          // one word (masked keys, merged group members) and serialise
-          if (n) {
-            if (GM == GM_PACKED) {
-              atomicAdd(&S.s[x >> 1], n << ((x & 1u) << 4));
-            } else if (GM == GM_HALF) {
-              atomicAdd(&S.s[x & 0x7FFFu], n);
-            } else {
-              atomicAdd(&S.s[x], n);
-            }
-          }
-        }
+        count_quad<NT, LOG2W, AGG, GM>(S, d[j], (int32_t)((q0 + k0 + j) * 8), s, e, half, st);
       }
     }
     lo = nlo;
