@@ -178,33 +178,40 @@ def profiled_traffic(kernel: str):
 
 
 def time_calls(ds, hip, call, K, W, n, U, nev=12):
-    """W untimed calls, then K timed calls with per-launch events.  Returns a dict."""
+    """W untimed calls, then K timed calls bracketed by one event per step
+    boundary (the step times), then K more calls with an event after every
+    launch (the per-kernel times; those events add a little to each step, so
+    the step figures come from the first pass).  Returns a dict."""
     import torch
 
     for _ in range(W):
         call()
     torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+    torch.cuda.synchronize()
+    marks[0].record(stream)
+    for k in range(K):
+        call()
+        marks[k + 1].record(stream)
+    torch.cuda.synchronize()
+    steps = [marks[k].elapsed_time(marks[k + 1]) for k in range(K)]
+    total_ms = marks[0].elapsed_time(marks[K])
     evsets = [hip.make(nev) for _ in range(K)]
     count = ctypes.c_uint32(0)
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0.record()
     for k in range(K):
         ds.dialsort_set_launch_events(evsets[k], nev, count)
         call()
-    t1.record()
     ds.dialsort_set_launch_events(None, 0, None)
     torch.cuda.synchronize()
-    total_ms = t0.elapsed_time(t1)
     nl = count.value
     names = [ds.dialsort_launch_name(i) for i in range(nl)]
-    steps = [hip.ms(e[0], e[nl]) for e in evsets]
     per_kernel = {}
     for i, name in enumerate(names):
         d = [hip.ms(e[i], e[i + 1]) for e in evsets]
         key = f"{i}:{name}"
         per_kernel[key] = {"avg_ms": statistics.fmean(d), "min_ms": min(d)}
+    evented = [hip.ms(e[0], e[nl]) for e in evsets]
     for e in evsets:
         hip.free(e)
     ms_step = total_ms / K
@@ -213,6 +220,7 @@ def time_calls(ds, hip, call, K, W, n, U, nev=12):
         "best_ms": min(steps),
         "median_ms": statistics.median(steps),
         "cv": (statistics.pstdev(steps) / statistics.fmean(steps)) if len(steps) > 1 else 0.0,
+        "ms_per_step_with_launch_events": statistics.fmean(evented),
         "kernels": per_kernel,
         "names": names,
     }

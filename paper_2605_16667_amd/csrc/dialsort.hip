@@ -2,9 +2,10 @@
 // plan selection, workspace layout and kernel launches behind the C ABI of
 // include/dialsort.h.
 //
-// Launch sequences (every sequence starts with k_init, which clears the control
-// block and the look-back tile flags, and zeroes H only where H is accumulated
-// with atomics):
+// Launch sequences (each starts with k_init, which clears the control block and
+// the look-back tile flags, and zeroes H only where H is accumulated with
+// atomics -- except an LDS ingestion into partial rows, which clears them
+// itself):
 //   LDS32 / LDS16 (U <= 65536):  k_hist_lds -> [k_scan: sum rows into H]
 //   PART (65536 < U <= 2^29):     k_partition -> k_bucket (H, and fill items)
 //   GLOBAL (tiny n, or U > 2^29): k_hist_global
@@ -159,6 +160,14 @@ Layout plan(uint64_t n, uint64_t U, int mode) {
   return L;
 }
 
+// LDS ingestion into partial rows: the ingestion launch clears the control
+// block and the look-back flags itself (k_hist_lds, init), and the scan reads
+// the rows' status words, so no clearing launch runs first.
+// (Partial rows are U + 1 words at least: word U of a row is free.)
+bool fold_init(const Layout& L) {
+  return L.rows_in_ws && (L.kind == K_LDS32S || L.kind == K_LDS32 || L.kind == K_LDS16);
+}
+
 // k_init: clear the control block, the look-back flags, the bucket-total
 // counters, and optionally H.
 __global__ void k_init(Ctl* ctl, uint64_t* tiles, uint64_t ntiles, uint32_t* z, uint64_t nz, uint32_t* H,
@@ -188,18 +197,22 @@ dialsort_status launch_ingest(const uint32_t* keys, uint64_t n, uint64_t U, uint
   const uint32_t umax = (uint32_t)(U - 1);
   const bool ka = aligned16(keys);
   uint32_t* rows = L.rows_in_ws ? (uint32_t*)(base + L.off_rows) : H;
+  // the LDS ingestion into partial rows also clears what the scan needs
+  const uint32_t fi = fold_init(L) ? 1u : 0u;
+  uint64_t* clr = (uint64_t*)(base + L.off_tile);
+  const uint64_t nclr = fi && L.scan ? L.scan_tiles : 0;
   switch (L.kind) {
     case K_LDS32S:
-      if (ka) DS_LAUNCH((k_hist_lds<1024, 4096, false, 6, true, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo);
-      else DS_LAUNCH((k_hist_lds<1024, 4096, false, 6, false, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo);
+      if (ka) DS_LAUNCH((k_hist_lds<1024, 4096, false, 6, true, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo, fi, clr, nclr);
+      else DS_LAUNCH((k_hist_lds<1024, 4096, false, 6, false, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo, fi, clr, nclr);
       break;
     case K_LDS32:
-      if (ka) DS_LAUNCH((k_hist_lds<1024, 32768, false, 6, true, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo);
-      else DS_LAUNCH((k_hist_lds<1024, 32768, false, 6, false, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo);
+      if (ka) DS_LAUNCH((k_hist_lds<1024, 32768, false, 6, true, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo, fi, clr, nclr);
+      else DS_LAUNCH((k_hist_lds<1024, 32768, false, 6, false, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo, fi, clr, nclr);
       break;
     case K_LDS16:
-      if (ka) DS_LAUNCH((k_hist_lds<1024, 32768, true, 6, true, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo);
-      else DS_LAUNCH((k_hist_lds<1024, 32768, true, 6, false, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo);
+      if (ka) DS_LAUNCH((k_hist_lds<1024, 32768, true, 6, true, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo, fi, clr, nclr);
+      else DS_LAUNCH((k_hist_lds<1024, 32768, true, 6, false, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo, fi, clr, nclr);
       break;
     case K_PART: {
       uint16_t* stg = (uint16_t*)(base + L.off_stage);
@@ -256,9 +269,11 @@ dialsort_status launch_scan(const uint32_t* rows, uint32_t nrows, uint64_t row_s
   FillRun* runs = (FillRun*)(base + L.off_runs);
   const uint32_t rcap = (uint32_t)std::min<uint64_t>(L.run_cap, 0xFFFFFFF0ull);
   const dim3 grid((uint32_t)L.scan_tiles);
+  // rows are the ingestion's partial rows carrying status words
+  const uint32_t rstat = fold_init(L) && nrows == L.G && row_stride == L.row_stride ? 1u : 0u;
 #define DS_SCAN(VPT, FULL, DIRECT)                                                                                  \
   DS_LAUNCH((k_scan<SCAN_NT, VPT, FULL, DIRECT>), grid, dim3(SCAN_NT), s, rows, nrows, row_stride, H_out, U, ctl, \
-            tiles, items, icap, L.limit, FILL_CL2, report_overflow, runs, rcap, out, fc)
+            tiles, items, icap, L.limit, FILL_CL2, report_overflow, runs, rcap, out, fc, rstat)
   if (full && L.direct) {
     if (L.scan_vpt == 1) DS_SCAN(1, true, true); else DS_SCAN(16, true, true);
   } else if (full) {
@@ -328,7 +343,7 @@ dialsort_status run_sort(const uint32_t* keys, uint64_t n, uint64_t U, uint32_t 
   const Layout L = plan(n, U, mode);
   char* base = ws_base(ws);
   const bool zeroH = L.kind == K_EMPTY || L.kind == K_GLOBAL;
-  DS_TRY(launch_init(base, L, H, zeroH ? U : 0, s));
+  if (!fold_init(L)) DS_TRY(launch_init(base, L, H, zeroH ? U : 0, s));
   DS_TRY(launch_ingest(keys, n, U, lo, H, base, L, s));
   const uint32_t* rows = L.rows_in_ws ? (const uint32_t*)(base + L.off_rows) : H;
   const uint32_t nrows = L.rows_in_ws ? L.G : 1;

@@ -287,15 +287,31 @@ __device__ __forceinline__ void hist_slab(SM& S, const uint32_t* __restrict__ ke
 
 // NT threads; CAP = LDS words; PACKED selects the 16-bit layout.
 // rows: G rows of `row_stride` uint32 each (row g at rows + g*row_stride).
+// init (partial rows in the workspace, row_stride > U): the launch also does
+// what a clearing launch before it would -- block 0 zeroes the control block,
+// all blocks zero the nclear look-back words of the scan that follows
+// (clear_tiles) -- and each block reports a key past U in its own row, word U
+// (zeroed by the block first), which the scan folds into the status.  No block
+// touches the control block's status then, so clearing it cannot race with a
+// report.
 template <int NT, int CAP, bool PACKED, int AGG, bool ALIGNED, int UNR>
 __global__ __launch_bounds__(NT) void k_hist_lds(const uint32_t* __restrict__ keys, uint64_t n, uint64_t per,
                                                  uint32_t umax, uint32_t U, uint32_t* __restrict__ rows,
-                                                 uint64_t row_stride, Ctl* ctl, uint32_t lo) {
+                                                 uint64_t row_stride, Ctl* ctl, uint32_t lo, uint32_t init,
+                                                 uint64_t* __restrict__ clear_tiles, uint64_t nclear) {
   __shared__ HistSmem<CAP, PACKED> S;
   const uint64_t beg = (uint64_t)blockIdx.x * per;
   const uint64_t end = beg + per < n ? beg + per : n;
-  hist_slab<NT, PACKED, AGG, ALIGNED, UNR>(S, keys, beg, end, umax, U, rows + (uint64_t)blockIdx.x * row_stride,
-                                                  &ctl->status, lo);
+  uint32_t* row = rows + (uint64_t)blockIdx.x * row_stride;
+  uint32_t* status = &ctl->status;
+  if (init) {
+    if (blockIdx.x == 0 && threadIdx.x < sizeof(Ctl) / 4) reinterpret_cast<uint32_t*>(ctl)[threadIdx.x] = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * NT + threadIdx.x; i < nclear; i += (uint64_t)gridDim.x * NT)
+      clear_tiles[i] = 0;
+    status = row + U;
+    if (threadIdx.x == 0) *status = 0;  // the same thread reports into it, after barriers
+  }
+  hist_slab<NT, PACKED, AGG, ALIGNED, UNR>(S, keys, beg, end, umax, U, row, status, lo);
 }
 
 // Direct global atomics into a zeroed H, after the same wave merge.  Used when

@@ -117,7 +117,7 @@ __global__ __launch_bounds__(NT) void k_scan(const uint32_t* __restrict__ rows, 
                                              uint64_t* tile_state, FillItem* __restrict__ items,
                                              uint32_t item_cap, uint64_t limit, int CL2, int report_overflow,
                                              FillRun* __restrict__ runs, uint32_t run_cap, uint32_t* __restrict__ out,
-                                             FillCfg fc) {
+                                             FillCfg fc, uint32_t row_status) {
   constexpr int TB = NT * VPT;
   constexpr int PADW = TB + TB / 32;
   __shared__ uint32_t tr[VPT > 1 ? PADW : 1];
@@ -127,6 +127,13 @@ __global__ __launch_bounds__(NT) void k_scan(const uint32_t* __restrict__ rows, 
   __shared__ uint32_t s_tile;
   __shared__ uint32_t s_item0;
   const uint32_t tid = threadIdx.x;
+
+  // row_status: each partial row holds its ingestion's status bits in word U
+  if (row_status && blockIdx.x == 0) {
+    uint32_t bits = 0;
+    for (uint32_t r = tid; r < nrows; r += NT) bits |= rows[(uint64_t)r * row_stride + U];
+    if (bits) atomicOr(&ctl->status, bits);  // only on a faulty input
+  }
 
   uint64_t t = blockIdx.x;
   if constexpr (FULL) {

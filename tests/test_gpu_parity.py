@@ -279,3 +279,30 @@ def test_runs_near_window_sizes(ds, U):
     rng.shuffle(keys)
     assert_parity(ds, keys, U, label="runs near window sizes")
     assert_parity(ds, keys, U, in_place=True, label="runs near window sizes")
+
+
+@pytest.mark.parametrize("U", [4096, 30000, 65536])
+def test_range_report_through_partial_rows(ds, U):
+    """n = 2^20 ingests into many partial rows, with no clearing launch first:
+    each ingestion workgroup reports a key past U in its own row and the scan
+    folds the reports into the status.  A bad key in the first or the last
+    workgroup's slab is reported, in sort and histogram mode, and the next
+    clean call on the same workspace is clean and exact again."""
+    dev = torch.device("cuda:0")
+    n = 1 << 20
+    ws = ds.workspace(ds.dialsort_workspace_bytes(n, U, ds.DIALSORT_MODE_SORT), dev)
+    H = torch.empty(U, dtype=torch.int32, device=dev)
+    out = torch.empty(n, dtype=torch.int32, device=dev)
+    for pos in [0, n - 1]:
+        keys = w.uniform(n, U, SEED + pos).to(dev)
+        keys[pos] = U + pos % 7
+        say(f"range report U={U} pos={pos}")
+        ds.check(ds.dialsort_sort(keys, U, H, out, ws))
+        assert ds.dialsort_status_sync(ws) == ds.DIALSORT_ERANGE
+        ds.check(ds.dialsort_histogram(keys, U, H, ws))
+        assert ds.dialsort_status_sync(ws) == ds.DIALSORT_ERANGE
+        good = w.uniform(n, U, SEED + 3 + pos).to(dev)
+        ds.check(ds.dialsort_sort(good, U, H, out, ws))
+        assert ds.dialsort_status_sync(ws) == ds.DIALSORT_OK
+        _, H_ref, out_ref = oracle.sort(w.as_u32(good), U)
+        assert np.array_equal(w.as_u32(H), H_ref) and np.array_equal(w.as_u32(out), out_ref)
