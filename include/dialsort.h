@@ -267,10 +267,11 @@ dialsort_status dialsort_batch_default_config(const dialsort_desc *descs, uint32
  * for the first `count` arrays, the time in ms from the start of the launch's
  * first work unit to the end of the array's last one (array_ms[i]), in
  * *launch_ms (if not NULL) the time to the end of the last unit of the whole
- * launch, and in unit_ms[0..9] (if not NULL), for the unit types ingestion
- * (LDS), ingestion (partition), row sum + scan, bucket, fill, the
- * workgroup-milliseconds spent working (unit_ms[2t]) and waiting for other
- * units (unit_ms[2t+1]).  Read from the device wall clock. */
+ * launch, and in unit_ms[0..11] (if not NULL), for the unit types ingestion
+ * (LDS), ingestion (partition), row sum + scan, bucket, fill in the fused
+ * kernel, fill in the late-fill kernel, the workgroup-milliseconds spent
+ * working (unit_ms[2t]) and waiting for other units (unit_ms[2t+1], always 0
+ * for the late fills, which never wait).  Read from the device wall clock. */
 dialsort_status dialsort_batch_times(const dialsort_batch_plan *plan, hipStream_t stream,
                                      double *array_ms, uint32_t count, double *launch_ms,
                                      double *unit_ms);

@@ -324,7 +324,7 @@ def dialsort_batch_default_config(descs, count: int) -> Tuple[int, dialsort_batc
     return st, cfg
 
 
-UNIT_TYPES = ("hist", "partition", "rows", "bucket", "fill")
+UNIT_TYPES = ("hist", "partition", "rows", "bucket", "fill", "fill_late")
 
 
 def dialsort_batch_times(plan: dialsort_batch_plan, count: int, stream=None, units: bool = False):
@@ -333,7 +333,7 @@ def dialsort_batch_times(plan: dialsort_batch_plan, count: int, stream=None, uni
     to its (busy, waiting) workgroup-milliseconds."""
     arr = (ctypes.c_double * max(count, 1))()
     tot = ctypes.c_double(0.0)
-    um = (ctypes.c_double * 10)()
+    um = (ctypes.c_double * 12)()
     st = _lib.dialsort_batch_times(ctypes.byref(plan), _stream(stream), arr, count, ctypes.byref(tot), um)
     if units:
         return st, list(arr[:count]), tot.value, {t: (um[2 * i], um[2 * i + 1]) for i, t in enumerate(UNIT_TYPES)}

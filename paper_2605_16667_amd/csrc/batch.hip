@@ -530,7 +530,7 @@ dialsort_status dialsort_batch_times(const dialsort_batch_plan* plan, hipStream_
     array_ms[i] = st[i].t_done >= ctl.total ? (double)(st[i].t_done - ctl.total) * tick_ms : 0.0;
   if (launch_ms) *launch_ms = ctl.limit >= ctl.total ? (double)(ctl.limit - ctl.total) * tick_ms : 0.0;
   if (unit_ms)
-    for (int i = 0; i < 10; ++i) unit_ms[i] = (double)ctl.prof[i] * tick_ms;
+    for (int i = 0; i < 12; ++i) unit_ms[i] = (double)ctl.prof[i] * tick_ms;
   return DIALSORT_OK;
 }
 

@@ -90,7 +90,8 @@ struct BUnit {
 // Ctl::tile_ticket is the unit ticket; Ctl::total receives the launch's start
 // time (wall clock) and Ctl::limit the time its last unit finished;
 // Ctl::prof[2 t] / [2 t + 1] sum, over the units of type t, the clock ticks
-// their workgroups spent working / waiting for other units.
+// their workgroups spent working / waiting for other units; Ctl::prof[10]
+// sums the busy ticks of the fill units run by k_batch_fill.
 
 template <int NT, int LOG2W>
 union BatchSmem {
@@ -337,7 +338,7 @@ __global__ __launch_bounds__(NTF, 8) void k_batch_fill(const BArray* __restrict_
     if (tid == 0) {
       const uint32_t old = __hip_atomic_fetch_add(&st->c_done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (old + 1 == A.nf) mark_done(st, ctl);
-      __hip_atomic_fetch_add(&ctl->prof[2 * UT_FILL], wall_clock64() - t0, __ATOMIC_RELAXED,
+      __hip_atomic_fetch_add(&ctl->prof[2 * UT_FILL + 2], wall_clock64() - t0, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
     }
   }
