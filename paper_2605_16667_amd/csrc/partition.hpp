@@ -816,12 +816,17 @@ __device__ __forceinline__ void bucket_body(BinSmem<NT, LOG2W>& S, const uint16_
         project_piece<NT, W / NT, false>(S, status, nitems, items, item_cap, CL2, bp.base, hb, cnt, klast);
     }
   } else {
-    uint64_t fsum = 0;
-    for (uint32_t wv = tid; wv < SM::WORDS; wv += NT) {
-      const uint32_t word = S.s[wv];
-      fsum += (word & 0xFFFFu) + (word >> 16);
+    // fewer than 2^16 keys cannot wrap a field: no check needed
+    bool clean = gathered <= 0xFFFFu;
+    if (!clean) {
+      uint64_t fsum = 0;
+      for (uint32_t wv = tid; wv < SM::WORDS; wv += NT) {
+        const uint32_t word = S.s[wv];
+        fsum += (word & 0xFFFFu) + (word >> 16);
+      }
+      clean = block_sum<NT>(S, fsum) == gathered;
     }
-    if (block_sum<NT>(S, fsum) == gathered) {
+    if (clean) {
       // ---- no field wrapped ------------------------------------------------
       emit_bins<NT, true, HALIGNED>(S, dst, dhb, 0, cnt, split);
       if constexpr (FULL) {
