@@ -21,8 +21,8 @@ using namespace dsh;
 
 namespace dsb {
 
-constexpr uint32_t UNIT_KEYS = 1u << 18;  // target keys per A or B unit
-constexpr uint32_t FILL_PER = 32;         // item slots per fill unit (shared by its waves)
+constexpr uint32_t UNIT_KEYS = 1u << 19;  // target keys per A or B unit
+constexpr uint32_t FILL_PER = 64;         // item slots per fill unit (shared by its waves)
 constexpr uint64_t CLASS_MIN_COST = 1ull << 22;  // keys plus bins of the first size class, at least
 constexpr uint64_t CLASS_GROWTH = 3;             // a class closes at this many times the cost before it
 constexpr uint64_t BT_PACKED_CHUNK_MAX = 1ull << 22;
