@@ -316,7 +316,23 @@ struct BinSmem {
   uint32_t n, item0;
 };
 
-enum GatherMode { GM_PACKED, GM_HALF, GM_DIRECT };
+enum GatherMode { GM_PACKED, GM_PACKED_HOT, GM_HALF, GM_DIRECT };
+
+// GM_PACKED_HOT: as GM_PACKED, except that each wave counts one candidate key
+// in registers (each lane adds its matches to acc; no LDS atomic for them) and
+// flushes the count into the bucket's hot table -- pairs (key, count) in the
+// packed layout's event-log storage (S.ev, unused on this path), numbered by
+// S.nev -- when the candidate changes and when the gather ends.  Every 16th slot looks
+// for a group of AGG_HOT_MIN or more lanes on one key other than the
+// candidate; a group larger than the candidate's in that slot becomes the
+// candidate.  A hot key therefore never passes through a 16-bit field.
+constexpr uint32_t BK_HOTCAP = LDS16_EVCAP / 2;  // hot table entries
+
+struct HotGather {
+  uint32_t hk = 0xFFFFFFFFu;  // wave-uniform; bucket-relative keys are below 2^16
+  uint32_t acc = 0;           // per lane
+  uint32_t slot = 15;         // wave-uniform
+};
 
 // Gather the segments of bucket b and count their relative keys.  GM_PACKED:
 // into the packed 16-bit fields (W = 2^16), with no check for a field passing
@@ -338,9 +354,36 @@ enum GatherMode { GM_PACKED, GM_HALF, GM_DIRECT };
 // segments this thread owned (each segment belongs to one lane of one wave).
 // Count the 8 keys of quad d (tile-local key indices [8q, 8q + 8)) that lie in
 // [s, e) (and, GM_HALF, in half `half`) into S, after the wave merge.
+template <int NT, int LOG2W>
+__device__ __forceinline__ void hot_flush(BinSmem<NT, LOG2W>& S, HotGather& h) {
+  const uint32_t c = __builtin_amdgcn_readfirstlane(wave_sum(h.acc));
+  h.acc = 0;
+  if (c && lane_id() == 0) {
+    const uint32_t i = atomicAdd(&S.nev, 1u);
+    if (i < BK_HOTCAP) {
+      S.ev[2 * i] = h.hk;
+      S.ev[2 * i + 1] = c;
+    }
+  }
+}
+
+// Total count of hot bin k (relative) from the bucket's merged hot table:
+// after the merge each key has one live entry holding field + table counts.
+template <typename SM>
+__device__ __forceinline__ uint32_t hot_total(const SM& S, uint32_t nhot, uint32_t k) {
+  for (uint32_t i = 0; i < nhot; ++i)
+    if (S.ev[2 * i] == k) return S.ev[2 * i + 1];
+  return 0;
+}
+
+template <typename SM>
+__device__ __forceinline__ bool hot_flag(const SM& S, uint32_t k) {
+  return (S.evflag[k >> 5] >> (k & 31)) & 1u;
+}
+
 template <int NT, int LOG2W, int AGG, GatherMode GM>
 __device__ __forceinline__ void count_quad(BinSmem<NT, LOG2W>& S, const uint4& d, int32_t q8, uint32_t s, uint32_t e,
-                                           uint32_t half, WaveAgg& st) {
+                                           uint32_t half, WaveAgg& st, HotGather& h) {
   const int32_t lob = max((int32_t)s - q8, 0), hib = min((int32_t)e - q8, 8);
   const uint32_t qm = hib > lob ? ((1u << hib) - 1u) & ~((1u << lob) - 1u) : 0u;
   const uint32_t wds[4] = {d.x, d.y, d.z, d.w};
@@ -348,6 +391,28 @@ __device__ __forceinline__ void count_quad(BinSmem<NT, LOG2W>& S, const uint4& d
   for (int m = 0; m < 8; ++m) {
     const uint32_t x = (m & 1) ? (wds[m >> 1] >> 16) : (wds[m >> 1] & 0xFFFFu);
     bool ok = (qm >> m) & 1u;
+    if constexpr (GM == GM_PACKED_HOT) {
+      const bool eq = ok && x == h.hk;
+      h.acc += eq ? 1u : 0u;
+      bool act = ok && !eq;
+      if (((++h.slot) & 15u) == 0u) {
+        const uint64_t am = __ballot(act);
+        if (am) {
+          const uint32_t ll = (uint32_t)__ffsll((unsigned long long)am) - 1;
+          const uint32_t lk = (uint32_t)__builtin_amdgcn_readlane((int)x, (int)ll);
+          const bool e2 = act && x == lk;
+          const uint32_t c2 = (uint32_t)__popcll(__ballot(e2));
+          if (c2 >= AGG_HOT_MIN && c2 > (uint32_t)__popcll(__ballot(eq))) {
+            hot_flush(S, h);
+            h.hk = lk;
+            h.acc = e2 ? 1u : 0u;
+            act = act && !e2;
+          }
+        }
+      }
+      if (act) atomicAdd(&S.s[x >> 1], 1u << ((x & 1u) << 4));
+      continue;
+    }
     if (GM == GM_HALF) ok = ok && (x >> 15) == half;
     WaveGroups grp;
     const uint32_t n = wave_merge_count<AGG>(x, ok, st, grp);
@@ -377,6 +442,7 @@ __device__ __forceinline__ uint32_t bucket_gather_few(BinSmem<NT, LOG2W>& S, con
                                                       uint32_t T, uint32_t b, uint32_t half) {
   constexpr uint32_t NW = NT / WAVE;
   WaveAgg st;
+  HotGather h;
   const uint32_t lane = lane_id(), w = threadIdx.x / WAVE;
   const uint4* sq = reinterpret_cast<const uint4*>(staging);
   const uint32_t wpt = T < NW ? NW / T : 1;  // waves per tile
@@ -405,10 +471,11 @@ __device__ __forceinline__ uint32_t bucket_gather_few(BinSmem<NT, LOG2W>& S, con
       for (int j = 0; j < BK_SQ; ++j) {
         const uint32_t q = c0 + j * WAVE + lane;
         // a reread quad counts nothing: its window [8q, 8q + 8) lies past e
-        count_quad<NT, LOG2W, AGG, GM>(S, d[j], (int32_t)(q * 8), s, e, half, st);
+        count_quad<NT, LOG2W, AGG, GM>(S, d[j], (int32_t)(q * 8), s, e, half, st, h);
       }
     }
   }
+  if constexpr (GM == GM_PACKED_HOT) hot_flush(S, h);  // the wave's last candidate
   return counted;
 }
 
@@ -419,6 +486,7 @@ __device__ __forceinline__ uint32_t bucket_gather(BinSmem<NT, LOG2W>& S, const u
   static_assert(TK % 8 == 0 && TK <= 32768, "tile-local key indices and quad offsets fit 16 bits");
   constexpr uint32_t NW = NT / WAVE;
   WaveAgg st;
+  HotGather h;
   const uint32_t lane = lane_id(), w = threadIdx.x / WAVE;
   const uint4* sq = reinterpret_cast<const uint4*>(staging);
   uint32_t counted = 0;
@@ -465,12 +533,13 @@ __device__ __forceinline__ uint32_t bucket_gather(BinSmem<NT, LOG2W>& S, const u
 #pragma unroll
       for (int j = 0; j < BK_SQ; ++j) {
         // valid keys of this quad: tile-local indices [s, e) within [q, q + 8)
-        count_quad<NT, LOG2W, AGG, GM>(S, d[j], (int32_t)((q0 + k0 + j) * 8), s, e, half, st);
+        count_quad<NT, LOG2W, AGG, GM>(S, d[j], (int32_t)((q0 + k0 + j) * 8), s, e, half, st, h);
       }
     }
     lo = nlo;
     hi = nhi;
   }
+  if constexpr (GM == GM_PACKED_HOT) hot_flush(S, h);  // the wave's last candidate
   return counted;
 }
 
@@ -646,7 +715,7 @@ constexpr uint32_t PT_BINS = 1024;
 template <int NT, uint32_t NB, bool PACKED, typename SM>
 __device__ __forceinline__ uint64_t project_piece(SM& S, uint32_t* status, uint32_t* nitems, FillItem* items,
                                                   uint32_t item_cap, int CL2, uint64_t base, uint64_t hb,
-                                                  uint32_t pcnt, uint32_t klast) {
+                                                  uint32_t pcnt, uint32_t klast, uint32_t nhot = 0) {
   constexpr uint32_t G = PT_BINS / NB < (uint32_t)WAVE ? (PT_BINS / NB > 0 ? PT_BINS / NB : 1) : (uint32_t)WAVE;
   static_assert((G & (G - 1)) == 0, "tiles are a power of two of threads");
   const uint32_t tid = threadIdx.x, lane = lane_id();
@@ -661,6 +730,11 @@ __device__ __forceinline__ uint64_t project_piece(SM& S, uint32_t* status, uint3
     for (uint32_t w = 0; w < NW; ++w) {
       const uint32_t word = S.s[(j0 >> 1) + ((w + lane) & (NW - 1))];
       sum += (word & 0xFFFFu) + (word >> 16);
+    }
+    if (nhot) {
+      // hot bins: their merged totals in place of their fields
+      for (uint32_t j = 0; j < NB; ++j)
+        if (hot_flag(S, j0 + j)) sum += hot_total(S, nhot, j0 + j) - packed_count(S, j0 + j);
     }
   } else {
 #pragma unroll 8
@@ -699,8 +773,15 @@ __device__ __forceinline__ uint64_t project_piece(SM& S, uint32_t* status, uint3
   if (item0 == 0xFFFFFFFFu) return tot;
   const uint32_t my0 = item0 + (uint32_t)tile_off;
   if constexpr (PACKED) {
-    auto count = [&](uint32_t i) -> uint32_t { return packed_count(S, i); };
-    emit_items<NT, NB, (NB % 2 == 0)>(S, items, my0, CL2, ts, te, hb, j0, pcnt, base + pre, sum, tklast, count);
+    if (nhot) {
+      auto count = [&](uint32_t i) -> uint32_t {
+        return hot_flag(S, i) ? hot_total(S, nhot, i) : packed_count(S, i);
+      };
+      emit_items<NT, NB, false>(S, items, my0, CL2, ts, te, hb, j0, pcnt, base + pre, sum, tklast, count);
+    } else {
+      auto count = [&](uint32_t i) -> uint32_t { return packed_count(S, i); };
+      emit_items<NT, NB, (NB % 2 == 0)>(S, items, my0, CL2, ts, te, hb, j0, pcnt, base + pre, sum, tklast, count);
+    }
   } else {
     auto count = [&](uint32_t i) -> uint32_t { return S.s[i]; };
     emit_items<NT, NB, false>(S, items, my0, CL2, ts, te, hb, j0, pcnt, base + pre, sum, tklast, count);
@@ -747,14 +828,21 @@ struct BucketPart {
 // lo0).
 template <int NT, bool PACKED_SRC, bool HALIGNED, typename SM>
 __device__ __forceinline__ void emit_bins(const SM& S, uint32_t* __restrict__ H, uint64_t hb, uint32_t lo0,
-                                          uint32_t len, bool add) {
+                                          uint32_t len, bool add, uint32_t nhot = 0) {
   const uint32_t tid = threadIdx.x;
   if constexpr (PACKED_SRC) {
-    // len bins from bin 0, two per word
+    // len bins from bin 0, two per word; with nhot (not add) the flagged hot
+    // bins take their merged totals instead of their fields
     for (uint32_t wv = tid; wv < (len + 1) / 2; wv += NT) {
       const uint32_t k = 2 * wv;
       const uint32_t word = S.s[wv];
-      const uint32_t c0 = word & 0xFFFFu, c1 = word >> 16;
+      uint32_t c0 = word & 0xFFFFu, c1 = word >> 16;
+      if constexpr (SM::PACKED) {
+        if (nhot && ((S.evflag[k >> 5] >> (k & 31)) & 3u)) {
+          if (hot_flag(S, k)) c0 = hot_total(S, nhot, k);
+          if (hot_flag(S, k + 1)) c1 = hot_total(S, nhot, k + 1);
+        }
+      }
       if (add) {
         if (c0) atomicAdd(&H[hb + k], c0);
         if (c1 && k + 1 < len) atomicAdd(&H[hb + k + 1], c1);
@@ -799,10 +887,14 @@ __device__ __forceinline__ void bucket_body(BinSmem<NT, LOG2W>& S, const uint16_
   const bool split = bp.P > 1;
 
   for (uint32_t i = tid; i < SM::WORDS; i += NT) S.s[i] = 0;
+  if constexpr (SM::PACKED) {
+    for (uint32_t i = tid; i < 65536 / 32; i += NT) S.evflag[i] = 0;  // hot-bin flags
+    if (tid == 0) S.nev = 0;                                          // hot table entries
+  }
   __syncthreads();
-  const uint32_t mine =
-      bucket_gather<NT, LOG2W, AGG, SM::PACKED ? GM_PACKED : GM_DIRECT, TK>(S, staging, seg, bstride, bp.t0, bp.t1, b, 0);
-  // the block sums end with barriers: every LDS count is in place afterwards
+  const uint32_t mine = bucket_gather<NT, LOG2W, AGG, SM::PACKED ? GM_PACKED_HOT : GM_DIRECT, TK>(
+      S, staging, seg, bstride, bp.t0, bp.t1, b, 0);
+  // the block sums end with barriers: every LDS count and hot entry is in place afterwards
   const uint64_t gathered = block_sum<NT>(S, (uint64_t)mine);
 
   // a split part adds into its bucket's scratch row instead of H
@@ -816,18 +908,60 @@ __device__ __forceinline__ void bucket_body(BinSmem<NT, LOG2W>& S, const uint16_
         project_piece<NT, W / NT, false>(S, status, nitems, items, item_cap, CL2, bp.base, hb, cnt, klast);
     }
   } else {
-    // fewer than 2^16 keys cannot wrap a field: no check needed
-    bool clean = gathered <= 0xFFFFu;
-    if (!clean) {
+    // The hot keys counted in registers sit in the hot table (nhot entries;
+    // a table that overflowed lost entries, and the bucket is counted again).
+    // The fields hold the other keys: fewer than 2^16 keys cannot wrap one,
+    // otherwise the fields must sum to the keys gathered less the table's.
+    const uint32_t nev = S.nev;
+    const uint32_t nhot = nev < BK_HOTCAP ? nev : BK_HOTCAP;
+    bool clean = nev <= BK_HOTCAP;
+    if (clean && gathered > 0xFFFFu) {
       uint64_t fsum = 0;
       for (uint32_t wv = tid; wv < SM::WORDS; wv += NT) {
         const uint32_t word = S.s[wv];
         fsum += (word & 0xFFFFu) + (word >> 16);
       }
+      for (uint32_t i = tid; i < nhot; i += NT) fsum += S.ev[2 * i + 1];
       clean = block_sum<NT>(S, fsum) == gathered;
     }
-    if (clean) {
-      // ---- no field wrapped ------------------------------------------------
+    if (clean && nhot > 0 && split) {
+      // ---- a part with hot keys: fields and table entries all added -------
+      emit_bins<NT, true, HALIGNED>(S, dst, dhb, 0, cnt, true);
+      for (uint32_t i = tid; i < nhot; i += NT) atomicAdd(&dst[S.ev[2 * i]], S.ev[2 * i + 1]);
+    } else if (clean && nhot > 0) {
+      // ---- hot keys: merge the table into one entry per key holding the
+      // bin's total (its field plus all its entries), flag the hot bins, and
+      // read counts through the table where flagged ------------------------
+      uint32_t tot = 0, live = 0;
+      if (tid < nhot) {
+        const uint32_t k = S.ev[2 * tid];
+        live = 1;
+        for (uint32_t j = 0; j < tid; ++j)
+          if (S.ev[2 * j] == k) live = 0;  // an earlier entry holds this key
+        if (live) {
+          tot = packed_count(S, k);
+          for (uint32_t j = tid; j < nhot; ++j)
+            if (S.ev[2 * j] == k) tot += S.ev[2 * j + 1];
+        }
+      }
+      __syncthreads();
+      if (tid < nhot) {
+        const uint32_t k = S.ev[2 * tid];
+        if (live) {
+          S.ev[2 * tid + 1] = tot;
+          atomicOr(&S.evflag[k >> 5], 1u << (k & 31));
+        }
+      }
+      __syncthreads();
+      if (tid < nhot && !live) S.ev[2 * tid] = 0xFFFFFFFFu;  // no bin matches it
+      __syncthreads();
+      emit_bins<NT, true, HALIGNED>(S, dst, dhb, 0, cnt, false, nhot);
+      if constexpr (FULL) {
+        if (gathered)
+          project_piece<NT, W / NT, true>(S, status, nitems, items, item_cap, CL2, bp.base, hb, cnt, klast, nhot);
+      }
+    } else if (clean) {
+      // ---- no field wrapped, no hot key -----------------------------------
       emit_bins<NT, true, HALIGNED>(S, dst, dhb, 0, cnt, split);
       if constexpr (FULL) {
         if (!split && gathered)

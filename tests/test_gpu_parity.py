@@ -306,3 +306,41 @@ def test_range_report_through_partial_rows(ds, U):
         assert ds.dialsort_status_sync(ws) == ds.DIALSORT_OK
         _, H_ref, out_ref = oracle.sort(w.as_u32(good), U)
         assert np.array_equal(w.as_u32(H), H_ref) and np.array_equal(w.as_u32(out), out_ref)
+
+
+@pytest.mark.parametrize("case", ["one_hot_whole_bucket", "one_hot_split_bucket", "three_hot_fields_wrap",
+                                  "many_runs"])
+def test_partitioned_hot_keys(ds, case):
+    """Partitioned path (U = 2^20 + 1, buckets of 2^16 bins) with keys whose
+    counts pass 2^16 inside one bucket.  The bucket pass counts each wave's
+    hot key in registers: a whole bucket reads such a bin through its hot
+    table, a part of a split bucket adds the table into the scratch row, and
+    a bucket whose other keys still wrap a 16-bit field is counted again in
+    halves.  The last case, 400 keys of one bucket in runs of equal keys,
+    makes the candidates change often."""
+    rng = np.random.default_rng(SEED + ["one_hot_whole_bucket", "one_hot_split_bucket", "three_hot_fields_wrap",
+                                        "many_runs"].index(case))
+    U = (1 << 20) + 1
+    if case == "one_hot_whole_bucket":
+        # 200 000 copies of one key; its bucket stays whole (below 2 chunks)
+        keys = rng.integers(0, U, 400_000).astype(np.uint32)
+        keys = np.concatenate([keys, np.full(200_000, 3 * 65536 + 777, dtype=np.uint32)])
+    elif case == "one_hot_split_bucket":
+        # 2 million copies of one key: its bucket is split into parts, each
+        # holding far more than 2^16 copies
+        keys = rng.integers(0, U, 1_000_000).astype(np.uint32)
+        keys = np.concatenate([keys, np.full(2_000_000, 9 * 65536 + 12345, dtype=np.uint32)])
+    elif case == "three_hot_fields_wrap":
+        # three keys of 150 000 copies each in one whole bucket: a wave has one
+        # candidate, so the others' 16-bit fields wrap
+        keys = rng.integers(0, U, 300_000).astype(np.uint32)
+        hot = [5 * 65536 + 1, 5 * 65536 + 2, 5 * 65536 + 60000]
+        keys = np.concatenate([keys] + [np.full(150_000, h, dtype=np.uint32) for h in hot])
+    else:
+        # 400 keys of one bucket in runs of 1500 equal keys, in order
+        runs = [np.full(1500, 7 * 65536 + 97 * i, dtype=np.uint32) for i in range(400)]
+        keys = np.concatenate([rng.integers(0, U, 100_000).astype(np.uint32)] + runs)
+    if case != "many_runs":
+        rng.shuffle(keys)
+    assert_parity(ds, keys, U, label=case)
+    assert_parity(ds, keys, U, mode="hist", label=case)
