@@ -263,6 +263,7 @@ __device__ __forceinline__ void hist_slab(SM& S, const uint32_t* __restrict__ ke
     for (uint32_t i = tid; i < U; i += NT) row[i] = S.s[i];
   } else {
     const uint32_t ne = S.nev < LDS16_EVCAP ? S.nev : LDS16_EVCAP;
+    const bool r8 = (reinterpret_cast<uintptr_t>(row) & 7u) == 0;  // a pair of bins per 8-byte store
     if (tid == 0 && S.nev > LDS16_EVCAP) atomicOr(status, ST_INT_EVLOG);  // cannot happen within the key bound
     for (uint32_t w = tid; w < nwords; w += NT) {
       const uint32_t word = S.s[w];
@@ -279,8 +280,12 @@ __device__ __forceinline__ void hist_slab(SM& S, const uint32_t* __restrict__ ke
           }
         }
       }
-      row[2 * w] = (uint32_t)cnt[0];
-      if (2 * w + 1 < U) row[2 * w + 1] = (uint32_t)cnt[1];
+      if (r8 && 2 * w + 1 < U) {
+        *reinterpret_cast<uint2*>(row + 2 * w) = make_uint2((uint32_t)cnt[0], (uint32_t)cnt[1]);
+      } else {
+        row[2 * w] = (uint32_t)cnt[0];
+        if (2 * w + 1 < U) row[2 * w + 1] = (uint32_t)cnt[1];
+      }
     }
   }
 }

@@ -150,8 +150,14 @@ __global__ __launch_bounds__(NT) void k_scan(const uint32_t* __restrict__ rows, 
     const uint64_t k = base + (uint64_t)j * NT + tid;
     uint32_t a = 0;
     if (k < U) {
+      if constexpr (VPT == 1) {
+        // one bin per thread: 16 rows' loads in flight at once
+#pragma unroll 16
+        for (uint32_t r = 0; r < nrows; ++r) a += rows[(uint64_t)r * row_stride + k];
+      } else {
 #pragma unroll 8
-      for (uint32_t r = 0; r < nrows; ++r) a += rows[(uint64_t)r * row_stride + k];
+        for (uint32_t r = 0; r < nrows; ++r) a += rows[(uint64_t)r * row_stride + k];
+      }
       if (H_out) H_out[k] = a;
     }
     v[j] = a;
