@@ -203,16 +203,16 @@ dialsort_status launch_ingest(const uint32_t* keys, uint64_t n, uint64_t U, uint
   const uint64_t nclr = fi && L.scan ? L.scan_tiles : 0;
   switch (L.kind) {
     case K_LDS32S:
-      if (ka) DS_LAUNCH((k_hist_lds<1024, 4096, false, 6, true, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo, fi, clr, nclr);
-      else DS_LAUNCH((k_hist_lds<1024, 4096, false, 6, false, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo, fi, clr, nclr);
+      if (ka) DS_LAUNCH((k_hist_lds<1024, 4096, false, 8, true, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo, fi, clr, nclr);
+      else DS_LAUNCH((k_hist_lds<1024, 4096, false, 8, false, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo, fi, clr, nclr);
       break;
     case K_LDS32:
-      if (ka) DS_LAUNCH((k_hist_lds<1024, 32768, false, 6, true, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo, fi, clr, nclr);
-      else DS_LAUNCH((k_hist_lds<1024, 32768, false, 6, false, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo, fi, clr, nclr);
+      if (ka) DS_LAUNCH((k_hist_lds<1024, 32768, false, 8, true, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo, fi, clr, nclr);
+      else DS_LAUNCH((k_hist_lds<1024, 32768, false, 8, false, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo, fi, clr, nclr);
       break;
     case K_LDS16:
-      if (ka) DS_LAUNCH((k_hist_lds<1024, 32768, true, 6, true, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo, fi, clr, nclr);
-      else DS_LAUNCH((k_hist_lds<1024, 32768, true, 6, false, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo, fi, clr, nclr);
+      if (ka) DS_LAUNCH((k_hist_lds<1024, 32768, true, 8, true, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo, fi, clr, nclr);
+      else DS_LAUNCH((k_hist_lds<1024, 32768, true, 8, false, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo, fi, clr, nclr);
       break;
     case K_PART: {
       uint16_t* stg = (uint16_t*)(base + L.off_stage);

@@ -141,15 +141,18 @@ __device__ __forceinline__ void hist_slab(SM& S, const uint32_t* __restrict__ ke
       }
     }
   };
-  // One slot of AGG 6: returns the count this lane adds to its key's bin
-  // (0 or 1), after counting a match of the candidate in registers.  The
+  // One slot of AGG 6 / 8: cin is the lane's count for its key in this slot
+  // (1, or with AGG 8 its run's length, 0 for an invalid or merged key);
+  // returns what the lane adds to its key's bin, after counting a match of
+  // the candidate in registers.  The
   // first slot of every iteration (probe) also looks for a group of
   // AGG_HOT_MIN or more lanes on one key other than the candidate; a group
   // larger than the candidate's in that slot takes its place, so the
   // candidate settles on the key most lanes share.
-  auto slot_count6 = [&](uint32_t x, bool ok, bool probe) -> uint32_t {
+  auto slot_count6 = [&](uint32_t x, uint32_t cin, bool probe) -> uint32_t {
+    const bool ok = cin != 0;
     const bool eq = ok && x == hk;
-    acc += eq ? 1u : 0u;
+    acc += eq ? cin : 0u;
     bool act = ok && !eq;
     if (probe) {
       const uint64_t am = __ballot(act);
@@ -161,16 +164,34 @@ __device__ __forceinline__ void hist_slab(SM& S, const uint32_t* __restrict__ ke
         if (c2 >= AGG_HOT_MIN && c2 > (uint32_t)__popcll(__ballot(eq))) {
           flush();
           hk = lk;
-          acc = eq2 ? 1u : 0u;
+          acc = eq2 ? cin : 0u;
           act = act && !eq2;
         }
       }
     }
-    return act ? 1u : 0u;
+    return act ? cin : 0u;
+  };
+  // AGG 8 adds the lane-local merge (a3): the 4 keys a lane loads together
+  // are consecutive in memory, and a run of equal ones among them is counted
+  // once, by its first key carrying the run's length (equality tests only);
+  // the others carry 0.  run[i] is that count; ok[i] marks valid keys.
+  auto lane_runs = [&](const uint32_t (&x)[4], const bool (&ok)[4], uint32_t (&run)[4]) {
+    bool eqn[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) eqn[i] = ok[i] && ok[i + 1] && x[i] == x[i + 1];
+    uint32_t r = ok[3] ? 1u : 0u;
+    run[3] = r;
+#pragma unroll
+    for (int i = 2; i >= 0; --i) {
+      r = ok[i] ? (eqn[i] ? r + 1 : 1u) : 0u;
+      run[i] = r;
+    }
+#pragma unroll
+    for (int i = 1; i < 4; ++i) run[i] = eqn[i - 1] ? 0u : run[i];
   };
   // uniform trip count across the workgroup: every lane takes part in the ballots
   for (uint64_t g0 = beg; g0 < end; g0 += (uint64_t)NT * 4 * UNR) {
-    if constexpr (AGG == 6 && PACKED) {
+    if constexpr (AGG >= 6 && PACKED) {
       if (++since > HOT_FLUSH_ITERS) flush();
     }
     uint32_t v[UNR][4];
@@ -190,11 +211,16 @@ __device__ __forceinline__ void hist_slab(SM& S, const uint32_t* __restrict__ ke
     if (clean) {
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
+        uint32_t run[4] = {1u, 1u, 1u, 1u};
+        if constexpr (AGG == 8) {
+          const bool all[4] = {true, true, true, true};
+          lane_runs(v[u], all, run);
+        }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           uint32_t c;
-          if constexpr (AGG == 6) {
-            c = slot_count6(v[u][i], true, u == 0 && i == 0);
+          if constexpr (AGG >= 6) {
+            c = slot_count6(v[u][i], run[i], u == 0 && i == 0);
           } else {
             WaveGroups g;
             c = wave_merge_count<AGG>(v[u][i], true, st, g);
@@ -211,14 +237,23 @@ __device__ __forceinline__ void hist_slab(SM& S, const uint32_t* __restrict__ ke
     } else {
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
+        bool oks[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const bool valid = (uint32_t)i < nv[u];
-          const bool ok = valid && v[u][i] <= umax;
-          bad |= valid && !ok;
+          oks[i] = valid && v[u][i] <= umax;
+          bad |= valid && !oks[i];
+        }
+        uint32_t run[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) run[i] = oks[i] ? 1u : 0u;
+        if constexpr (AGG == 8) lane_runs(v[u], oks, run);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const bool ok = oks[i];
           uint32_t c;
-          if constexpr (AGG == 6) {
-            c = slot_count6(v[u][i], ok, u == 0 && i == 0);
+          if constexpr (AGG >= 6) {
+            c = slot_count6(v[u][i], run[i], u == 0 && i == 0);
           } else {
             WaveGroups g;
             c = wave_merge_count<AGG>(v[u][i], ok, st, g);
@@ -256,7 +291,7 @@ __device__ __forceinline__ void hist_slab(SM& S, const uint32_t* __restrict__ ke
       }
     }
   }
-  if constexpr (AGG == 6) flush();
+  if constexpr (AGG >= 6) flush();
   if (__syncthreads_or(bad) && tid == 0) atomicOr(status, ST_RANGE);
 
   if constexpr (!PACKED) {
