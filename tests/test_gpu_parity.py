@@ -344,3 +344,14 @@ def test_partitioned_hot_keys(ds, case):
         rng.shuffle(keys)
     assert_parity(ds, keys, U, label=case)
     assert_parity(ds, keys, U, mode="hist", label=case)
+
+
+@pytest.mark.parametrize("dist", ["sorted", "reverse"])
+@pytest.mark.parametrize("U", [4096, 40001, 65536])
+def test_sorted_runs_large(ds, dist, U):
+    """2^24 sorted or reverse-sorted keys: every lane's 16-byte load holds a
+    run of equal keys, merged in the lane before the wave merge, on the
+    32-bit and the packed 16-bit LDS paths."""
+    keys = w.as_u32(w.PAPER_DISTRIBUTIONS[dist](1 << 24, U, SEED + 5))
+    assert_parity(ds, keys, U, label=f"{dist} 2^24")
+    assert_parity(ds, keys, U, mode="hist", label=f"{dist} 2^24")
