@@ -316,22 +316,25 @@ struct BinSmem {
   uint32_t n, item0;
 };
 
-enum GatherMode { GM_PACKED, GM_PACKED_HOT, GM_HALF, GM_DIRECT };
+enum GatherMode { GM_PACKED, GM_PACKED_HOT, GM_PACKED_HOT2, GM_HALF, GM_DIRECT };
 
-// GM_PACKED_HOT: as GM_PACKED, except that each wave counts one candidate key
-// in registers (each lane adds its matches to acc; no LDS atomic for them) and
-// flushes the count into the bucket's hot table -- pairs (key, count) in the
-// packed layout's event-log storage (S.ev, unused on this path), numbered by
-// S.nev -- when the candidate changes and when the gather ends.  Every 16th slot looks
-// for a group of AGG_HOT_MIN or more lanes on one key other than the
-// candidate; a group larger than the candidate's in that slot becomes the
-// candidate.  A hot key therefore never passes through a 16-bit field.
+// GM_PACKED_HOT (GM_PACKED_HOT2): as GM_PACKED, except that each wave counts
+// one (two) candidate keys in registers (each lane adds its matches to acc; no
+// LDS atomic for them) and flushes a candidate's count into the bucket's hot
+// table -- pairs (key, count) in the packed layout's event-log storage (S.ev,
+// unused on this path), numbered by S.nev -- when the candidate changes and
+// when the gather ends.  Every 16th slot looks for a group of AGG_HOT_MIN or
+// more lanes on one key that is no candidate; a group larger than the
+// (smaller) candidate's group in that slot replaces that candidate.  A hot key
+// therefore never passes through a 16-bit field.  The second candidate costs
+// every key a compare, so a bucket is gathered with one, and again with two
+// only if another key wrapped a field.
 constexpr uint32_t BK_HOTCAP = LDS16_EVCAP / 2;  // hot table entries
 
 struct HotGather {
-  uint32_t hk = 0xFFFFFFFFu;  // wave-uniform; bucket-relative keys are below 2^16
-  uint32_t acc = 0;           // per lane
-  uint32_t slot = 15;         // wave-uniform
+  uint32_t hk[2] = {0xFFFFFFFFu, 0xFFFFFFFFu};  // wave-uniform; bucket-relative keys are below 2^16
+  uint32_t acc[2] = {0, 0};                      // per lane
+  uint32_t slot = 15;                            // wave-uniform
 };
 
 // Gather the segments of bucket b and count their relative keys.  GM_PACKED:
@@ -355,13 +358,13 @@ struct HotGather {
 // Count the 8 keys of quad d (tile-local key indices [8q, 8q + 8)) that lie in
 // [s, e) (and, GM_HALF, in half `half`) into S, after the wave merge.
 template <int NT, int LOG2W>
-__device__ __forceinline__ void hot_flush(BinSmem<NT, LOG2W>& S, HotGather& h) {
-  const uint32_t c = __builtin_amdgcn_readfirstlane(wave_sum(h.acc));
-  h.acc = 0;
+__device__ __forceinline__ void hot_flush(BinSmem<NT, LOG2W>& S, HotGather& h, int j) {
+  const uint32_t c = __builtin_amdgcn_readfirstlane(wave_sum(h.acc[j]));
+  h.acc[j] = 0;
   if (c && lane_id() == 0) {
     const uint32_t i = atomicAdd(&S.nev, 1u);
     if (i < BK_HOTCAP) {
-      S.ev[2 * i] = h.hk;
+      S.ev[2 * i] = h.hk[j];
       S.ev[2 * i + 1] = c;
     }
   }
@@ -391,10 +394,12 @@ __device__ __forceinline__ void count_quad(BinSmem<NT, LOG2W>& S, const uint4& d
   for (int m = 0; m < 8; ++m) {
     const uint32_t x = (m & 1) ? (wds[m >> 1] >> 16) : (wds[m >> 1] & 0xFFFFu);
     bool ok = (qm >> m) & 1u;
-    if constexpr (GM == GM_PACKED_HOT) {
-      const bool eq = ok && x == h.hk;
-      h.acc += eq ? 1u : 0u;
-      bool act = ok && !eq;
+    if constexpr (GM == GM_PACKED_HOT || GM == GM_PACKED_HOT2) {
+      constexpr bool TWO = GM == GM_PACKED_HOT2;
+      const bool eq0 = ok && x == h.hk[0], eq1 = TWO && ok && x == h.hk[1];
+      h.acc[0] += eq0 ? 1u : 0u;
+      if constexpr (TWO) h.acc[1] += eq1 ? 1u : 0u;
+      bool act = ok && !eq0 && !eq1;
       if (((++h.slot) & 15u) == 0u) {
         const uint64_t am = __ballot(act);
         if (am) {
@@ -402,10 +407,13 @@ __device__ __forceinline__ void count_quad(BinSmem<NT, LOG2W>& S, const uint4& d
           const uint32_t lk = (uint32_t)__builtin_amdgcn_readlane((int)x, (int)ll);
           const bool e2 = act && x == lk;
           const uint32_t c2 = (uint32_t)__popcll(__ballot(e2));
-          if (c2 >= AGG_HOT_MIN && c2 > (uint32_t)__popcll(__ballot(eq))) {
-            hot_flush(S, h);
-            h.hk = lk;
-            h.acc = e2 ? 1u : 0u;
+          const uint32_t n0 = (uint32_t)__popcll(__ballot(eq0));
+          const uint32_t n1 = TWO ? (uint32_t)__popcll(__ballot(eq1)) : 0xFFFFFFFFu;
+          const int jm = n1 < n0 ? 1 : 0;  // the candidate with the smaller group here
+          if (c2 >= AGG_HOT_MIN && c2 > (jm ? n1 : n0)) {
+            hot_flush(S, h, jm);
+            h.hk[jm] = lk;
+            h.acc[jm] = e2 ? 1u : 0u;
             act = act && !e2;
           }
         }
@@ -475,7 +483,10 @@ __device__ __forceinline__ uint32_t bucket_gather_few(BinSmem<NT, LOG2W>& S, con
       }
     }
   }
-  if constexpr (GM == GM_PACKED_HOT) hot_flush(S, h);  // the wave's last candidate
+  if constexpr (GM == GM_PACKED_HOT || GM == GM_PACKED_HOT2) {  // the wave's last candidates
+    hot_flush(S, h, 0);
+    if constexpr (GM == GM_PACKED_HOT2) hot_flush(S, h, 1);
+  }
   return counted;
 }
 
@@ -539,7 +550,10 @@ __device__ __forceinline__ uint32_t bucket_gather(BinSmem<NT, LOG2W>& S, const u
     lo = nlo;
     hi = nhi;
   }
-  if constexpr (GM == GM_PACKED_HOT) hot_flush(S, h);  // the wave's last candidate
+  if constexpr (GM == GM_PACKED_HOT || GM == GM_PACKED_HOT2) {  // the wave's last candidates
+    hot_flush(S, h, 0);
+    if constexpr (GM == GM_PACKED_HOT2) hot_flush(S, h, 1);
+  }
   return counted;
 }
 
@@ -912,17 +926,32 @@ __device__ __forceinline__ void bucket_body(BinSmem<NT, LOG2W>& S, const uint16_
     // a table that overflowed lost entries, and the bucket is counted again).
     // The fields hold the other keys: fewer than 2^16 keys cannot wrap one,
     // otherwise the fields must sum to the keys gathered less the table's.
-    const uint32_t nev = S.nev;
-    const uint32_t nhot = nev < BK_HOTCAP ? nev : BK_HOTCAP;
-    bool clean = nev <= BK_HOTCAP;
-    if (clean && gathered > 0xFFFFu) {
-      uint64_t fsum = 0;
-      for (uint32_t wv = tid; wv < SM::WORDS; wv += NT) {
-        const uint32_t word = S.s[wv];
-        fsum += (word & 0xFFFFu) + (word >> 16);
+    auto check = [&](uint32_t& nhot) -> bool {
+      const uint32_t nev = S.nev;
+      nhot = nev < BK_HOTCAP ? nev : BK_HOTCAP;
+      bool ok = nev <= BK_HOTCAP;
+      if (ok && gathered > 0xFFFFu) {
+        uint64_t fsum = 0;
+        for (uint32_t wv = tid; wv < SM::WORDS; wv += NT) {
+          const uint32_t word = S.s[wv];
+          fsum += (word & 0xFFFFu) + (word >> 16);
+        }
+        for (uint32_t i = tid; i < nhot; i += NT) fsum += S.ev[2 * i + 1];
+        ok = block_sum<NT>(S, fsum) == gathered;
       }
-      for (uint32_t i = tid; i < nhot; i += NT) fsum += S.ev[2 * i + 1];
-      clean = block_sum<NT>(S, fsum) == gathered;
+      return ok;
+    };
+    uint32_t nhot = 0;
+    bool clean = check(nhot);
+    if (!clean) {
+      // a second key wrapped a field: gather again with two candidates per wave
+      __syncthreads();
+      for (uint32_t i = tid; i < SM::WORDS; i += NT) S.s[i] = 0;
+      if (tid == 0) S.nev = 0;
+      __syncthreads();
+      bucket_gather<NT, LOG2W, AGG, GM_PACKED_HOT2, TK>(S, staging, seg, bstride, bp.t0, bp.t1, b, 0);
+      __syncthreads();
+      clean = check(nhot);
     }
     if (clean && nhot > 0 && split) {
       // ---- a part with hot keys: fields and table entries all added -------
