@@ -161,7 +161,12 @@ dialsort_status dialsort_reconstruct(const uint32_t *H, uint64_t U, uint32_t *ou
 /* Ingestion followed by the ordered projection: H as in dialsort_histogram and
  * out[0 .. n) = the keys in nondecreasing order (Theorem "thm:correct").  out may
  * equal keys: the projection is then written in place over the input, as the
- * paper's implementation does (Sec. 9.2, Table "tab:struct_cost"). */
+ * paper's implementation does (Sec. 9.2, Table "tab:struct_cost").  A small sort
+ * with U <= 65536 (up to 16 keys per 1024 bins, at most 2^24 keys) is one kernel
+ * launch whose scan blocks wait for flags carrying a value the host draws per
+ * call; on a stream that is capturing a graph (where replays would repeat that
+ * value) the same sort is enqueued as two launches instead, so a captured sort
+ * replays exactly. */
 dialsort_status dialsort_sort(const uint32_t *keys, uint64_t n, uint64_t U, uint32_t *H,
                               uint32_t *out, void *ws, size_t ws_bytes, hipStream_t stream);
 

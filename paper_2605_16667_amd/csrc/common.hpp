@@ -34,6 +34,7 @@ constexpr uint32_t ST_INT_ITEMS = ST_INTERNAL | 0x40000000u;  // fill-item list 
 constexpr uint32_t ST_INT_ITEM = ST_INTERNAL | 0x20000000u;   // a fill item outside its array
 constexpr uint32_t ST_INT_EVLOG = ST_INTERNAL | 0x10000000u;  // packed-counter event log full
 constexpr uint32_t ST_INT_UNIT = ST_INTERNAL | 0x08000000u;   // unknown work unit
+constexpr uint32_t ST_INT_WAIT = ST_INTERNAL | 0x04000000u;   // a one-launch sort gave up waiting for its rows
 constexpr uint64_t SAT_MAX = (uint64_t(1) << 62) - 1;
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
@@ -62,6 +63,20 @@ __device__ __forceinline__ T wave_sum(T x) {
 #pragma unroll
   for (int d = WAVE / 2; d >= 1; d >>= 1) x += __shfl_xor(x, d, WAVE);
   return x;
+}
+
+// Sum over each 32-lane half of the wave, left in lanes 31 and 63: prefix sums
+// within each row of 16 lanes (DPP row shifts, lanes shifted in read 0), then
+// row 0's total added into row 1 and row 2's into row 3 (DPP row broadcast of
+// lane 15).  Every lane must be active.
+__device__ __forceinline__ uint32_t half_wave_sum(uint32_t x) {
+  int v = (int)x;
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, true);   // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, true);   // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, true);   // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, true);   // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);  // row_bcast:15 into rows 1 and 3
+  return (uint32_t)v;
 }
 
 // Maximum over the wave, in a scalar register (the same in every lane).

@@ -7,6 +7,7 @@
 // atomics -- except an LDS ingestion into partial rows, which clears them
 // itself):
 //   LDS32 / LDS16 (U <= 65536):  k_hist_lds -> [k_scan: sum rows into H]
+//   small LDS sorts:               k_sort_lds alone (counting and scan in one launch)
 //   PART (65536 < U <= 2^29):     k_partition -> k_bucket (H, and fill items)
 //   GLOBAL (tiny n, or U > 2^29): k_hist_global
 //   sort adds                      [k_scan: look-back scan + fill items] -> k_fill
@@ -14,8 +15,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cstring>
 #include <mutex>
+#include <random>
 #include <vector>
 
 #include "../../include/dialsort.h"
@@ -24,6 +28,7 @@
 #include "hist_lds.hpp"
 #include "partition.hpp"
 #include "scan_fill.hpp"
+#include "sort_lds.hpp"
 
 using namespace ds;
 using namespace dsh;
@@ -42,6 +47,8 @@ constexpr int SCAN_NT = 256;
 constexpr uint64_t PART_NCU = 256;  // compute units of the target (MI355X)
 constexpr uint64_t DIRECT_NMAX = 1ull << 24;     // direct projection from the scan: at most this many keys,
 constexpr uint64_t DIRECT_PER_TILE = 1ull << 14;  // and at most this many per scan tile on average
+constexpr int FUSED_NT = 1024;  // one-launch sort: threads per block
+constexpr uint64_t FUSED_PER_SLICE = 1ull << 14;  // and at most this many keys per slice of bins on average
 
 enum Kind { K_EMPTY, K_LDS32S, K_LDS32, K_LDS16, K_PART, K_GLOBAL, K_NONE };
 
@@ -53,9 +60,13 @@ struct Layout {
   uint32_t X = 0;        // PART: extra workgroups for the parts of heavy buckets
   uint64_t chunk = 0;    // PART: keys per part of a heavy bucket
   bool rows_in_ws = false;
+  bool row16 = false;    // partial rows hold 16-bit counts, two bins per word (fewer than 2^16 keys per row)
   uint64_t row_stride = 0;
   bool scan = false;     // full projection
   bool direct = false;   // LDS paths, sort: the scan tiles write the output (no fill items)
+  bool fused = false;    // LDS paths, sort: k_sort_lds may do the whole sort in one launch
+  uint32_t NS = 0;       // its slices of bins
+  size_t off_pre = 0, off_flags = 0;  // its per-slab slice prefixes (G x (NS + 1)) and G publication flags
   int scan_vpt = 16;
   uint64_t scan_tiles = 0;
   uint64_t limit = 0;
@@ -74,7 +85,9 @@ uint32_t choose_G(uint64_t n, uint64_t U, uint32_t gmax, uint64_t max_per) {
   double best_t = 1e30;
   for (uint32_t g = 1; g <= gmax; g *= 2) {
     uint32_t gg = std::max(g, g_lo);
-    const double t = 4.0 * n / std::min(BWR, gg * RWG) + gg * U * 4.0 / BWW + gg * U * 4.0 / BWR +
+    // bytes per bin of a partial row: 2 when a row counts fewer than 2^16 keys
+    const double rb = gg > 1 && align_up(cdiv(n, gg), 4) < 65536 ? 2.0 : 4.0;
+    const double t = 4.0 * n / std::min(BWR, gg * RWG) + gg * U * rb / BWW + gg * U * rb / BWR +
                      (gg > 1 ? (gg / 8.0) * 1.0e-6 * (U < 16384 ? 1.0 : 0.1) : 0.0);
     if (t < best_t) { best_t = t; best = gg; }
   }
@@ -116,6 +129,7 @@ Layout plan(uint64_t n, uint64_t U, int mode) {
     L.per = align_up(cdiv(n, L.G), 4);
     L.G = (uint32_t)cdiv(n, L.per);
     L.rows_in_ws = L.G > 1;
+    L.row16 = L.rows_in_ws && L.per < 65536;
     L.row_stride = align_up(U + 1, 64);
   }
   // scan tiles (also used to sum partial rows in histogram mode); the
@@ -126,8 +140,20 @@ Layout plan(uint64_t n, uint64_t U, int mode) {
   // from the scan itself: one launch and the fill items fewer
   L.direct = mode == DIALSORT_MODE_SORT && (L.kind == K_LDS32S || L.kind == K_LDS32 || L.kind == K_LDS16) &&
              n <= DIRECT_NMAX && n <= DIRECT_PER_TILE * L.scan_tiles;
+  // one launch for the whole sort (k_sort_lds): 16-bit rows, and a slice of
+  // bins holds few output positions on average (whether the grid fits the
+  // device is checked at launch)
+  if (mode == DIALSORT_MODE_SORT && L.row16) {
+    const uint64_t ns = cdiv(U, (uint64_t)SLICE);
+    L.fused = ns <= FUSED_SLICES_MAX && n <= DIRECT_NMAX && n <= FUSED_PER_SLICE * ns;
+    L.NS = L.fused ? (uint32_t)ns : 0;
+  }
   if (L.scan) {
     L.off_tile = off; off = align_up(off + L.scan_tiles * 8, ALIGN);
+  }
+  if (L.fused) {
+    L.off_pre = off; off = align_up(off + (size_t)L.G * (L.NS + 1) * 4, ALIGN);
+    L.off_flags = off; off = align_up(off + (size_t)L.G * 8, ALIGN);
   }
   if (L.scan && !L.direct) {
     // one item per chunk of output positions, plus one per span boundary that
@@ -203,16 +229,16 @@ dialsort_status launch_ingest(const uint32_t* keys, uint64_t n, uint64_t U, uint
   const uint64_t nclr = fi && L.scan ? L.scan_tiles : 0;
   switch (L.kind) {
     case K_LDS32S:
-      if (ka) DS_LAUNCH((k_hist_lds<1024, 4096, false, 8, true, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo, fi, clr, nclr);
-      else DS_LAUNCH((k_hist_lds<1024, 4096, false, 8, false, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo, fi, clr, nclr);
+      if (ka) DS_LAUNCH((k_hist_lds<1024, 4096, false, 8, true, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo, fi, clr, nclr, L.row16 ? 1u : 0u);
+      else DS_LAUNCH((k_hist_lds<1024, 4096, false, 8, false, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo, fi, clr, nclr, L.row16 ? 1u : 0u);
       break;
     case K_LDS32:
-      if (ka) DS_LAUNCH((k_hist_lds<1024, 32768, false, 8, true, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo, fi, clr, nclr);
-      else DS_LAUNCH((k_hist_lds<1024, 32768, false, 8, false, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo, fi, clr, nclr);
+      if (ka) DS_LAUNCH((k_hist_lds<1024, 32768, false, 8, true, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo, fi, clr, nclr, L.row16 ? 1u : 0u);
+      else DS_LAUNCH((k_hist_lds<1024, 32768, false, 8, false, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo, fi, clr, nclr, L.row16 ? 1u : 0u);
       break;
     case K_LDS16:
-      if (ka) DS_LAUNCH((k_hist_lds<1024, 32768, true, 8, true, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo, fi, clr, nclr);
-      else DS_LAUNCH((k_hist_lds<1024, 32768, true, 8, false, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo, fi, clr, nclr);
+      if (ka) DS_LAUNCH((k_hist_lds<1024, 32768, true, 8, true, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo, fi, clr, nclr, L.row16 ? 1u : 0u);
+      else DS_LAUNCH((k_hist_lds<1024, 32768, true, 8, false, 4>), dim3(L.G), dim3(1024), s, keys, n, L.per, umax, (uint32_t)U, rows, L.row_stride, ctl, lo, fi, clr, nclr, L.row16 ? 1u : 0u);
       break;
     case K_PART: {
       uint16_t* stg = (uint16_t*)(base + L.off_stage);
@@ -269,11 +295,13 @@ dialsort_status launch_scan(const uint32_t* rows, uint32_t nrows, uint64_t row_s
   FillRun* runs = (FillRun*)(base + L.off_runs);
   const uint32_t rcap = (uint32_t)std::min<uint64_t>(L.run_cap, 0xFFFFFFF0ull);
   const dim3 grid((uint32_t)L.scan_tiles);
-  // rows are the ingestion's partial rows carrying status words
+  // rows are the ingestion's partial rows carrying status words (and, with
+  // row16, counts of 16 bits)
   const uint32_t rstat = fold_init(L) && nrows == L.G && row_stride == L.row_stride ? 1u : 0u;
+  const uint32_t r16 = rstat && L.row16 ? 1u : 0u;
 #define DS_SCAN(VPT, FULL, DIRECT)                                                                                  \
   DS_LAUNCH((k_scan<SCAN_NT, VPT, FULL, DIRECT>), grid, dim3(SCAN_NT), s, rows, nrows, row_stride, H_out, U, ctl, \
-            tiles, items, icap, L.limit, FILL_CL2, report_overflow, runs, rcap, out, fc, rstat)
+            tiles, items, icap, L.limit, FILL_CL2, report_overflow, runs, rcap, out, fc, rstat, r16)
   if (full && L.direct) {
     if (L.scan_vpt == 1) DS_SCAN(1, true, true); else DS_SCAN(16, true, true);
   } else if (full) {
@@ -337,12 +365,82 @@ dialsort_status check_common(uint64_t U, const void* ws, size_t ws_bytes, size_t
   return DIALSORT_OK;
 }
 
+// A fresh launch epoch for k_sort_lds: a process-wide sequence from a random
+// start, never 0.
+uint64_t next_epoch() {
+  static std::atomic<uint64_t> seq{[] {
+    std::random_device rd;
+    const uint64_t t = (uint64_t)std::chrono::steady_clock::now().time_since_epoch().count();
+    return (((uint64_t)rd() << 32) | rd()) ^ (t * 0x9E3779B97F4A7C15ull);
+  }()};
+  uint64_t e;
+  do { e = seq.fetch_add(1, std::memory_order_relaxed); } while (e == 0);
+  return e;
+}
+
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
+}
+
+// Compute units of the current device (cached per device ordinal; 0 if unknown).
+uint32_t device_cus() {
+  static std::atomic<uint32_t> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  uint32_t v = cache[dev].load(std::memory_order_relaxed);
+  if (v == 0) {
+    int c = 0;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0) return 0;
+    v = (uint32_t)c;
+    cache[dev].store(v, std::memory_order_relaxed);
+  }
+  return v;
+}
+
+// The one-launch sort: a counting block per slab and a scan block per slice of
+// bins, all resident at once, outside graph capture.
+bool use_fused(const Layout& L, hipStream_t s) {
+  return L.fused && std::max(L.G, L.NS) <= device_cus() && !capturing(s);
+}
+
+dialsort_status launch_sort_fused(const uint32_t* keys, uint64_t n, uint64_t U, uint32_t* H, uint32_t* out,
+                                  char* base, const Layout& L, const FillCfg& fc, hipStream_t s) {
+  const bool ka = aligned16(keys);
+  uint32_t* rows = (uint32_t*)(base + L.off_rows);
+  uint32_t* pre = (uint32_t*)(base + L.off_pre);
+  uint64_t* flags = (uint64_t*)(base + L.off_flags);
+  const uint64_t epoch = next_epoch();
+  const dim3 grid(std::max(L.G, L.NS));
+#define DS_FUSED(CAP, PACKED, KA)                                                                              \
+  DS_LAUNCH((k_sort_lds<FUSED_NT, CAP, PACKED, 8, KA, 4>), grid, dim3(FUSED_NT), s, keys, n, L.per,            \
+            (uint32_t)(U - 1), (uint32_t)U, L.G, L.NS, rows, L.row_stride, pre, (Ctl*)base, flags, epoch, H, out, \
+            fc)
+  switch (L.kind) {
+    case K_LDS32S: if (ka) DS_FUSED(4096, false, true); else DS_FUSED(4096, false, false); break;
+    case K_LDS32: if (ka) DS_FUSED(32768, false, true); else DS_FUSED(32768, false, false); break;
+    case K_LDS16: if (ka) DS_FUSED(32768, true, true); else DS_FUSED(32768, true, false); break;
+    default: return DIALSORT_EINVAL;
+  }
+#undef DS_FUSED
+  return DIALSORT_OK;
+}
+
 // histogram or sort, after argument checks
 dialsort_status run_sort(const uint32_t* keys, uint64_t n, uint64_t U, uint32_t lo, uint32_t* H, uint32_t* out, void* ws,
                          int mode, hipStream_t s, const uint32_t* lut = nullptr) {
   const Layout L = plan(n, U, mode);
   char* base = ws_base(ws);
   const bool zeroH = L.kind == K_EMPTY || L.kind == K_GLOBAL;
+  if (use_fused(L, s)) {
+    FillCfg fc;
+    fc.lo = lo;
+    fc.lut = lut;
+    fc.limit = n;
+    fc.oal = aligned16(out);
+    fc.nts = fc.oal && n * 4 >= FILL_NTS_BYTES;
+    return launch_sort_fused(keys, n, U, H, out, base, L, fc, s);
+  }
   if (!fold_init(L)) DS_TRY(launch_init(base, L, H, zeroH ? U : 0, s));
   DS_TRY(launch_ingest(keys, n, U, lo, H, base, L, s));
   const uint32_t* rows = L.rows_in_ws ? (const uint32_t*)(base + L.off_rows) : H;

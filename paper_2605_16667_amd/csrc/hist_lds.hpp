@@ -93,22 +93,30 @@ __device__ __noinline__ void lds16_crossing(uint32_t* words, uint32_t word, uint
 // the packed layout.
 template <int CAP, bool PACKED>
 struct HistSmem {
-  uint32_t s[CAP];
+  __align__(16) uint32_t s[CAP];
   uint32_t evflag[PACKED ? 65536 / 32 : 1];
   uint32_t ev[PACKED ? LDS16_EVCAP : 1];
   uint32_t nev;
 };
 
+constexpr int SLICE_LOG2 = 8;  // slices of 256 bins (the one-launch sort's scan)
+constexpr uint32_t SLICE_BINS = 1u << SLICE_LOG2;
+
 // Count keys [beg, end) into S (NT threads) and write the U exact counts to row.
 // The word of bin x is x (uint32 counters) or x >> 1 (packed).  A key > umax
-// sets ST_RANGE in *status.
+// sets ST_RANGE in *status.  row16 (a slab of fewer than 2^16 keys, row
+// 16-byte aligned): the row holds 16-bit counts, bin 2w in the low and bin
+// 2w + 1 in the high half of word w; with it, scnt (LDS, zeroed, one word per
+// slice of 2^SLICE_LOG2 bins) receives the slab's keys per slice.
 template <int NT, bool PACKED, int AGG, bool ALIGNED, int UNR, typename SM>
 __device__ __forceinline__ void hist_slab(SM& S, const uint32_t* __restrict__ keys, uint64_t beg, uint64_t end,
                                           uint32_t umax, uint32_t U, uint32_t* __restrict__ row,
-                                          uint32_t* status, uint32_t lo = 0) {
+                                          uint32_t* status, uint32_t lo = 0, bool row16 = false,
+                                          uint32_t* scnt = nullptr) {
   const uint32_t nwords = PACKED ? (U + 1) / 2 : U;
   const uint32_t tid = threadIdx.x;
-  for (uint32_t i = tid; i < nwords; i += NT) S.s[i] = 0;
+  for (uint32_t i = tid; i < nwords / 4; i += NT) reinterpret_cast<uint4*>(S.s)[i] = make_uint4(0, 0, 0, 0);
+  for (uint32_t i = (nwords & ~3u) + tid; i < nwords; i += NT) S.s[i] = 0;
   if constexpr (PACKED) {
     for (uint32_t i = tid; i < 65536 / 32; i += NT) S.evflag[i] = 0;
     if (tid == 0) S.nev = 0;
@@ -294,6 +302,43 @@ __device__ __forceinline__ void hist_slab(SM& S, const uint32_t* __restrict__ ke
   if constexpr (AGG >= 6) flush();
   if (__syncthreads_or(bad) && tid == 0) atomicOr(status, ST_RANGE);
 
+  if (row16) {
+    // no count reaches 2^16, so no packed field wrapped and the packed words
+    // are the row as they stand; uint32 counters are paired
+    if constexpr (PACKED) {
+      if (tid == 0 && S.nev) atomicOr(status, ST_INT_EVLOG);  // cannot happen below 2^16 keys
+    }
+    auto word = [&](uint32_t w) -> uint32_t {
+      if constexpr (PACKED) return S.s[w];
+      else return S.s[2 * w] | ((2 * w + 1 < U ? S.s[2 * w + 1] : 0u) << 16);
+    };
+    auto fsum = [](uint32_t x) { return (x & 0xFFFFu) + (x >> 16); };
+    const uint32_t nw = (U + 1) / 2, nq = nw / 4;
+    uint4* row4 = reinterpret_cast<uint4*>(row);
+    // quad q holds bins 8q .. 8q + 7, so the 32 quads of a half-wave (one
+    // iteration) are one slice: its sum goes to scnt with one add
+    for (uint32_t q0 = 0; q0 < nq; q0 += NT) {  // uniform trip count: every lane takes part in the sums
+      const uint32_t q = q0 + tid;
+      uint32_t c = 0;
+      if (q < nq) {
+        uint4 x;
+        if constexpr (PACKED) x = *reinterpret_cast<const uint4*>(&S.s[4 * q]);
+        else x = make_uint4(word(4 * q), word(4 * q + 1), word(4 * q + 2), word(4 * q + 3));
+        row4[q] = x;
+        c = fsum(x.x) + fsum(x.y) + fsum(x.z) + fsum(x.w);
+      }
+      if (scnt) {
+        c = half_wave_sum(c);
+        if ((lane_id() & 31u) == 31u && c) atomicAdd(&scnt[q >> (SLICE_LOG2 - 3)], c);
+      }
+    }
+    for (uint32_t w = 4 * nq + tid; w < nw; w += NT) {
+      const uint32_t x = word(w);
+      row[w] = x;
+      if (scnt && x) atomicAdd(&scnt[(2 * w) >> SLICE_LOG2], fsum(x));
+    }
+    return;
+  }
   if constexpr (!PACKED) {
     for (uint32_t i = tid; i < U; i += NT) row[i] = S.s[i];
   } else {
@@ -333,12 +378,12 @@ __device__ __forceinline__ void hist_slab(SM& S, const uint32_t* __restrict__ ke
 // (clear_tiles) -- and each block reports a key past U in its own row, word U
 // (zeroed by the block first), which the scan folds into the status.  No block
 // touches the control block's status then, so clearing it cannot race with a
-// report.
+// report.  row16: per < 2^16 and the rows are 16-byte aligned (16-bit rows).
 template <int NT, int CAP, bool PACKED, int AGG, bool ALIGNED, int UNR>
 __global__ __launch_bounds__(NT) void k_hist_lds(const uint32_t* __restrict__ keys, uint64_t n, uint64_t per,
                                                  uint32_t umax, uint32_t U, uint32_t* __restrict__ rows,
                                                  uint64_t row_stride, Ctl* ctl, uint32_t lo, uint32_t init,
-                                                 uint64_t* __restrict__ clear_tiles, uint64_t nclear) {
+                                                 uint64_t* __restrict__ clear_tiles, uint64_t nclear, uint32_t row16) {
   __shared__ HistSmem<CAP, PACKED> S;
   const uint64_t beg = (uint64_t)blockIdx.x * per;
   const uint64_t end = beg + per < n ? beg + per : n;
@@ -351,7 +396,7 @@ __global__ __launch_bounds__(NT) void k_hist_lds(const uint32_t* __restrict__ ke
     status = row + U;
     if (threadIdx.x == 0) *status = 0;  // the same thread reports into it, after barriers
   }
-  hist_slab<NT, PACKED, AGG, ALIGNED, UNR>(S, keys, beg, end, umax, U, row, status, lo);
+  hist_slab<NT, PACKED, AGG, ALIGNED, UNR>(S, keys, beg, end, umax, U, row, status, lo, row16 != 0);
 }
 
 // Direct global atomics into a zeroed H, after the same wave merge.  Used when

@@ -80,27 +80,34 @@ __device__ __forceinline__ uint64_t wave_sum_sat(uint64_t x) {
 }
 
 // Decoupled look-back for tile t (called by wave 0 of the block).  Returns the
-// exclusive prefix of tile t in lane 0's view (all lanes get it).
+// exclusive prefix of tile t (all lanes get it).  A round reads LB_GROUPS x 64
+// predecessors at once (lane l of group i reads tile j - 64 i - l), so a tile
+// far from the last published prefix reaches it in few round trips.  Groups
+// are taken nearest first; a group with an unpublished tile before its first
+// prefix is read again, from that group on, in the next round.
+constexpr int LB_GROUPS = 4;
 __device__ __forceinline__ uint64_t lookback(uint64_t* state, uint64_t t) {
   const int lane = lane_id();
   uint64_t prefix = 0;
-  int64_t j = (int64_t)t - 1;
+  int64_t j = (int64_t)t - 1;  // the nearest predecessor not yet added
   for (;;) {
-    const int64_t idx = j - lane;
-    uint64_t s;
-    for (;;) {
-      s = idx >= 0 ? ld_acquire_u64(&state[idx]) : LB_FLAG_P;
-      if (!__any((s >> 62) == 0)) break;
-      __builtin_amdgcn_s_sleep(1);
+    uint64_t s[LB_GROUPS];
+#pragma unroll
+    for (int i = 0; i < LB_GROUPS; ++i) {
+      const int64_t idx = j - i * WAVE - lane;
+      s[i] = idx >= 0 ? ld_acquire_u64(&state[idx]) : LB_FLAG_P;
     }
-    const uint64_t pm = __ballot((s >> 62) == 2);
-    if (pm) {
-      const int p = __ffsll((unsigned long long)pm) - 1;
-      prefix = sat_add(prefix, wave_sum_sat(lane <= p ? (s & LB_VAL) : 0));
-      return prefix;
+    bool pending = false;
+#pragma unroll
+    for (int i = 0; i < LB_GROUPS; ++i) {
+      const uint64_t pm = __ballot((s[i] >> 62) == 2);
+      const int p = pm ? __ffsll((unsigned long long)pm) - 1 : WAVE - 1;  // the lanes this group needs: 0 .. p
+      if (__ballot((s[i] >> 62) == 0) & ((2ull << p) - 1)) { pending = true; break; }
+      prefix = sat_add(prefix, wave_sum_sat(lane <= p ? (s[i] & LB_VAL) : 0));
+      if (pm) return prefix;
+      j -= WAVE;
     }
-    prefix = sat_add(prefix, wave_sum_sat(s & LB_VAL));
-    j -= WAVE;
+    if (pending) __builtin_amdgcn_s_sleep(1);
   }
 }
 
@@ -111,13 +118,14 @@ __device__ __forceinline__ uint64_t lookback(uint64_t* state, uint64_t t) {
 // into out once its prefix is known (wave_fill; the counts must come from keys,
 // so that any sum of them fits 32 bits).
 // limit: number of output positions that may be written (n, or out_cap).
+// row16: the rows hold 16-bit counts (bin k is halfword k of its row).
 template <int NT, int VPT, bool FULL, bool DIRECT = false>
 __global__ __launch_bounds__(NT) void k_scan(const uint32_t* __restrict__ rows, uint32_t nrows, uint64_t row_stride,
                                              uint32_t* __restrict__ H_out, uint64_t U, Ctl* ctl,
                                              uint64_t* tile_state, FillItem* __restrict__ items,
                                              uint32_t item_cap, uint64_t limit, int CL2, int report_overflow,
                                              FillRun* __restrict__ runs, uint32_t run_cap, uint32_t* __restrict__ out,
-                                             FillCfg fc, uint32_t row_status) {
+                                             FillCfg fc, uint32_t row_status, uint32_t row16) {
   constexpr int TB = NT * VPT;
   constexpr int PADW = TB + TB / 32;
   __shared__ uint32_t tr[VPT > 1 ? PADW : 1];
@@ -150,13 +158,24 @@ __global__ __launch_bounds__(NT) void k_scan(const uint32_t* __restrict__ rows, 
     const uint64_t k = base + (uint64_t)j * NT + tid;
     uint32_t a = 0;
     if (k < U) {
+      const uint16_t* rows16 = reinterpret_cast<const uint16_t*>(rows);
       if constexpr (VPT == 1) {
-        // one bin per thread: 16 rows' loads in flight at once
+        // one bin per thread: 32 rows' loads in flight at once
+        if (row16) {
+#pragma unroll 32
+          for (uint32_t r = 0; r < nrows; ++r) a += rows16[(uint64_t)r * row_stride * 2 + k];
+        } else {
 #pragma unroll 16
-        for (uint32_t r = 0; r < nrows; ++r) a += rows[(uint64_t)r * row_stride + k];
+          for (uint32_t r = 0; r < nrows; ++r) a += rows[(uint64_t)r * row_stride + k];
+        }
       } else {
+        if (row16) {
 #pragma unroll 8
-        for (uint32_t r = 0; r < nrows; ++r) a += rows[(uint64_t)r * row_stride + k];
+          for (uint32_t r = 0; r < nrows; ++r) a += rows16[(uint64_t)r * row_stride * 2 + k];
+        } else {
+#pragma unroll 8
+          for (uint32_t r = 0; r < nrows; ++r) a += rows[(uint64_t)r * row_stride + k];
+        }
       }
       if (H_out) H_out[k] = a;
     }

@@ -105,6 +105,23 @@ def test_all_keys_equal(ds, U, which):
     assert_parity(ds, keys, U, label=f"all-equal {which}")
 
 
+@pytest.mark.parametrize("U,n", [(7, 4194048), (4097, 4194048), (30000, 16776192), (65535, 8388096),
+                                 (65536, 8388096)])
+@pytest.mark.parametrize("which", ["one", "pair"])
+def test_sixteen_bit_rows_at_the_limit(ds, U, n, which):
+    # slabs of 65532 keys (n = 65532 x workgroups for each ingestion kind): a
+    # slab of fewer than 2^16 keys is written as a row of 16-bit counts, so
+    # one bin holding the whole slab, or two bins of one packed word sharing
+    # it, are the largest counts such a row ever holds
+    if which == "one":
+        keys = np.full(n, U - 1, dtype=np.uint32)
+    else:
+        b0 = (U - 2) & ~1  # bins b0 and b0 + 1 share a packed word
+        keys = np.where(np.arange(n) % 2 == 0, b0, b0 + 1).astype(np.uint32)
+    assert_parity(ds, keys, U, label=f"16-bit rows {which}")
+    assert_parity(ds, keys, U, mode="hist", label=f"16-bit rows {which}")
+
+
 @pytest.mark.parametrize("U", [4096, 40001, 65536, 1 << 24])
 def test_hot_zipf(ds, U):
     keys = w.as_u32(w.hot_zipf(1_000_003, U, SEED))
@@ -225,6 +242,71 @@ def test_universe_2_pow_32(ds):
     assert int(torch.count_nonzero(H)) == uniq.size
     del H
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("U", [4096, 30000, 65536])
+def test_one_launch_sort_workspace_reuse(ds, U):
+    """Small LDS sorts run as one launch whose scan blocks wait for flags that
+    carry the launch's epoch.  One workspace serves sorts of different sizes in
+    turn (so flags of earlier launches, with other epochs and other row counts,
+    are in it), and every result is exact."""
+    dev = torch.device("cuda:0")
+    sizes = [1 << 20, 65539, 1 << 18, 1 << 20, 300_007, 1 << 16]
+    ws = ds.workspace(max(ds.dialsort_workspace_bytes(n, U, ds.DIALSORT_MODE_SORT) for n in sizes), dev)
+    for i, n in enumerate(sizes):
+        kh = w.as_u32(w.uniform(n, U, SEED + 11 * i + U))
+        keys = torch.from_numpy(kh.view(np.int32)).to(dev)
+        H = torch.full((U,), -1, dtype=torch.int32, device=dev)
+        out = torch.full((n,), -7, dtype=torch.int32, device=dev)
+        say(f"one-launch reuse U={U} n={n}")
+        ds.check(ds.dialsort_sort(keys, U, H, out, ws))
+        assert ds.dialsort_status_sync(ws) == ds.DIALSORT_OK
+        _, H_ref, out_ref = oracle.sort(kh, U)
+        assert np.array_equal(w.as_u32(H), H_ref) and np.array_equal(w.as_u32(out), out_ref)
+
+
+@pytest.mark.parametrize("U,n", [(4096, 200_000), (40001, 1 << 20), (65536, 1 << 20), (65536, (1 << 22) - 4)])
+@pytest.mark.parametrize("which", ["one", "two_slices"])
+def test_one_launch_sort_skew(ds, U, n, which):
+    """The one-launch sort on skewed keys: every key in one bin, or split
+    between the last bin of one slice of 256 bins and the first of the next."""
+    if which == "one":
+        keys = np.full(n, U // 3, dtype=np.uint32)
+    else:
+        keys = np.where(np.arange(n) % 3 == 0, 255, 256).astype(np.uint32)
+    assert_parity(ds, keys, U, label=f"one-launch skew {which}")
+
+
+@pytest.mark.parametrize("U", [4096, 65536])
+def test_single_sort_graph_capture_replay(ds, U):
+    """A sort captured in a HIP graph (the launch sequence that does not rely
+    on a per-launch epoch) replays exactly, several times, on new keys."""
+    dev = torch.device("cuda:0")
+    n = 1 << 20
+    keys = torch.empty(n, dtype=torch.int32, device=dev)
+    H = torch.empty(U, dtype=torch.int32, device=dev)
+    out = torch.empty(n, dtype=torch.int32, device=dev)
+    ws = ds.workspace(ds.dialsort_workspace_bytes(n, U, ds.DIALSORT_MODE_SORT), dev)
+    say(f"graph capture of one sort U={U}")
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            ds.check(ds.dialsort_sort(keys, U, H, out, ws, stream=side))
+    torch.cuda.current_stream().wait_stream(side)
+    for r in range(3):
+        kh = w.as_u32(w.uniform(n, U, SEED + 100 * r + U))
+        keys.copy_(torch.from_numpy(kh.view(np.int32)))
+        H.fill_(-1)
+        out.fill_(-7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert ds.dialsort_status_sync(ws) == ds.DIALSORT_OK
+        _, H_ref, out_ref = oracle.sort(kh, U)
+        assert np.array_equal(w.as_u32(H), H_ref), f"replay {r}: H"
+        assert np.array_equal(w.as_u32(out), out_ref), f"replay {r}: out"
 
 
 def test_batched_equals_single(ds):
