@@ -178,16 +178,26 @@ def profiled_traffic(kernel: str):
 
 
 def time_calls(ds, hip, call, K, W, n, U, nev=12):
-    """W untimed calls, then K timed calls bracketed by one event per step
-    boundary (the step times), then K more calls with an event after every
-    launch (the per-kernel times; those events add a little to each step, so
-    the step figures come from the first pass).  Returns a dict."""
+    """W untimed calls, then K timed calls between two events (the step time:
+    the whole K steps over K), then K calls with an event at every step
+    boundary (the spread of single steps), then K more calls with an event
+    after every launch (the per-kernel times).  Events between steps add a
+    little to each step, so the step time comes from the first pass.  Returns
+    a dict."""
     import torch
 
     for _ in range(W):
         call()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for k in range(K):
+        call()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = t0.elapsed_time(t1)
     marks = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
     torch.cuda.synchronize()
     marks[0].record(stream)
@@ -196,7 +206,6 @@ def time_calls(ds, hip, call, K, W, n, U, nev=12):
         marks[k + 1].record(stream)
     torch.cuda.synchronize()
     steps = [marks[k].elapsed_time(marks[k + 1]) for k in range(K)]
-    total_ms = marks[0].elapsed_time(marks[K])
     evsets = [hip.make(nev) for _ in range(K)]
     count = ctypes.c_uint32(0)
     for k in range(K):
@@ -220,6 +229,7 @@ def time_calls(ds, hip, call, K, W, n, U, nev=12):
         "best_ms": min(steps),
         "median_ms": statistics.median(steps),
         "cv": (statistics.pstdev(steps) / statistics.fmean(steps)) if len(steps) > 1 else 0.0,
+        "ms_per_step_with_step_events": statistics.fmean(steps),
         "ms_per_step_with_launch_events": statistics.fmean(evented),
         "kernels": per_kernel,
         "names": names,
