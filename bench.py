@@ -921,8 +921,8 @@ def cpu_parallel_baseline(kh, U, warmup=3, runs=7):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workloads", default="large,hist,query,plain,skewed,transforms,windows,radix,batch,serve")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-loads", default="0.5,0.7,0.9,1.2",
