@@ -277,6 +277,42 @@ def test_one_launch_sort_skew(ds, U, n, which):
     assert_parity(ds, keys, U, label=f"one-launch skew {which}")
 
 
+@pytest.mark.parametrize("U,n,one", [(65536, 1 << 20, True), (2001, 50_000, True), (65536, (1 << 22) + 5, False),
+                                     (4096, 1 << 20, False)])
+def test_small_sort_launches(ds, U, n, one):
+    """Which launch sequence a sort takes: one k_sort_lds for a small sort
+    with 16-bit rows and few keys per slice, the counting launch and the scan
+    otherwise; the result is exact either way."""
+    import ctypes
+
+    import bench
+
+    hip = bench.HipEvents()
+    ev = hip.make(8)
+    count = ctypes.c_uint32(0)
+    kh = w.as_u32(w.uniform(n, U, SEED + n))
+    keys = torch.from_numpy(kh.view(np.int32)).to("cuda:0")
+    H = torch.empty(U, dtype=torch.int32, device="cuda:0")
+    out = torch.empty(n, dtype=torch.int32, device="cuda:0")
+    ws = ds.workspace(ds.dialsort_workspace_bytes(n, U, ds.DIALSORT_MODE_SORT), keys.device)
+    say(f"launch sequence U={U} n={n}")
+    ds.check(ds.dialsort_set_launch_events(ev, 8, count))
+    try:
+        ds.check(ds.dialsort_sort(keys, U, H, out, ws))
+    finally:
+        ds.dialsort_set_launch_events(None, 0, None)
+    torch.cuda.synchronize()
+    names = [ds.dialsort_launch_name(i) for i in range(count.value)]
+    hip.free(ev)
+    if one:
+        assert len(names) == 1 and "k_sort_lds" in names[0], names
+    else:
+        assert not any("k_sort_lds" in x for x in names) and any("k_scan" in x for x in names), names
+    assert ds.dialsort_status_sync(ws) == ds.DIALSORT_OK
+    _, H_ref, out_ref = oracle.sort(kh, U)
+    assert np.array_equal(w.as_u32(H), H_ref) and np.array_equal(w.as_u32(out), out_ref)
+
+
 @pytest.mark.parametrize("U", [4096, 65536])
 def test_single_sort_graph_capture_replay(ds, U):
     """A sort captured in a HIP graph (the launch sequence that does not rely
