@@ -369,9 +369,15 @@ dialsort_status check_common(uint64_t U, const void* ws, size_t ws_bytes, size_t
 // start, never 0.
 uint64_t next_epoch() {
   static std::atomic<uint64_t> seq{[] {
-    std::random_device rd;
+    uint64_t r = 0;
+    try {
+      std::random_device rd;
+      r = ((uint64_t)rd() << 32) | rd();
+    } catch (...) {
+      r = (uint64_t)(uintptr_t)&r;  // no entropy source: the clock below still varies
+    }
     const uint64_t t = (uint64_t)std::chrono::steady_clock::now().time_since_epoch().count();
-    return (((uint64_t)rd() << 32) | rd()) ^ (t * 0x9E3779B97F4A7C15ull);
+    return r ^ (t * 0x9E3779B97F4A7C15ull);
   }()};
   uint64_t e;
   do { e = seq.fetch_add(1, std::memory_order_relaxed); } while (e == 0);
