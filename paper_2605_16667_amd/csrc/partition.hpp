@@ -306,7 +306,7 @@ template <int NT, int LOG2W>
 struct BinSmem {
   static constexpr bool PACKED = LOG2W == 16;
   static constexpr uint32_t WORDS = PACKED ? (1u << 15) : (1u << LOG2W);
-  uint32_t s[WORDS];
+  __align__(16) uint32_t s[WORDS];
   uint32_t evflag[PACKED ? 65536 / 32 : 1];
   uint32_t ev[PACKED ? LDS16_EVCAP : 1];
   uint32_t nev;
@@ -900,7 +900,8 @@ __device__ __forceinline__ void bucket_body(BinSmem<NT, LOG2W>& S, const uint16_
   const uint32_t klast = (uint32_t)(hb + cnt - 1);
   const bool split = bp.P > 1;
 
-  for (uint32_t i = tid; i < SM::WORDS; i += NT) S.s[i] = 0;
+  static_assert(SM::WORDS % 4 == 0, "16-byte clears");
+  for (uint32_t i = tid; i < SM::WORDS / 4; i += NT) reinterpret_cast<uint4*>(S.s)[i] = make_uint4(0, 0, 0, 0);
   if constexpr (SM::PACKED) {
     for (uint32_t i = tid; i < 65536 / 32; i += NT) S.evflag[i] = 0;  // hot-bin flags
     if (tid == 0) S.nev = 0;                                          // hot table entries
@@ -946,7 +947,7 @@ __device__ __forceinline__ void bucket_body(BinSmem<NT, LOG2W>& S, const uint16_
     if (!clean) {
       // a second key wrapped a field: gather again with two candidates per wave
       __syncthreads();
-      for (uint32_t i = tid; i < SM::WORDS; i += NT) S.s[i] = 0;
+      for (uint32_t i = tid; i < SM::WORDS / 4; i += NT) reinterpret_cast<uint4*>(S.s)[i] = make_uint4(0, 0, 0, 0);
       if (tid == 0) S.nev = 0;
       __syncthreads();
       bucket_gather<NT, LOG2W, AGG, GM_PACKED_HOT2, TK>(S, staging, seg, bstride, bp.t0, bp.t1, b, 0);
