@@ -259,8 +259,8 @@ dialsort_status dialsort_sort_each(const dialsort_desc *descs, uint32_t count, v
  * each candidate runs the whole batch three times, so every H and output is
  * written -- stores the fastest in *best and remembers it for batches of the
  * same sizes on this device (the library's only tuning state; besides it the
- * library keeps each device's CU count and the one-launch sort's epoch
- * sequence, see dialsort_sort).  Synchronises
+ * library keeps the one-launch sort's epoch sequence, see dialsort_sort).
+ * Synchronises
  * `stream`.  ws as for dialsort_batched_workspace_bytes(). */
 dialsort_status dialsort_batch_autotune(const dialsort_desc *descs, uint32_t count, void *ws,
                                         size_t ws_bytes, hipStream_t stream,

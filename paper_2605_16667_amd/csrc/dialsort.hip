@@ -141,8 +141,7 @@ Layout plan(uint64_t n, uint64_t U, int mode) {
   L.direct = mode == DIALSORT_MODE_SORT && (L.kind == K_LDS32S || L.kind == K_LDS32 || L.kind == K_LDS16) &&
              n <= DIRECT_NMAX && n <= DIRECT_PER_TILE * L.scan_tiles;
   // one launch for the whole sort (k_sort_lds): 16-bit rows, and a slice of
-  // bins holds few output positions on average (whether the grid fits the
-  // device is checked at launch)
+  // bins holds few output positions on average
   if (mode == DIALSORT_MODE_SORT && L.row16) {
     const uint64_t ns = cdiv(U, (uint64_t)SLICE);
     L.fused = ns <= FUSED_SLICES_MAX && n <= DIRECT_NMAX && n <= FUSED_PER_SLICE * ns;
@@ -389,26 +388,8 @@ bool capturing(hipStream_t s) {
   return hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
 }
 
-// Compute units of the current device (cached per device ordinal; 0 if unknown).
-uint32_t device_cus() {
-  static std::atomic<uint32_t> cache[64];
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
-  uint32_t v = cache[dev].load(std::memory_order_relaxed);
-  if (v == 0) {
-    int c = 0;
-    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0) return 0;
-    v = (uint32_t)c;
-    cache[dev].store(v, std::memory_order_relaxed);
-  }
-  return v;
-}
-
-// The one-launch sort: a counting block per slab and a scan block per slice of
-// bins, all resident at once, outside graph capture.
-bool use_fused(const Layout& L, hipStream_t s) {
-  return L.fused && std::max(L.G, L.NS) <= device_cus() && !capturing(s);
-}
+// The one-launch sort, outside graph capture.
+bool use_fused(const Layout& L, hipStream_t s) { return L.fused && !capturing(s); }
 
 dialsort_status launch_sort_fused(const uint32_t* keys, uint64_t n, uint64_t U, uint32_t* H, uint32_t* out,
                                   char* base, const Layout& L, const FillCfg& fc, hipStream_t s) {
@@ -417,7 +398,7 @@ dialsort_status launch_sort_fused(const uint32_t* keys, uint64_t n, uint64_t U, 
   uint32_t* pre = (uint32_t*)(base + L.off_pre);
   uint64_t* flags = (uint64_t*)(base + L.off_flags);
   const uint64_t epoch = next_epoch();
-  const dim3 grid(std::max(L.G, L.NS));
+  const dim3 grid(L.G + L.NS);
 #define DS_FUSED(CAP, PACKED, KA)                                                                              \
   DS_LAUNCH((k_sort_lds<FUSED_NT, CAP, PACKED, 8, KA, 4>), grid, dim3(FUSED_NT), s, keys, n, L.per,            \
             (uint32_t)(U - 1), (uint32_t)U, L.G, L.NS, rows, L.row_stride, pre, (Ctl*)base, flags, epoch, H, out, \

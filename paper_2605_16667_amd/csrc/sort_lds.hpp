@@ -8,10 +8,10 @@
 // keys).  While writing it, a block also sums its counts per slice of 256 bins
 // and stores the exclusive prefix of those sums over the slices (plus the
 // slab's total) as pre[g]: the start of slice s in the output is then
-// sum_g pre[g][s], with no scan across slices.  Blocks [0, NS) each own slice
-// s = block: once every counting block has published, a block sums the G rows
-// over its 256 bins, writes that part of H, and writes the slice's runs into
-// the output, 16 bins per wave.
+// sum_g pre[g][s], with no scan across slices.  Blocks [G, G + NS) each own
+// slice s = block - G: once every counting block has published, a block sums
+// the G rows over its 256 bins, writes that part of H, and writes the slice's
+// runs into the output, 16 bins per wave.
 //
 // The wait needs no counter that something must clear first: counting block g
 // stores the launch's epoch into flag g after its row, and a block goes on once
@@ -21,11 +21,12 @@
 // replayed graph would repeat the epoch, so the host uses this form only on a
 // stream that is not capturing.
 //
-// Progress: every counting block publishes before it waits, and the host uses
-// this form only when the whole grid fits the device at one block per CU, so
-// that no waiting block can keep a counting block from starting.  The wait is
-// bounded all the same: after FUSED_WAIT_TICKS of the 100 MHz clock a block
-// stops waiting and reports ST_INT_WAIT.
+// Progress: counting blocks never wait, and every block that waits has a
+// larger index than all of them: blocks are dispatched in index order, so
+// whenever a slice block is resident every counting block has been dispatched
+// and will finish, whatever else shares the device (other launches of this
+// kernel included).  The wait is bounded all the same: after FUSED_WAIT_TICKS
+// of the 100 MHz clock a block stops waiting and reports ST_INT_WAIT.
 //
 // Publication across XCDs: a counting block waits until its stores are
 // acknowledged, passes a barrier, and thread 0 stores the flag with release
@@ -95,8 +96,9 @@ __global__ __launch_bounds__(NT) void k_sort_lds(const uint32_t* __restrict__ ke
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (tid == 0) __hip_atomic_store(&flags[b], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    return;
   }
-  if (b >= NS) return;
+  const uint32_t sl = b - G;  // this block's slice
 
   if (tid < WAVE) {
     const uint64_t t0 = wall_clock64();
@@ -115,7 +117,7 @@ __global__ __launch_bounds__(NT) void k_sort_lds(const uint32_t* __restrict__ ke
   __syncthreads();
 
   // each row's status word (a key past U in its slab) into the control block
-  if (b == 0) {
+  if (sl == 0) {
     uint32_t bits = 0;
     for (uint32_t g = tid; g < G; g += NT) bits |= rows[(uint64_t)g * row_stride + U];
     if (bits) atomicOr(&ctl->status, bits);
@@ -124,7 +126,7 @@ __global__ __launch_bounds__(NT) void k_sort_lds(const uint32_t* __restrict__ ke
   // 1. the slice's counts: thread t sums word t mod 128 of the slice (bins
   //    2w, 2w + 1) over rows t / 128, + RG, ...; the slice's start and (last
   //    slice) the total from pre
-  const uint64_t sbase = (uint64_t)b << SLICE_LOG2;
+  const uint64_t sbase = (uint64_t)sl << SLICE_LOG2;
   {
     constexpr uint32_t RG = SliceSmem<NT>::RG;
     const uint32_t w = tid % (SLICE / 2), h = tid / (SLICE / 2);
@@ -141,8 +143,8 @@ __global__ __launch_bounds__(NT) void k_sort_lds(const uint32_t* __restrict__ ke
     S.s.part[h][w] = make_uint2(lo16, hi16);
     uint32_t pg = 0, tg = 0;
     if (tid < G) {
-      pg = pre[(uint64_t)tid * P1 + b];
-      if (b == NS - 1) tg = pre[(uint64_t)tid * P1 + NS];
+      pg = pre[(uint64_t)tid * P1 + sl];
+      if (sl == NS - 1) tg = pre[(uint64_t)tid * P1 + NS];
     }
     pg = wave_sum(pg);
     tg = wave_sum(tg);
@@ -175,7 +177,7 @@ __global__ __launch_bounds__(NT) void k_sort_lds(const uint32_t* __restrict__ ke
     uint32_t ssum = 0;
     for (uint32_t i = 0; i < SLICE / WAVE; ++i) ssum += S.s.wsum[i];
     S.s.excl[SLICE] = ssum;
-    if (b == NS - 1) {
+    if (sl == NS - 1) {
       uint64_t total = 0;
       for (uint32_t i = 0; i < NT / WAVE; ++i) total += S.s.tot[i];
       ctl->total = total;
