@@ -277,8 +277,8 @@ def test_one_launch_sort_skew(ds, U, n, which):
     assert_parity(ds, keys, U, label=f"one-launch skew {which}")
 
 
-@pytest.mark.parametrize("U,n,one", [(65536, 1 << 20, True), (2001, 50_000, True), (65536, (1 << 22) + 5, False),
-                                     (4096, 1 << 20, False)])
+@pytest.mark.parametrize("U,n,one", [(65536, 1 << 20, True), (2001, 50_000, True), (6, 16384, True),
+                                     (65536, (1 << 22) + 5, False), (4096, 1 << 20, False)])
 def test_small_sort_launches(ds, U, n, one):
     """Which launch sequence a sort takes: one k_sort_lds for a small sort
     with 16-bit rows and few keys per slice, the counting launch and the scan
@@ -311,6 +311,15 @@ def test_small_sort_launches(ds, U, n, one):
     assert ds.dialsort_status_sync(ws) == ds.DIALSORT_OK
     _, H_ref, out_ref = oracle.sort(kh, U)
     assert np.array_equal(w.as_u32(H), H_ref) and np.array_equal(w.as_u32(out), out_ref)
+
+
+@pytest.mark.parametrize("U", [1, 2, 6, 128, 255, 256, 257, 1000])
+@pytest.mark.parametrize("n", [5003, 16384])
+def test_one_launch_sort_small_universes(ds, U, n):
+    """Universes of at most a few slices of 256 bins, where the one-launch sort
+    has a single slice (or a partial last one) and its rows hold few words."""
+    keys = w.as_u32(w.uniform(n, U, SEED + 7 * n + U))
+    assert_parity(ds, keys, U, label="one-launch small universe")
 
 
 @pytest.mark.parametrize("U", [4096, 65536])
