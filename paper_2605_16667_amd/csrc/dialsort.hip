@@ -48,7 +48,7 @@ constexpr uint64_t PART_NCU = 256;  // compute units of the target (MI355X)
 constexpr uint64_t DIRECT_NMAX = 1ull << 24;     // direct projection from the scan: at most this many keys,
 constexpr uint64_t DIRECT_PER_TILE = 1ull << 14;  // and at most this many per scan tile on average
 constexpr int FUSED_NT = 1024;  // one-launch sort: threads per block
-constexpr uint64_t FUSED_PER_SLICE = 1ull << 14;  // and at most this many keys per slice of bins on average
+constexpr uint64_t FUSED_PER_SLICE = 1ull << 14;  // one-launch sort: at most this many keys per slice of bins on average
 
 enum Kind { K_EMPTY, K_LDS32S, K_LDS32, K_LDS16, K_PART, K_GLOBAL, K_NONE };
 

@@ -160,7 +160,7 @@ __global__ __launch_bounds__(NT) void k_scan(const uint32_t* __restrict__ rows, 
     if (k < U) {
       const uint16_t* rows16 = reinterpret_cast<const uint16_t*>(rows);
       if constexpr (VPT == 1) {
-        // one bin per thread: 32 rows' loads in flight at once
+        // one bin per thread: 32 (16-bit rows) or 16 rows' loads in flight at once
         if (row16) {
 #pragma unroll 32
           for (uint32_t r = 0; r < nrows; ++r) a += rows16[(uint64_t)r * row_stride * 2 + k];

@@ -1,7 +1,7 @@
 // A sort of a small input in one launch: Eq. (1) into LDS-privatized partial
 // rows, then Eq. (2) projected by slices of bins (DialSort Sec. 3.3).  What one
 // launch saves is a second launch, its start-up, and the look-back between
-// scan tiles: at 2^20 keys those are most of the sort.
+// scan tiles: at 2^20 keys, together with 16-bit rows, a third of the sort.
 //
 // Blocks [0, G) count slab g of the keys into LDS exactly as k_hist_lds does
 // and write partial row g as 16-bit counts (a slab holds fewer than 2^16
